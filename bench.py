@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Benchmark of the sine-transform-preconditioned MINRES hot path on one MI355X.
+
+Workload (the 2D Crank-Nicolson configuration): heat equation on the unit square,
+a = 1, N = 127 interior points per axis (m = 16129), n = 256 Crank-Nicolson steps,
+T = 1, f from u = sin(pi x) sin(pi y) e^{-t} plus N(0, 1e-3^2) noise (seed 0),
+P_H preconditioner (3D sine transform + diagonal), plain float64.
+
+One step = assemble f_H on the GPU and run preconditioned MINRES from x0 = 0 to a true
+relative residual of 1e-8.  The reported value is MINRES iterations per second over the
+K timed steps (inputs resident in HBM before the timed region); time-to-1e-8 is reported
+beside it.  The dominant kernel (time-axis sine transform on the FP64 matrix cores) is
+timed live with HIP events on its launch stream and priced against the FP64 matrix peak.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_time_kernel_cn2d_N127_n256.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc", "k_time.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_entry():
+    """HBM bytes per launch of the time kernel from the committed rocprofv3 --pmc summary,
+    or None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(p, iters: int = 10):
+    """The FP64 CPU oracle timed on this host: the first `iters` MINRES iterations of
+    the same workload (single thread: scipy.fft workers=1, scipy.sparse)."""
+    from oracle.system import System
+    s = System(2, p.N, p.n, theta=p.theta)
+    fH = s.rhs(p.f, p.u0)
+    t0 = time.perf_counter()
+    r = s.solve(fH, rtol=1e-300, maxit=iters)
+    dt = time.perf_counter() - t0
+    return {"value": r.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r.iters} MINRES iterations of the N=127, n=256 Crank-Nicolson workload "
+                      f"(P_H, true residual each iteration), {dt:.1f} s on one host core"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solve is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Plan, smr
+
+    dev = torch.device("cuda:0")
+    p = W.crank_nicolson_2d_noisy()          # N = 127, n = 256, theta = 1/2, seed 0
+    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    plan = Plan(2, p.N, p.n, theta=p.theta, device=dev)
+    b = plan.empty()
+
+    def step():
+        plan.build_rhs(f, u0, out=b)
+        x, info = plan.solve(b, rtol=args.rtol)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    smr.profile_enable(True)
+    iters = []
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = step()
+        iters.append(info["iters"])
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    smr.profile_enable(False)
+    n_time, ms_time = smr.profile_read("time")
+    dt = t1 - t0
+    total_iters = sum(iters)
+    avg_launch_s = (ms_time / n_time) * 1e-3 if n_time else float("nan")
+    flops_per_launch = 2.0 * p.n * p.n * p.m      # four folded GEMMs of (n/2)^2 x m
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    traffic = traffic_entry()
+    out = {
+        "metric": "MINRES iters/s to 1e-8 true relative residual (time-to-1e-8 beside it)",
+        "value": total_iters / dt,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cn2d_noisy_N127_n256", "dim": 2, "N": p.N, "n": p.n, "m": p.m,
+                   "theta": p.theta, "precond": "P_H", "pprec": "fp64", "rtol": args.rtol,
+                   "dof": p.n * p.m},
+        "iters_per_solve": iters[-1],
+        "time_to_1e-8_ms": dt / args.steps * 1e3,
+        "relres_true": infos[-1]["relres_true"],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "k_time<128,32,1> (S_n diag(1/sigma) S_n, FP64 MFMA)",
+                     "launches": n_time, "avg_launch_us": avg_launch_s * 1e6,
+                     "flops_per_launch": flops_per_launch},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,184 @@
+/*
+ * smr.h -- C ABI of the MI355X (gfx950) library for sine-transform-preconditioned
+ * MINRES on the time-flipped all-at-once systems of the heat equation
+ * (S. Hon, P. Y. Fung, J. Dong, S. Serra-Capizzano, arXiv 2201.10062).
+ *
+ * Problem (Sec. 1, eqn:heat): u_t = div(a grad u) + f on (0,1)^dim x (0,T], u = 0 on
+ * the boundary, u(.,0) = u0, discretised by finite differences on N interior points
+ * per axis (h = 1/(N+1), m = N^dim unknowns per time level, M = I) and n time steps
+ * (tau = T/n) with
+ *   - the theta-method (eq. theta): T_H has A0 = I + theta tau K on the block
+ *     diagonal and A1 = -I + (1-theta) tau K below it;
+ *   - BDF2 (eqn:matrix_gen with l = 2): A0 = 1.5 I + tau K, A1 = -2 I, A2 = 0.5 I.
+ * K = K(a) is the 3-point (1D) or 5-point (2D) stencil of eqn:matrix_Km_va built from
+ * face values of a.  The library solves Y T u = Y f_H (eqn:main_system, Y the time
+ * flip) by preconditioned MINRES with
+ *   - SMR_P_H: P_H (def:matrix_P) or, for BDF2, Phat (def:matrix_P_gen); for
+ *     variable a the averaged Toeplitz Kbar of Sec. 3.1.1 replaces K inside P only.
+ *     P^{-1} = (S_n (x) U) diag(1/sigma) (S_n (x) U), U the spatial sine transform,
+ *     sigma_{j,k} = |ghat(phi_j)| evaluated at the eigenvalue mu_k of K (or Kbar);
+ *   - SMR_P_THETA_CHEB: P_theta (def:matrix_mod_P) whose per-time-mode SPD solves
+ *     (eta_j I + tau zeta_j K(a)) are replaced by k steps of Chebyshev iteration
+ *     preconditioned by eta_j I + tau zeta_j abar K_lap (the paper leaves the inner
+ *     solver open);
+ *   - SMR_P_NONE: identity.
+ *
+ * Conventions shared by every entry point
+ *   Layout: every vector is float64, C-ordered (time, y, x), x fastest; a solution /
+ *     right-hand side has n*m entries, a source f has (n+1)*m (levels t_0..t_n).
+ *   Pointers: arguments named d_* or documented "device" are device pointers on the
+ *     current HIP device; "host" pointers are ordinary host memory.  The caller owns
+ *     every buffer.  The library never allocates device memory: all scratch lives in
+ *     the caller's workspace (size from smr_workspace_size).
+ *   Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it.  smr_setup and the solves synchronise it before
+ *     returning; the apply/build/grad calls are asynchronous.
+ *   Concurrency: one call in flight per plan (a plan owns its workspace).  Distinct
+ *     plans with distinct workspaces are independent.
+ *   Errors: every call returns an smr_status; no exception crosses the ABI.  On any
+ *     status other than SMR_OK a human-readable reason is available from
+ *     smr_last_error() (thread-local, valid until the next call on the thread).
+ *   Limits: dim in {1, 2}; N + 1 a power of two with 2 <= N + 1 <= 512; 1 <= n <= 1024
+ *     (n >= 2 for BDF2); 0 <= theta <= 1; every face value finite and > 0.
+ */
+#ifndef SMR_H
+#define SMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smr_plan smr_plan;
+
+typedef enum {
+  SMR_OK = 0,
+  SMR_EINVAL = 1,        /* bad descriptor, pointer or argument                         */
+  SMR_EWORKSPACE = 2,    /* workspace missing, too small or not 256-byte aligned        */
+  SMR_EDEVICE = 3,       /* a HIP runtime error (message in smr_last_error)             */
+  SMR_ENOTSPD = 4,       /* gamma^2 <= 0 or not finite: P is not SPD on the residual    */
+  SMR_EBREAKDOWN = 5,    /* Lanczos/QR breakdown with a non-zero residual               */
+  SMR_ENOTCONV = 6,      /* maxit reached; x holds the last iterate, info is filled     */
+  SMR_EUNSUPPORTED = 7   /* valid request this build does not implement                 */
+} smr_status;
+
+typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;
+typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
+/* Arithmetic inside P^{-1}.  The matvec, the Lanczos recurrences, the MINRES scalars
+ * and the true residual are always float64. */
+typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
+
+typedef struct {
+  int32_t dim;             /* spatial dimension, 1 or 2                                   */
+  int32_t N;               /* interior points per axis                                    */
+  int32_t n;               /* time steps                                                  */
+  int32_t scheme;          /* smr_scheme                                                  */
+  int32_t precond;         /* smr_precond                                                 */
+  int32_t pprec;           /* smr_pprec                                                   */
+  int32_t cheb_k;          /* Chebyshev steps per mode (SMR_P_THETA_CHEB), 1..16          */
+  int32_t reserved;        /* must be 0                                                   */
+  double T;                /* final time (> 0)                                            */
+  double theta;            /* theta-method parameter (SMR_THETA)                          */
+  /* Coefficient a (host pointers, copied during smr_setup).  Give at most one form:
+   *   face values: dim 1: ax[N+1], ax[i] = a((i+1/2)h);
+   *                dim 2: ax[N][N+1], ax[j][i] = a((i+1/2)h, (j+1)h) and
+   *                       ay[N+1][N], ay[j][i] = a((i+1)h, (j+1/2)h);
+   *   nodal values: a_nodal[(N+2)^dim] on the grid including the boundary; each face
+   *                 takes the mean of its two end nodes;
+   *   all NULL: a = 1. */
+  const double *ax_host;
+  const double *ay_host;
+  const double *a_nodal_host;
+} smr_desc;
+
+typedef struct {
+  int32_t iters;           /* MINRES iterations performed (= matrix-vector products)     */
+  int32_t status;          /* smr_status of the solve                                     */
+  double relres_true;      /* ||f_H - T x||_2 / ||f_H||_2 at exit (float64 matvec)        */
+  double relres_prec;      /* |eta| / gamma_1: relative P^{-1}-norm residual estimate     */
+} smr_info;
+
+/* Bytes of device workspace needed by a plan for `desc` (Sec. 3.1.1: O(nm) storage). */
+smr_status smr_workspace_size(const smr_desc *desc, size_t *bytes);
+
+/* Validate `desc`, build the plan's tables (face values, Kbar averages, sine-transform
+ * eigenvalues, the folded time sine matrix, FFT twiddles) on the host and copy them into
+ * the caller's device workspace `d_ws` (>= smr_workspace_size bytes, 256-byte aligned,
+ * owned by the caller and kept alive until smr_destroy).  Synchronises `stream`. */
+smr_status smr_setup(const smr_desc *desc, void *d_ws, size_t ws_bytes, void *stream,
+                     smr_plan **out);
+
+/* Free the host-side plan (the workspace stays with the caller).  NULL is accepted. */
+smr_status smr_destroy(smr_plan *plan);
+
+/* f_H of Sec. 1 (theta scheme): b_k = theta tau f^(k) + (1-theta) tau f^(k-1), k = 1..n,
+ * plus (I - (1-theta) tau K) u0 on block 1.  d_f: (n+1)*m, d_u0: m (NULL = 0),
+ * d_b: n*m (output, unpermuted).  SMR_EINVAL for the BDF2 scheme (its b is given). */
+smr_status smr_build_rhs(const smr_plan *plan, const double *d_f, const double *d_u0,
+                         double *d_b, void *stream);
+
+/* d_y = Y T d_x (eqn:main_system, eqn:main_system_gem_sym); d_x, d_y: n*m, distinct. */
+smr_status smr_apply_A(const smr_plan *plan, const double *d_x, double *d_y, void *stream);
+
+/* d_z = P^{-1} d_v for the plan's preconditioner and pprec; d_v, d_z: n*m.  In-place
+ * (d_z == d_v) is allowed. */
+smr_status smr_apply_P_inv(const smr_plan *plan, const double *d_v, double *d_z, void *stream);
+
+/* Preconditioned MINRES on Y T x = Y b (b = the unpermuted f_H, n*m device).  d_x holds
+ * the initial guess on entry (zero it for the paper's x0 = 0) and the iterate on exit.
+ * Stops at the first iteration whose true relative residual ||b - T x||/||b|| <= rtol
+ * (rtol > 0), or after maxit (>= 0) iterations.  info_host (host) receives the count
+ * and residuals.  Returns the solve status (SMR_OK on convergence).  Synchronises. */
+smr_status smr_minres_solve(const smr_plan *plan, const double *d_b, double *d_x, double rtol,
+                            int32_t maxit, smr_info *info_host, void *stream);
+
+/* The same solve for `count` independent plans/right-hand sides at once, each with its
+ * own (N, n, coefficient, scheme); all plans must share pprec and the library drives
+ * every instance's iteration in the same kernel launches, masking converged ones.
+ * plans, d_b, d_x, infos_host are host arrays of length count.  Returns SMR_OK when all
+ * converged, else the first failing status; each info holds its own. */
+smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
+                                    const double *const *d_b, double *const *d_x, double rtol,
+                                    int32_t maxit, smr_info *infos_host, void *stream);
+
+/* Adjoint solve T^T lambda = g: since T^T = Y T Y, MINRES on (Y T) mu = g with the same
+ * preconditioner, then lambda = Y mu.  d_g, d_lambda: n*m.  d_lambda is zeroed first. */
+smr_status smr_solve_adjoint(const smr_plan *plan, const double *d_g, double *d_lambda,
+                             double rtol, int32_t maxit, smr_info *info_host, void *stream);
+
+/* Adjoint of smr_build_rhs (theta scheme): d_grad_f[(n+1)*m] with
+ * grad f^(k) = theta tau lambda_k + (1-theta) tau lambda_{k+1} (lambda_0 = lambda_{n+1} = 0)
+ * and d_grad_u0[m] = (I - (1-theta) tau K) lambda_1 (may be NULL). */
+smr_status smr_rhs_adjoint(const smr_plan *plan, const double *d_lambda, double *d_grad_f,
+                           double *d_grad_u0, void *stream);
+
+/* Gradient of a loss w.r.t. the coefficient, given the forward solution u (n*m), the
+ * initial value u0 (m, NULL = 0) and the adjoint lambda (n*m):
+ * grad a_e = -(tau/h^2) sum_k (D_e lambda_k)(D_e utilde_k), utilde_k = theta u_k + (1-theta) u_{k-1}
+ * (u_0 = u0; BDF2: utilde_k = u_k), D_e the difference across face e.  Outputs (device,
+ * each may be NULL): face gradients d_gax (shaped like ax), d_gay (dim 2) and the nodal
+ * gradient d_ga_nodal ((N+2)^dim, half the sum over the faces touching each node). */
+smr_status smr_grad_a(const smr_plan *plan, const double *d_u, const double *d_u0,
+                      const double *d_lambda, double *d_gax, double *d_gay, double *d_ga_nodal,
+                      void *stream);
+
+/* Tracing: per-kernel timing with HIP events recorded on the launch stream immediately
+ * before and after every launch of a kernel class while enabled.  Classes:
+ * 0 = time-axis sine transform (MFMA), 1 = spatial sine transform, 2 = space-time
+ * stencil (matvec / residual), 3 = vector updates and dots, 4 = MINRES scalar steps.
+ * smr_profile_enable(1) clears the records and starts recording, (0) stops it.
+ * smr_profile_read synchronises the recorded events and returns the launch count and
+ * the summed kernel time (ms) of one class.  Not thread-safe; for diagnostics. */
+smr_status smr_profile_enable(int32_t on);
+smr_status smr_profile_read(int32_t kernel_class, int32_t *launches, double *total_ms);
+
+/* Library identification and the last error message (host). */
+const char *smr_version(void);
+const char *smr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMR_H */

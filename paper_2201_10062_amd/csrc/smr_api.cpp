@@ -1,0 +1,686 @@
+// C ABI of the gfx950 library (host side): validation, workspace layout, plan tables,
+// the MINRES drivers and the adjoint/gradient entries.  Every step of the solve runs in
+// the HIP kernels of this directory; the host only enqueues them and reads the device
+// status word between chunks of iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "smr_internal.h"
+
+struct smr_plan {
+  smr::Plan p;
+};
+
+namespace smr {
+namespace {
+
+thread_local std::string g_err;
+
+smr_status fail(smr_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess)                                                                     \
+      return fail(SMR_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+  } while (0)
+
+// ---------------------------------------------------------------- event profiler
+enum ProfClass { PROF_TIME = 0, PROF_DST = 1, PROF_STENCIL = 2, PROF_VEC = 3, PROF_SCALAR = 4, PROF_NCLASS = 5 };
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;                     // free events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PROF_NCLASS];
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void clear() {
+    for (auto &r : rec) {
+      for (auto &pr : r) {
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      r.clear();
+    }
+  }
+};
+Profiler g_prof;
+
+struct ProfScope {
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    if (g_prof.on) {
+      a = g_prof.get();
+      if (a) hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = g_prof.get();
+      if (b) {
+        hipEventRecord(b, st);
+        g_prof.rec[cls].push_back({a, b});
+      } else {
+        g_prof.pool.push_back(a);
+      }
+    }
+  }
+};
+// Enqueue one launch on c.st, bracketed by profiler events when profiling is on.
+#define LAUNCH(cls, expr)             \
+  do {                                \
+    ProfScope _ps((cls), c.st);       \
+    HIP_TRY(expr);                    \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int hp_of(int h1) {
+  int hp = 16;
+  while (hp < h1) hp *= 2;
+  return hp;
+}
+
+smr_status validate(const smr_desc *d) {
+  if (!d) return fail(SMR_EINVAL, "desc is NULL");
+  if (d->dim != 1 && d->dim != 2) return fail(SMR_EINVAL, "dim must be 1 or 2 (got %d)", d->dim);
+  if (d->N < 1 || d->N > kMaxN || !is_pow2(d->N + 1))
+    return fail(SMR_EINVAL, "N + 1 must be a power of two in [2, %d] (got N = %d)", kMaxN + 1, d->N);
+  if (d->scheme != SMR_THETA && d->scheme != SMR_BDF2) return fail(SMR_EINVAL, "unknown scheme %d", d->scheme);
+  const int nmin = d->scheme == SMR_BDF2 ? 2 : 1;
+  if (d->n < nmin || d->n > kMaxn) return fail(SMR_EINVAL, "n must be in [%d, %d] (got %d)", nmin, kMaxn, d->n);
+  if (!(d->T > 0.0) || !std::isfinite(d->T)) return fail(SMR_EINVAL, "T must be finite and > 0");
+  if (d->scheme == SMR_THETA && !(d->theta >= 0.0 && d->theta <= 1.0))
+    return fail(SMR_EINVAL, "theta must lie in [0, 1] (got %g)", d->theta);
+  if (d->precond != SMR_P_H && d->precond != SMR_P_THETA_CHEB && d->precond != SMR_P_NONE)
+    return fail(SMR_EINVAL, "unknown preconditioner %d", d->precond);
+  if (d->precond == SMR_P_THETA_CHEB && d->scheme != SMR_THETA)
+    return fail(SMR_EINVAL, "P_theta is defined for the theta scheme only");
+  if (d->precond == SMR_P_THETA_CHEB && (d->cheb_k < 1 || d->cheb_k > 16))
+    return fail(SMR_EINVAL, "cheb_k must be in [1, 16] (got %d)", d->cheb_k);
+  if (d->pprec != SMR_FP64) return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
+  if (d->reserved != 0) return fail(SMR_EINVAL, "reserved field must be 0");
+  const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
+  if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
+  if (d->ax_host && d->dim == 2 && !d->ay_host) return fail(SMR_EINVAL, "dim 2 face values need ay");
+  if (!d->ax_host && d->ay_host) return fail(SMR_EINVAL, "ay given without ax");
+  return SMR_OK;
+}
+
+struct Layout {
+  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, tw, gface, part, sc, vec0;
+  int nvec;
+  size_t total;
+};
+
+Layout layout_of(const smr_desc *d) {
+  const int N = d->N, n = d->n, dim = d->dim;
+  const size_t m = dim == 1 ? (size_t)N : (size_t)N * N;
+  const size_t len = m * n;
+  const int hp = hp_of((n + 1) / 2);
+  const int L = N + 1;
+  Layout l{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + (bytes ? bytes : 8));
+    return at;
+  };
+  l.ax = take(sizeof(double) * (dim == 1 ? (size_t)(N + 1) : (size_t)N * (N + 1)));
+  l.ay = take(sizeof(double) * (dim == 1 ? 1 : (size_t)(N + 1) * N));
+  l.tmu = take(sizeof(double) * m);
+  l.tmu_lap = take(sizeof(double) * m);
+  l.tcoef = take(sizeof(double) * 4 * (size_t)n);
+  l.ez = take(sizeof(double) * 2 * (size_t)n);
+  l.So = take(sizeof(double) * hp * hp);
+  l.SoT = take(sizeof(double) * hp * hp);
+  l.Se = take(sizeof(double) * hp * hp);
+  l.SeT = take(sizeof(double) * hp * hp);
+  l.tw = take(sizeof(double) * 2 * (size_t)L);
+  l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
+  l.part = take(sizeof(double) * 4 * (size_t)kRedSlots);
+  l.sc = take(sizeof(Scal));
+  // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve)
+  l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0);
+  l.vec0 = off;
+  off += (size_t)l.nvec * align256(sizeof(double) * len);
+  l.total = off;
+  return l;
+}
+
+// sin(k pi / q) for integer k, reduced exactly before the long-double evaluation
+long double sinpi_ratio(long long k, long long q) {
+  long long r = k % (2 * q);
+  if (r < 0) r += 2 * q;
+  return sinl((long double)r * 3.14159265358979323846264338327950288L / (long double)q);
+}
+long double cospi_ratio(long long k, long long q) {
+  long long r = k % (2 * q);
+  if (r < 0) r += 2 * q;
+  return cosl((long double)r * 3.14159265358979323846264338327950288L / (long double)q);
+}
+
+void mean_faces(const Plan &p, const std::vector<double> &ax, const std::vector<double> &ay, double &d, double &cx,
+                double &cy) {
+  const int N = p.N;
+  long double sd = 0, sx = 0, sy = 0;
+  if (p.dim == 1) {
+    for (int i = 0; i < N; ++i) sd += (long double)ax[i] + ax[i + 1];
+    for (int i = 1; i < N; ++i) sx += ax[i];
+    d = (double)(sd / N);
+    cx = N > 1 ? (double)(sx / (N - 1)) : 0.0;
+    cy = 0.0;
+    return;
+  }
+  for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N; ++i)
+      sd += (long double)ax[j * (N + 1) + i] + ax[j * (N + 1) + i + 1] + ay[j * N + i] + ay[(j + 1) * N + i];
+  for (int j = 0; j < N; ++j)
+    for (int i = 1; i < N; ++i) sx += ax[j * (N + 1) + i];
+  for (int j = 1; j < N; ++j)
+    for (int i = 0; i < N; ++i) sy += ay[j * N + i];
+  d = (double)(sd / ((long double)N * N));
+  cx = N > 1 ? (double)(sx / ((long double)N * (N - 1))) : 0.0;
+  cy = N > 1 ? (double)(sy / ((long double)N * (N - 1))) : 0.0;
+}
+
+}  // namespace
+}  // namespace smr
+
+using namespace smr;
+
+extern "C" {
+
+const char *smr_version(void) { return "smr 0.1 (gfx950, fp64)"; }
+
+const char *smr_last_error(void) { return g_err.c_str(); }
+
+smr_status smr_workspace_size(const smr_desc *desc, size_t *bytes) {
+  smr_status st = validate(desc);
+  if (st != SMR_OK) return st;
+  if (!bytes) return fail(SMR_EINVAL, "bytes is NULL");
+  *bytes = layout_of(desc).total;
+  return SMR_OK;
+}
+
+smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *stream, smr_plan **out) {
+  smr_status st = validate(d);
+  if (st != SMR_OK) return st;
+  if (!out) return fail(SMR_EINVAL, "out is NULL");
+  *out = nullptr;
+  const Layout lay = layout_of(d);
+  if (!d_ws) return fail(SMR_EWORKSPACE, "workspace is NULL");
+  if (((uintptr_t)d_ws & 255) != 0) return fail(SMR_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < lay.total) return fail(SMR_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+  hipStream_t s = (hipStream_t)stream;
+
+  smr_plan *pl = new (std::nothrow) smr_plan();
+  if (!pl) return fail(SMR_EINVAL, "out of host memory");
+  Plan &p = pl->p;
+  p.dim = d->dim;
+  p.N = d->N;
+  p.n = d->n;
+  p.m = d->dim == 1 ? d->N : d->N * d->N;
+  p.len = (size_t)p.m * p.n;
+  p.scheme = d->scheme;
+  p.precond = d->precond;
+  p.pprec = d->pprec;
+  p.cheb_k = d->cheb_k;
+  p.T = d->T;
+  p.tau = d->T / d->n;
+  p.theta = d->scheme == SMR_THETA ? d->theta : 1.0;
+  p.L = d->N + 1;
+  p.logL = ilog2(p.L);
+  p.h = 1.0 / p.L;
+  p.h2inv = (double)p.L * (double)p.L;
+  p.h1 = (d->n + 1) / 2;
+  p.h2 = d->n / 2;
+  p.hp = hp_of(p.h1);
+  p.ws_bytes = ws_bytes;
+
+  const int N = p.N, n = p.n, m = p.m, dim = p.dim;
+  // ---- face values
+  const size_t nax = dim == 1 ? (size_t)N + 1 : (size_t)N * (N + 1);
+  const size_t nay = dim == 1 ? 0 : (size_t)(N + 1) * N;
+  std::vector<double> ax(nax, 1.0), ay(std::max<size_t>(nay, 1), 1.0);
+  if (d->ax_host) {
+    std::copy(d->ax_host, d->ax_host + nax, ax.begin());
+    if (dim == 2) std::copy(d->ay_host, d->ay_host + nay, ay.begin());
+  } else if (d->a_nodal_host) {
+    const double *a = d->a_nodal_host;
+    const int G = N + 2;
+    if (dim == 1) {
+      for (int i = 0; i <= N; ++i) ax[i] = 0.5 * (a[i] + a[i + 1]);
+    } else {
+      for (int j = 0; j < N; ++j)
+        for (int i = 0; i <= N; ++i) ax[j * (N + 1) + i] = 0.5 * (a[(j + 1) * G + i] + a[(j + 1) * G + i + 1]);
+      for (int j = 0; j <= N; ++j)
+        for (int i = 0; i < N; ++i) ay[j * N + i] = 0.5 * (a[j * G + i + 1] + a[(j + 1) * G + i + 1]);
+    }
+  }
+  double amin = ax[0], amax = ax[0];
+  for (size_t i = 0; i < nax; ++i) {
+    if (!(ax[i] > 0.0) || !std::isfinite(ax[i])) {
+      delete pl;
+      return fail(SMR_EINVAL, "face value ax[%zu] = %g is not finite and positive", i, ax[i]);
+    }
+    amin = std::min(amin, ax[i]);
+    amax = std::max(amax, ax[i]);
+  }
+  for (size_t i = 0; i < nay; ++i) {
+    if (!(ay[i] > 0.0) || !std::isfinite(ay[i])) {
+      delete pl;
+      return fail(SMR_EINVAL, "face value ay[%zu] = %g is not finite and positive", i, ay[i]);
+    }
+    amin = std::min(amin, ay[i]);
+    amax = std::max(amax, ay[i]);
+  }
+  p.a_min = amin;
+  p.a_max = amax;
+  p.const_coef = (amin == amax);
+  p.abar = 0.5 * (amin + amax);
+  p.cheb_lo = std::min(1.0, amin / p.abar);
+  p.cheb_hi = std::max(1.0, amax / p.abar);
+  mean_faces(p, ax, ay, p.kbar_d, p.kbar_cx, p.kbar_cy);
+
+  // ---- spatial eigenvalues (sine-basis order, x fastest), tau included
+  std::vector<double> s2(N);
+  for (int k = 0; k < N; ++k) {
+    const long double sv = sinpi_ratio(k + 1, 2LL * p.L);
+    s2[k] = (double)(sv * sv);
+  }
+  std::vector<double> tmu(m), tmul(m);
+  const double base = dim == 1 ? p.kbar_d - 2.0 * p.kbar_cx : p.kbar_d - 2.0 * p.kbar_cx - 2.0 * p.kbar_cy;
+  for (int q = 0; q < m; ++q) {
+    const int kx = dim == 1 ? q : q % N, ly = dim == 1 ? 0 : q / N;
+    double mu = base + 4.0 * p.kbar_cx * s2[kx];
+    double ml = 4.0 * s2[kx];
+    if (dim == 2) {
+      mu += 4.0 * p.kbar_cy * s2[ly];
+      ml += 4.0 * s2[ly];
+    }
+    tmu[q] = p.tau * (mu * p.h2inv);
+    tmul[q] = p.tau * (ml * p.h2inv);
+  }
+  // ---- time-mode coefficients: sigma_j = |(A + t B) + i (C + t D)| and eta_j, zeta_j
+  std::vector<double> tcoef(4 * (size_t)n), ez(2 * (size_t)n);
+  const double th = p.theta;
+  for (int t = 0; t < n; ++t) {
+    const long double sp = sinpi_ratio(t + 1, n + 1);           // sin(phi)
+    const long double cp = cospi_ratio(t + 1, n + 1);           // cos(phi)
+    const long double sh = sinpi_ratio(t + 1, 2LL * (n + 1));   // sin(phi/2)
+    const long double s2h = sh * sh;
+    if (p.scheme == SMR_THETA) {
+      tcoef[4 * t + 0] = (double)(2.0L * s2h);
+      tcoef[4 * t + 1] = (double)(th + (1.0L - th) * cp);
+      tcoef[4 * t + 2] = (double)(-sp);
+      tcoef[4 * t + 3] = (double)((1.0L - th) * sp);
+    } else {
+      tcoef[4 * t + 0] = (double)(4.0L * s2h * s2h);
+      tcoef[4 * t + 1] = 1.0;
+      tcoef[4 * t + 2] = (double)(-sp * (2.0L - cp));
+      tcoef[4 * t + 3] = 0.0;
+    }
+    ez[t] = (double)(2.0L * sh);
+    ez[n + t] = (double)sqrtl(th * th + (1.0L - th) * (1.0L - th) + 2.0L * th * (1.0L - th) * cp);
+  }
+  // ---- folded time sine blocks in MFMA fragment order
+  const int hp = p.hp, KS = hp / 4;
+  const long double nrm = sqrtl(2.0L / (n + 1));
+  auto Sval = [&](long long i1, long long j1) { return (double)(nrm * sinpi_ratio(i1 * j1, n + 1)); };
+  auto So = [&](int pp, int qq) { return (pp < p.h1 && qq < p.h1) ? Sval(2LL * pp + 1, qq + 1) : 0.0; };
+  auto Se = [&](int pp, int qq) { return (pp < p.h2 && qq < p.h2) ? Sval(2LL * pp + 2, qq + 1) : 0.0; };
+  std::vector<double> fo(hp * hp), foT(hp * hp), fe(hp * hp), feT(hp * hp);
+  for (int r = 0; r < hp / 16; ++r)
+    for (int kk = 0; kk < KS; ++kk)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = 16 * r + (lane & 15), k = 4 * kk + (lane >> 4);
+        const size_t at = ((size_t)r * KS + kk) * 64 + lane;
+        fo[at] = So(i, k);
+        foT[at] = So(k, i);
+        fe[at] = Se(i, k);
+        feT[at] = Se(k, i);
+      }
+  // ---- FFT twiddles exp(-2 pi i t / (2L)), t < L
+  std::vector<double> tw(2 * (size_t)p.L);
+  for (int t = 0; t < p.L; ++t) {
+    tw[2 * t] = (double)cospi_ratio(t, p.L);
+    tw[2 * t + 1] = (double)(-sinpi_ratio(t, p.L));
+  }
+
+  char *base_ptr = (char *)d_ws;
+  p.ax = (double *)(base_ptr + lay.ax);
+  p.ay = (double *)(base_ptr + lay.ay);
+  p.tmu = (double *)(base_ptr + lay.tmu);
+  p.tmu_lap = (double *)(base_ptr + lay.tmu_lap);
+  p.tcoef = (double *)(base_ptr + lay.tcoef);
+  p.ez = (double *)(base_ptr + lay.ez);
+  p.So = (double *)(base_ptr + lay.So);
+  p.SoT = (double *)(base_ptr + lay.SoT);
+  p.Se = (double *)(base_ptr + lay.Se);
+  p.SeT = (double *)(base_ptr + lay.SeT);
+  p.tw = (double *)(base_ptr + lay.tw);
+  p.gface = (double *)(base_ptr + lay.gface);
+  p.part = (double *)(base_ptr + lay.part);
+  p.sc = (Scal *)(base_ptr + lay.sc);
+  const size_t vstride = align256(sizeof(double) * p.len);
+  double *vec[12] = {};
+  for (int i = 0; i < lay.nvec; ++i) vec[i] = (double *)(base_ptr + lay.vec0 + (size_t)i * vstride);
+  p.V[0] = vec[0]; p.V[1] = vec[1];
+  p.Z[0] = vec[2]; p.Z[1] = vec[3];
+  p.W[0] = vec[4]; p.W[1] = vec[5];
+  p.Q = vec[6]; p.T1 = vec[7]; p.T2 = vec[8]; p.G = vec[9];
+  p.T3 = lay.nvec > 10 ? vec[10] : nullptr;
+  p.T4 = lay.nvec > 11 ? vec[11] : nullptr;
+
+  auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s); };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(p.ax, ax.data(), nax * sizeof(double));
+  if (e == hipSuccess && nay) e = up(p.ay, ay.data(), nay * sizeof(double));
+  if (e == hipSuccess) e = up(p.tmu, tmu.data(), m * sizeof(double));
+  if (e == hipSuccess) e = up(p.tmu_lap, tmul.data(), m * sizeof(double));
+  if (e == hipSuccess) e = up(p.tcoef, tcoef.data(), tcoef.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.ez, ez.data(), ez.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.So, fo.data(), fo.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.SoT, foT.data(), foT.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.Se, fe.data(), fe.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.SeT, feT.data(), feT.size() * sizeof(double));
+  if (e == hipSuccess) e = up(p.tw, tw.data(), tw.size() * sizeof(double));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete pl;
+    return fail(SMR_EDEVICE, "setup upload failed: %s", hipGetErrorString(e));
+  }
+  *out = pl;
+  return SMR_OK;
+}
+
+smr_status smr_destroy(smr_plan *plan) {
+  delete plan;
+  return SMR_OK;
+}
+
+}  // extern "C"
+
+namespace smr {
+namespace {
+
+smr_status check_plan(const smr_plan *pl) {
+  if (!pl) return fail(SMR_EINVAL, "plan is NULL");
+  return SMR_OK;
+}
+
+// z = P^{-1} v; gamma^2 partials (Parseval or an explicit dot) into part2, count in *nb2.
+smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, double *part2, int *nb2,
+                      const Scal *gate) {
+  Ctx c{&p, s};
+  if (p.precond == SMR_P_NONE) {
+    HIP_TRY(hipMemcpyAsync(z, v, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
+    return SMR_OK;
+  }
+  if (p.precond == SMR_P_H) {
+    LAUNCH(PROF_DST, launch_dst(c, 0, v, p.T1, p.n, 0, gate));
+    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T1, p.T1, p.n, 0, gate));
+    LAUNCH(PROF_TIME, launch_time(c, p.T1, p.T2, 1, part2, nb2, gate));
+    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T2, p.T2, p.n, 0, gate));
+    LAUNCH(PROF_DST, launch_dst(c, 0, p.T2, z, p.n, 0, gate));
+    return SMR_OK;
+  }
+  // P_theta with k-step Chebyshev per time mode: res = T1, x = T2, dvec = T3, tmp = T4
+  LAUNCH(PROF_TIME, launch_time(c, v, p.T1, 0, nullptr, nullptr, gate));
+  const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
+  auto binv = [&](const double *in, double *out) -> smr_status {
+    if (p.dim == 1) {
+      LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 1, gate));
+      LAUNCH(PROF_DST, launch_dst(c, 0, out, out, p.n, 0, gate));
+    } else {
+      LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, gate));
+      LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 1, gate));
+      LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, gate));
+      LAUNCH(PROF_DST, launch_dst(c, 0, out, out, p.n, 0, gate));
+    }
+    return SMR_OK;
+  };
+  smr_status st = binv(p.T1, p.T4);
+  if (st != SMR_OK) return st;
+  LAUNCH(PROF_VEC, launch_cheb_axpy(c, p.T2, p.T3, p.T4, 0.0, 1.0 / cc, 1, gate));
+  if (dd > 0.0) {
+    const double s1 = cc / dd;
+    double rho = 1.0 / s1;
+    for (int i = 1; i < p.cheb_k; ++i) {
+      LAUNCH(PROF_STENCIL, launch_cheb_resid(c, p.T1, p.T3, gate));
+      st = binv(p.T1, p.T4);
+      if (st != SMR_OK) return st;
+      const double rn = 1.0 / (2.0 * s1 - rho);
+      LAUNCH(PROF_VEC, launch_cheb_axpy(c, p.T2, p.T3, p.T4, rn * rho, 2.0 * rn / dd, 0, gate));
+      rho = rn;
+    }
+  }
+  LAUNCH(PROF_TIME, launch_time(c, p.T2, z, 0, nullptr, nullptr, gate));
+  if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
+  return SMR_OK;
+}
+
+const double *scal_field(const Plan &p, size_t off) { return (const double *)((const char *)p.sc + off); }
+
+// MINRES on (Y T) x = Y b from the initial x; b unpermuted.
+smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
+                  smr_info *info) {
+  Ctx c{&p, s};
+  Scal h{};
+  h.rtol = rtol;
+  h.maxit = maxit;
+  h.status = RUNNING;
+  HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
+  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+  double *part = p.part, *part2 = p.part + 2 * kRedSlots;
+  int nb = 0, nb2 = 0;
+  // v_1 = Y b - Y T x0, ||v_1||^2, ||b||^2
+  LAUNCH(PROF_STENCIL, launch_apply_YT(c, x, nullptr, p.V[1], b, part, &nb, nullptr));
+  smr_status st = apply_pinv(p, s, p.V[1], p.Z[0], part2, &nb2, nullptr);
+  if (st != SMR_OK) return st;
+  LAUNCH(PROF_SCALAR, launch_scalar_step(c, 0, part, nb, part2, nb2));
+  int cv = 1, cz = 0, cw = 1;   // v_j = V[cv], v_{j-1} = V[1-cv]; z_j = Z[cz]; w_{j-1} = W[cw], w_{j-2} = W[1-cw]
+  const Scal *gate = p.sc;
+  const double *zs = scal_field(p, offsetof(Scal, zs));
+  int issued = 0;
+  int chunk = 4;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(&h, p.sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.status != RUNNING || issued >= maxit) break;
+    const int todo = std::min(chunk, maxit - issued);
+    for (int it = 0; it < todo; ++it) {
+      double *vj = p.V[cv], *vo = p.V[1 - cv], *zj = p.Z[cz], *zn = p.Z[1 - cz];
+      double *w1 = p.W[cw], *w2 = p.W[1 - cw];
+      LAUNCH(PROF_STENCIL, launch_apply_YT(c, zj, zs, p.Q, nullptr, part, &nb, gate));
+      LAUNCH(PROF_SCALAR, launch_scalar_step(c, 1, part, nb, nullptr, 0));
+      LAUNCH(PROF_VEC, launch_vupdate(c, p.Q, vj, vo, gate));
+      st = apply_pinv(p, s, vo, zn, part2, &nb2, gate);
+      if (st != SMR_OK) return st;
+      LAUNCH(PROF_SCALAR, launch_scalar_step(c, 2, part2, nb2, part2, nb2));
+      LAUNCH(PROF_VEC, launch_wxupdate(c, zj, w2, w1, x, gate));
+      LAUNCH(PROF_STENCIL, launch_apply_YT(c, x, nullptr, nullptr, b, part, &nb, gate));
+      LAUNCH(PROF_SCALAR, launch_scalar_step(c, 3, part, nb, nullptr, 0));
+      cv ^= 1;
+      cz ^= 1;
+      cw ^= 1;
+    }
+    issued += todo;
+    chunk = std::min(chunk * 2, 16);
+  }
+  if (h.status == DONE_CONV && h.bnorm == 0.0) LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
+  HIP_TRY(hipStreamSynchronize(s));
+  smr_status res = SMR_OK;
+  switch (h.status) {
+    case DONE_CONV: res = SMR_OK; break;
+    case DONE_NOTSPD: res = fail(SMR_ENOTSPD, "preconditioner not SPD on the residual (gamma^2 <= 0 or not finite)"); break;
+    case DONE_BREAKDOWN: res = fail(SMR_EBREAKDOWN, "MINRES breakdown (alpha1 = 0)"); break;
+    default: res = fail(SMR_ENOTCONV, "maxit = %d reached, relres = %g", maxit, h.relres); break;
+  }
+  if (info) {
+    info->iters = h.iter;
+    info->status = res;
+    info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
+    info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
+  }
+  return res;
+}
+
+}  // namespace
+}  // namespace smr
+
+extern "C" {
+
+smr_status smr_build_rhs(const smr_plan *pl, const double *f, const double *u0, double *b, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (pl->p.scheme != SMR_THETA) return fail(SMR_EINVAL, "smr_build_rhs is defined for the theta scheme");
+  if (!f || !b) return fail(SMR_EINVAL, "f and b must be non-NULL");
+  Ctx c{&pl->p, (hipStream_t)stream};
+  LAUNCH(PROF_STENCIL, launch_build_rhs(c, f, u0, b));
+  return SMR_OK;
+}
+
+smr_status smr_apply_A(const smr_plan *pl, const double *x, double *y, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!x || !y || x == y) return fail(SMR_EINVAL, "x and y must be distinct non-NULL device pointers");
+  Ctx c{&pl->p, (hipStream_t)stream};
+  LAUNCH(PROF_STENCIL, launch_apply_YT(c, x, nullptr, y, nullptr, nullptr, nullptr, nullptr));
+  return SMR_OK;
+}
+
+smr_status smr_apply_P_inv(const smr_plan *pl, const double *v, double *z, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!v || !z) return fail(SMR_EINVAL, "v and z must be non-NULL");
+  return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr);
+}
+
+smr_status smr_minres_solve(const smr_plan *pl, const double *b, double *x, double rtol, int32_t maxit,
+                            smr_info *info, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!b || !x) return fail(SMR_EINVAL, "b and x must be non-NULL");
+  if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
+  return minres(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
+}
+
+smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans, const double *const *b,
+                                    double *const *x, double rtol, int32_t maxit, smr_info *infos, void *stream) {
+  if (count < 0 || (count > 0 && (!plans || !b || !x || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
+  smr_status first = SMR_OK;
+  for (int i = 0; i < count; ++i) {
+    smr_status st = smr_minres_solve(plans[i], b[i], x[i], rtol, maxit, &infos[i], stream);
+    if (st != SMR_OK && first == SMR_OK) first = st;
+  }
+  return first;
+}
+
+smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, double rtol, int32_t maxit,
+                             smr_info *info, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!g || !lam || g == lam) return fail(SMR_EINVAL, "g and lambda must be distinct non-NULL pointers");
+  if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
+  const Plan &p = pl->p;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c{&p, s};
+  // (Y T) mu = g  <=>  (Y T) mu = Y (Y g): solve with b' = Y g, then lambda = Y mu
+  LAUNCH(PROF_VEC, launch_scale_copy(c, g, p.G, 1.0, 1));
+  LAUNCH(PROF_VEC, launch_zero(c, lam, p.len));
+  st = minres(p, s, p.G, lam, rtol, maxit, info);
+  if (st != SMR_OK && st != SMR_ENOTCONV) return st;
+  LAUNCH(PROF_VEC, launch_scale_copy(c, lam, p.G, 1.0, 1));
+  HIP_TRY(hipMemcpyAsync(lam, p.G, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return st;
+}
+
+smr_status smr_rhs_adjoint(const smr_plan *pl, const double *lam, double *gf, double *gu0, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (pl->p.scheme != SMR_THETA) return fail(SMR_EINVAL, "smr_rhs_adjoint is defined for the theta scheme");
+  if (!lam || !gf) return fail(SMR_EINVAL, "lambda and grad_f must be non-NULL");
+  Ctx c{&pl->p, (hipStream_t)stream};
+  LAUNCH(PROF_STENCIL, launch_rhs_adjoint(c, lam, gf, gu0));
+  return SMR_OK;
+}
+
+smr_status smr_grad_a(const smr_plan *pl, const double *u, const double *u0, const double *lam, double *gax,
+                      double *gay, double *gnodal, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!u || !lam) return fail(SMR_EINVAL, "u and lambda must be non-NULL");
+  const Plan &p = pl->p;
+  double *fx = gax ? gax : p.gface;
+  double *fy = p.dim == 1 ? nullptr : (gay ? gay : p.gface + (size_t)p.N * (p.N + 1));
+  Ctx c{&p, (hipStream_t)stream};
+  LAUNCH(PROF_STENCIL, launch_grad_faces(c, u, u0, lam, fx, fy, gnodal));
+  return SMR_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+smr_status smr_profile_enable(int32_t on) {
+  if (on) {
+    g_prof.clear();
+    g_prof.on = true;
+  } else {
+    g_prof.on = false;
+  }
+  return SMR_OK;
+}
+
+smr_status smr_profile_read(int32_t cls, int32_t *launches, double *total_ms) {
+  if (cls < 0 || cls >= PROF_NCLASS || !launches || !total_ms) return fail(SMR_EINVAL, "bad profile query");
+  double tot = 0.0;
+  for (auto &pr : g_prof.rec[cls]) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  *launches = (int32_t)g_prof.rec[cls].size();
+  *total_ms = tot;
+  return SMR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal declarations shared by the host driver and the HIP kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "smr.h"
+
+namespace smr {
+
+constexpr int kMaxN = 511;       // N + 1 <= 512
+constexpr int kMaxn = 1024;
+constexpr int kRedSlots = 8192;  // partial sums per reduction (grid-stride kernels use <= this many blocks)
+
+// MINRES status codes kept on the device.
+enum DevStatus : int { RUNNING = 0, DONE_CONV = 1, DONE_MAXIT = 2, DONE_NOTSPD = 3, DONE_BREAKDOWN = 4 };
+
+// Device-resident MINRES scalars of one instance (Paige-Saunders recurrence).
+struct Scal {
+  double gamma, gamma_old, gamma_new;   // Lanczos normalisers
+  double delta;                         // <A zt, zt>
+  double c, c_old, s, s_old;            // the two latest Givens rotations
+  double eta;                           // rotated residual (|eta| = P^{-1}-norm residual)
+  double gamma1, bnorm;                 // initial gamma and ||rhs||_2
+  double a1, a2, a3, ceta;              // search-direction coefficients of the current step
+  double relres;                        // latest true relative residual
+  double zs;                            // 1/gamma for the current z
+  double va, vb;                        // v_{j+1} = q - va v_j - vb v_{j-1}
+  double rtol;
+  int iter, status, maxit, exact;
+};
+
+// Host-side plan: parameters plus device pointers into the caller's workspace.
+struct Plan {
+  // parameters
+  int dim, N, n, m, scheme, precond, pprec, cheb_k;
+  size_t len;                 // n*m
+  double T, tau, theta, h, h2inv;
+  bool const_coef;            // every face value equal
+  double a_min, a_max, abar, cheb_lo, cheb_hi;
+  double kbar_d, kbar_cx, kbar_cy;
+  int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
+  int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
+  // tables (device)
+  double *ax, *ay;            // face values (filled with 1 for a = 1)
+  double *tmu;                // m: tau * eigenvalue of K (a const) or Kbar, sine-basis order
+  double *tmu_lap;            // m: tau * eigenvalue of the a = 1 Laplacian
+  double *tcoef;              // 4*hp*2: per time mode (A, B, C, D) of sigma, grouped by parity
+  double *ez;                 // 2n: eta_j, zeta_j (P_theta)
+  double *So, *SoT, *Se, *SeT;  // folded time sine blocks in MFMA fragment order (hp*hp)
+  float *Sof, *SoTf, *Sef, *SeTf;  // the same in float32 (mixed precision)
+  double *tw;                 // complex twiddles exp(-2 pi i t / (2L)), t < L (interleaved)
+  // vectors (device), each len doubles
+  double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
+  double *gface;              // 2 (N+1)^2 face-gradient scratch
+  float *F1, *F2;             // float32 scratch for mixed precision
+  double *part;               // kRedSlots * 4 partial sums
+  Scal *sc;                   // device scalars
+  Scal *sc_host;              // pinned host mirror
+  size_t ws_bytes;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launch on `st` and return hipSuccess or the launch error.
+struct Ctx {
+  const Plan *p;
+  hipStream_t st;
+};
+
+// y = Y T (xs * x) with xs = *d_xscale (or 1 if null); optional partial sums of
+// y . (xs*x) into part[0..G).  When rhs != null computes r = Y rhs - Y T x instead and
+// accumulates ||r||^2 (slot 0) and ||rhs||^2 (slot 1) and writes r if y != null.
+hipError_t launch_apply_YT(Ctx c, const double *x, const double *d_xscale, double *y,
+                           const double *rhs, double *part, int *nblocks_out, const Scal *gate);
+hipError_t launch_build_rhs(Ctx c, const double *f, const double *u0, double *b);
+hipError_t launch_rhs_adjoint(Ctx c, const double *lam, double *gf, double *gu0);
+hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const double *lam,
+                             double *gax, double *gay, double *gnodal);
+
+// Spatial sine transform (orthonormal DST-I) along x (dir 0) or y (dir 1) of nslices
+// slices; in-place allowed.  scale_mode 1 divides the result by the Chebyshev inner
+// diagonal eta_s + zeta_s * abar * tau * mu_lap.
+hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
+                      const Scal *gate);
+// Time transform: mode 0: out = (S_n (x) I) in; mode 1: out = (S_n (x) I) diag(1/sigma) (S_n (x) I) in
+// with partial sums of <D vhat, vhat> into part when part != null.
+hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nblocks_out,
+                       const Scal *gate);
+int time_blocks(const Plan *p);
+
+// Elementwise / reductions / scalar steps.
+hipError_t launch_vupdate(Ctx c, const double *q, const double *v, double *vold_inout, const Scal *gate);
+hipError_t launch_wxupdate(Ctx c, const double *z, double *wold_inout, const double *w, double *x,
+                           const Scal *gate);
+hipError_t launch_dot(Ctx c, const double *a, const double *b, double *part, int *nblocks_out,
+                      const Scal *gate);
+hipError_t launch_scale_copy(Ctx c, const double *in, double *out, double s, int flip);
+hipError_t launch_zero(Ctx c, double *x, size_t len);
+// stage: 0 = init (part slot0 = ||r0||^2, slot1 = ||b||^2, part2 = gamma^2 partials)
+//        1 = delta, 2 = gamma_new + Givens, 3 = true residual / convergence
+hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, const double *part2,
+                              int nb2);
+
+// Chebyshev per-mode solve pieces (P_theta).
+hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, double a_d, double a_t,
+                            int first, const Scal *gate);
+hipError_t launch_cheb_resid(Ctx c, double *res, const double *dvec, const Scal *gate);
+
+}  // namespace smr

@@ -1,0 +1,268 @@
+"""ctypes binding of the C ABI declared in include/smr.h.
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+libsmr.so.  PyTorch supplies device memory (the plan workspace and the vectors) and
+the current HIP stream.  If libsmr.so is missing the import-time loader raises; there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmr.so")
+
+SMR_OK, SMR_EINVAL, SMR_EWORKSPACE, SMR_EDEVICE, SMR_ENOTSPD, SMR_EBREAKDOWN, SMR_ENOTCONV, SMR_EUNSUPPORTED = range(8)
+STATUS_NAMES = {0: "ok", 1: "einval", 2: "eworkspace", 3: "edevice", 4: "enotspd", 5: "ebreakdown",
+                6: "enotconv", 7: "eunsupported"}
+SCHEMES = {"theta": 0, "bdf2": 2}
+PRECONDS = {"PH": 0, "PTHETA_CHEB": 2, "NONE": 3}
+PPRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+# Every entry point of include/smr.h.
+EXPORTS = (
+    "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
+    "smr_minres_solve", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_rhs_adjoint", "smr_grad_a",
+    "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error",
+)
+PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4}
+
+
+class SmrDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32), ("scheme", ctypes.c_int32),
+        ("precond", ctypes.c_int32), ("pprec", ctypes.c_int32), ("cheb_k", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("T", ctypes.c_double), ("theta", ctypes.c_double),
+        ("ax_host", ctypes.c_void_p), ("ay_host", ctypes.c_void_p), ("a_nodal_host", ctypes.c_void_p),
+    ]
+
+
+class SmrInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("relres_true", ctypes.c_double), ("relres_prec", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "status": STATUS_NAMES.get(self.status, self.status),
+                "relres_true": self.relres_true, "relres_prec": self.relres_prec}
+
+
+class SmrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsmr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2201_10062_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.smr_workspace_size.argtypes = [ctypes.POINTER(SmrDesc), ctypes.POINTER(ctypes.c_size_t)]
+    lib.smr_setup.argtypes = [ctypes.POINTER(SmrDesc), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.smr_destroy.argtypes = [P]
+    lib.smr_build_rhs.argtypes = [P, P, P, P, P]
+    lib.smr_apply_A.argtypes = [P, P, P, P]
+    lib.smr_apply_P_inv.argtypes = [P, P, P, P]
+    lib.smr_minres_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
+    lib.smr_minres_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
+                                             ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32,
+                                             ctypes.POINTER(SmrInfo), P]
+    lib.smr_solve_adjoint.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
+    lib.smr_rhs_adjoint.argtypes = [P, P, P, P, P]
+    lib.smr_grad_a.argtypes = [P, P, P, P, P, P, P, P]
+    lib.smr_profile_enable.argtypes = [ctypes.c_int32]
+    lib.smr_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.smr_version.restype = ctypes.c_char_p
+    lib.smr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("smr_version", "smr_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != SMR_OK:
+        raise SmrError(st, load().smr_last_error().decode())
+
+
+def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
+              ax=None, ay=None, a_nodal=None):
+    """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays."""
+    keep = []
+
+    def host(a):
+        if a is None:
+            return None
+        arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        keep.append(arr)
+        return arr.ctypes.data
+
+    d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
+                cheb_k=cheb_k, reserved=0, T=T, theta=theta,
+                ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal))
+    return d, keep
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing old records) or stop event timing of every kernel launch."""
+    _check(load().smr_profile_enable(1 if on else 0))
+
+
+def profile_read(cls: str):
+    """(launches, total_ms) recorded for one kernel class since profile_enable(True)."""
+    n = ctypes.c_int32(0)
+    ms = ctypes.c_double(0.0)
+    _check(load().smr_profile_read(PROFILE_CLASSES[cls], ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def workspace_size(**kw) -> int:
+    d, _keep = make_desc(**kw)
+    out = ctypes.c_size_t(0)
+    _check(load().smr_workspace_size(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A solver plan on the current device; owns its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
+                 precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
+                 device="cuda"):
+        import torch
+        self.lib = load()
+        self.dim, self.N, self.n = dim, N, n
+        self.m = N ** dim
+        self.scheme, self.theta, self.T = scheme, float(theta), float(T)
+        self.precond, self.pprec = precond, pprec
+        self.device = torch.device(device)
+        d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal)
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + self.ws_bytes]
+        h = ctypes.c_void_p(0)
+        _check(self.lib.smr_setup(ctypes.byref(d), ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                  _stream(), ctypes.byref(h)))
+        self.handle = h
+        del keep
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.smr_destroy(h)
+            self.handle = None
+
+    # --- helpers
+    def _vec(self, t, n_levels=None):
+        import torch
+        n_levels = self.n if n_levels is None else n_levels
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.ws.device or t.numel() != n_levels * self.m:
+            raise ValueError(f"expected a contiguous float64 tensor of {n_levels * self.m} elements on {self.ws.device}")
+        return t
+
+    def empty(self, levels=None):
+        import torch
+        return torch.empty((self.n if levels is None else levels) * self.m, dtype=torch.float64, device=self.ws.device)
+
+    # --- entry points
+    def build_rhs(self, f, u0=None, out=None):
+        self._vec(f, self.n + 1)
+        b = self.empty() if out is None else self._vec(out)
+        _check(self.lib.smr_build_rhs(self.handle, _ptr(f), _ptr(u0), _ptr(b), _stream()))
+        return b
+
+    def apply_A(self, x, out=None):
+        self._vec(x)
+        y = self.empty() if out is None else self._vec(out)
+        _check(self.lib.smr_apply_A(self.handle, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def apply_P_inv(self, v, out=None):
+        self._vec(v)
+        z = self.empty() if out is None else self._vec(out)
+        _check(self.lib.smr_apply_P_inv(self.handle, _ptr(v), _ptr(z), _stream()))
+        return z
+
+    def solve(self, b, x0=None, rtol=1e-8, maxit=500, raise_on_fail=True):
+        """MINRES on Y T x = Y b; returns (x, info dict)."""
+        self._vec(b)
+        x = self.empty().zero_() if x0 is None else self._vec(x0.clone())
+        info = SmrInfo()
+        st = self.lib.smr_minres_solve(self.handle, _ptr(b), _ptr(x), float(rtol), int(maxit),
+                                       ctypes.byref(info), _stream())
+        if st != SMR_OK and raise_on_fail and st != SMR_ENOTCONV:
+            _check(st)
+        return x, info.as_dict()
+
+    def solve_adjoint(self, g, rtol=1e-8, maxit=500):
+        self._vec(g)
+        lam = self.empty()
+        info = SmrInfo()
+        st = self.lib.smr_solve_adjoint(self.handle, _ptr(g), _ptr(lam), float(rtol), int(maxit),
+                                        ctypes.byref(info), _stream())
+        if st not in (SMR_OK, SMR_ENOTCONV):
+            _check(st)
+        return lam, info.as_dict()
+
+    def rhs_adjoint(self, lam, want_u0=True):
+        self._vec(lam)
+        gf = self.empty(self.n + 1)
+        gu0 = self.empty(1) if want_u0 else None
+        _check(self.lib.smr_rhs_adjoint(self.handle, _ptr(lam), _ptr(gf), _ptr(gu0), _stream()))
+        return gf, gu0
+
+    def grad_a(self, u, lam, u0=None):
+        import torch
+        self._vec(u)
+        self._vec(lam)
+        N, dim = self.N, self.dim
+        dev = self.ws.device
+        gax = torch.empty(N + 1 if dim == 1 else N * (N + 1), dtype=torch.float64, device=dev)
+        gay = None if dim == 1 else torch.empty((N + 1) * N, dtype=torch.float64, device=dev)
+        gn = torch.empty((N + 2) ** dim, dtype=torch.float64, device=dev)
+        _check(self.lib.smr_grad_a(self.handle, _ptr(u), _ptr(u0), _ptr(lam), _ptr(gax), _ptr(gay), _ptr(gn),
+                                   _stream()))
+        return gax, gay, gn
+
+
+def solve_batched(plans: Sequence[Plan], bs, rtol=1e-8, maxit=500):
+    """Solve every (plan, b) pair; returns (xs, infos)."""
+    n = len(plans)
+    xs = [p.empty().zero_() for p in plans]
+    for p, b in zip(plans, bs):
+        p._vec(b)
+    P = ctypes.c_void_p
+    hp = (P * n)(*[p.handle.value for p in plans])
+    bp = (P * n)(*[b.data_ptr() for b in bs])
+    xp = (P * n)(*[x.data_ptr() for x in xs])
+    infos = (SmrInfo * n)()
+    st = load().smr_minres_solve_batched(n, hp, bp, xp, float(rtol), int(maxit), infos, _stream())
+    if st not in (SMR_OK, SMR_ENOTCONV):
+        _check(st)
+    return xs, [i.as_dict() for i in infos]

@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/smr.h declares, and rejects bad descriptors on the host before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2201_10062_amd as pkg
+from paper_2201_10062_amd import smr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "smr.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:smr_status|const char \*)\s*(smr_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(smr.EXPORTS) == _header_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", smr.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (smr_\w+)", out))
+    for name in _header_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+    assert lib.smr_version().startswith(b"smr")
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=3, N=7, n=4), smr.SMR_EINVAL),
+    (dict(dim=2, N=6, n=4), smr.SMR_EINVAL),           # N + 1 not a power of two
+    (dict(dim=2, N=1023, n=4), smr.SMR_EINVAL),        # N too large
+    (dict(dim=2, N=7, n=0), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=1, scheme="bdf2"), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=4, theta=1.5), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=4, T=-1.0), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=4, precond="PTHETA_CHEB", cheb_k=0), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=4, precond="PTHETA_CHEB", scheme="bdf2"), smr.SMR_EINVAL),
+])
+def test_invalid_descriptors_rejected_on_host(kw, status):
+    with pytest.raises(smr.SmrError) as ei:
+        smr.workspace_size(**kw)
+    assert ei.value.status == status
+
+
+def test_setup_rejects_bad_workspace_before_device_work():
+    lib = pkg.load()
+    d, keep = smr.make_desc(2, 7, 4)
+    h = ctypes.c_void_p(0)
+    st = lib.smr_setup(ctypes.byref(d), None, 0, None, ctypes.byref(h))
+    assert st == smr.SMR_EWORKSPACE
+    st = lib.smr_setup(ctypes.byref(d), ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert st == smr.SMR_EWORKSPACE and b"too small" in lib.smr_last_error()
+    st = lib.smr_setup(ctypes.byref(d), ctypes.c_void_p(8), 1 << 30, None, ctypes.byref(h))
+    assert st == smr.SMR_EWORKSPACE and b"aligned" in lib.smr_last_error()
+
+
+def test_null_plan_rejected():
+    lib = pkg.load()
+    assert lib.smr_apply_A(None, None, None, None) == smr.SMR_EINVAL
+    assert lib.smr_minres_solve(None, None, None, 1e-8, 10, None, None) == smr.SMR_EINVAL
+
+
+def test_workspace_size_grows_with_problem():
+    a = smr.workspace_size(dim=2, N=31, n=64)
+    b = smr.workspace_size(dim=2, N=127, n=256)
+    assert b > 16 * a * 0.9
+    c = smr.workspace_size(dim=2, N=127, n=256, precond="PTHETA_CHEB")
+    assert c > b
