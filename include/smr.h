@@ -69,6 +69,11 @@ typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
 /* Arithmetic inside P^{-1}.  The matvec, the Lanczos recurrences, the MINRES scalars
  * and the true residual are always float64. */
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
+/* Constant a with P_H / Phat in float64: the solve runs in the spatial sine basis, where
+ * Y T and P^{-1} act per spatial mode (one fused kernel per MINRES iteration, b and x0
+ * transformed on entry, x on exit; same iterates in exact arithmetic).  This flag forces
+ * the general physical-basis iteration instead (stencil matvec and 3D transforms). */
+#define SMR_FLAG_GENERAL_PATH 1
 
 typedef struct {
   int32_t dim;             /* spatial dimension, 1 or 2                                   */
@@ -78,7 +83,8 @@ typedef struct {
   int32_t precond;         /* smr_precond                                                 */
   int32_t pprec;           /* smr_pprec                                                   */
   int32_t cheb_k;          /* Chebyshev steps per mode (SMR_P_THETA_CHEB), 1..16          */
-  int32_t reserved;        /* must be 0                                                   */
+  int32_t flags;           /* bit 0 (SMR_FLAG_GENERAL_PATH): iterate in the physical basis
+                            * even when a is constant; other bits must be 0              */
   double T;                /* final time (> 0)                                            */
   double theta;            /* theta-method parameter (SMR_THETA)                          */
   /* Coefficient a (host pointers, copied during smr_setup).  Give at most one form:
@@ -167,7 +173,9 @@ smr_status smr_grad_a(const smr_plan *plan, const double *d_u, const double *d_u
 /* Tracing: per-kernel timing with HIP events recorded on the launch stream immediately
  * before and after every launch of a kernel class while enabled.  Classes:
  * 0 = time-axis sine transform (MFMA), 1 = spatial sine transform, 2 = space-time
- * stencil (matvec / residual), 3 = vector updates and dots, 4 = MINRES scalar steps.
+ * stencil (matvec / residual), 3 = vector updates and dots, 4 = MINRES scalar steps,
+ * 5 = fused sine-basis MINRES iteration.  Launches that a solve enqueues past its
+ * convergence (they exit on the device status word) are not recorded.
  * smr_profile_enable(1) clears the records and starts recording, (0) stops it.
  * smr_profile_read synchronises the recorded events and returns the launch count and
  * the summed kernel time (ms) of one class.  Not thread-safe; for diagnostics. */

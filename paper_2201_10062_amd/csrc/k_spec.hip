@@ -1,0 +1,508 @@
+// Fused MINRES iteration in the spatial sine basis (gfx950), for constant coefficients.
+//
+// When a is constant, K = U Lambda U with U the (orthogonal, symmetric) spatial sine
+// transform (Sec. 3.1.1), and both Y T and P_H / Phat are block diagonal over the
+// spatial modes after the change of basis I (x) U:
+//   (Y T)^ : per spatial mode k a flipped time stencil l0_k z_t + l1_k z_{t-1} (+ l2 z_{t-2});
+//   P^-1 ^ : per spatial mode k the time-axis S_n diag(1/sigma_{.,k}) S_n.
+// MINRES is invariant under an orthogonal change of basis, so the iteration runs on the
+// transformed vectors and only b, x0 and the result cross the spatial transform.  One
+// kernel does a whole iteration for a tile of C spatial modes (all n time levels):
+//   A. q = (Y T)^ zt_j, v_{j+1} = q - va v_j - vb v_{j-1} (stored), butterflied into LDS;
+//      lagged search direction w_{j-1} and x_{j-1} (its coefficients need gamma_j, which
+//      the previous launch produced);
+//   B. true residual of x_{j-1}: ||Y b - (Y T)^ x||^2 partial;
+//   C. z_{j+1} = S diag(1/sigma) S v_{j+1} on the FP64 matrix cores (two folded GEMMs),
+//      gamma_{j+1}^2 = <v, z> by Parseval between them;
+//   D. z_{j+1} stored, <(Y T)^ z_{j+1}, z_{j+1}> partial (gives delta_{j+1});
+//   E. block partials -> the last block to finish reduces them in a fixed order and runs
+//      the MINRES scalar recurrence (Givens rotation, convergence test).
+// The iterate x_{j-1} and its residual are final one launch after v_j, z_j: the stop test
+// is the same (first iteration whose true residual is <= rtol), one launch later.
+#include "smr_internal.h"
+
+namespace smr {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kThreads = 512;         // 8 waves
+constexpr int kWaves = kThreads / 64;
+
+struct SpecP {
+  int n, m, h1, h2, scheme;
+  double theta;
+  const double *So, *SoT, *Se, *SeT, *tcoef, *tmu;
+  // vectors (spatial-sine basis)
+  const double *zprev;   // z_{j-1}
+  const double *zcur;    // z_j (INIT: unused)
+  double *znext;         // z_{j+1} (INIT: z_1)
+  const double *vcur;    // v_j
+  double *vold;          // in v_{j-1}, out v_{j+1} (INIT: out v_1)
+  const double *wa;      // w_{j-2}
+  double *wb;            // in w_{j-3}, out w_{j-1}
+  double *x;             // x (INIT: x0, read only)
+  const double *bh;      // transformed right-hand side b^ (unpermuted)
+  double *part;          // 4 partial sums per block
+  int *counter;          // last-block ticket
+  Scal *sc;
+};
+
+enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2 };
+
+// per-column stencil coefficients of (T y)_t = l0 y_t + l1 y_{t-1} + l2 y_{t-2}
+struct Coef {
+  double l0, l1, l2;
+};
+__device__ __forceinline__ Coef coef_of(const SpecP &P, double tm) {
+  if (P.scheme == SMR_THETA) return Coef{1.0 + P.theta * tm, -1.0 + (1.0 - P.theta) * tm, 0.0};
+  return Coef{1.5 + tm, -2.0, 0.5};
+}
+
+// (T y)_t for one column of a row-major (n, m) array
+__device__ __forceinline__ double Tt(const double *__restrict__ y, int t, int m, int col, const Coef &k) {
+  double r = k.l0 * y[(size_t)t * m + col];
+  if (t >= 1) r += k.l1 * y[(size_t)(t - 1) * m + col];
+  if (t >= 2 && k.l2 != 0.0) r += k.l2 * y[(size_t)(t - 2) * m + col];
+  return r;
+}
+
+// 1/|re + i im| from a float reciprocal square root refined by two Newton steps in float64
+// (relative error ~1e-16, well inside the 1e-12 parity bound of the preconditioner).
+__device__ __forceinline__ double rsqrt64(double q) {
+  double r = (double)__frsqrt_rn((float)q);
+  r = r * (1.5 - 0.5 * q * r * r);
+  r = r * (1.5 - 0.5 * q * r * r);
+  return r;
+}
+
+__device__ __forceinline__ double inv_sigma(const SpecP &P, int tmode, double t) {
+  const double *c = P.tcoef + 4 * tmode;
+  const double re = c[0] + t * c[1];
+  const double im = c[2] + t * c[3];
+  return rsqrt64(re * re + im * im);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ double ld_agent(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// MINRES scalar recurrence for one launch (thread 0 of the last block).
+template <int MODE>
+__device__ void scalar_update(Scal *sc, double s0, double s1, double s2, double s3) {
+  if (MODE == MODE_INIT) {
+    // s0 = ||v_1||^2, s1 = ||b||^2, s2 = gamma_1^2, s3 = <T^ z_1, z_1>
+    sc->bnorm = sqrt(s1);
+    sc->iter = 0;
+    sc->exact = 0;
+    sc->status = RUNNING;
+    if (s1 == 0.0) { sc->relres = 0.0; sc->status = DONE_CONV; return; }
+    sc->relres = sqrt(s0) / sc->bnorm;
+    if (sc->relres <= sc->rtol) { sc->status = DONE_CONV; return; }
+    if (!(s2 > 0.0) || !isfinite(s2)) { sc->status = DONE_NOTSPD; return; }
+    if (sc->maxit <= 0) { sc->status = DONE_MAXIT; return; }
+    const double g = sqrt(s2);
+    sc->gamma = g; sc->gamma1 = g; sc->gamma_old = 1.0;
+    sc->eta = g; sc->c = sc->c_old = 1.0; sc->s = sc->s_old = 0.0;
+    sc->delta = s3 / s2;
+    sc->zs = 1.0 / g;
+    sc->va = sc->delta / g;
+    sc->vb = 0.0;
+    return;
+  }
+  // s0 = ||r(x_{j-1})||^2 (STEADY), s2 = gamma_{j+1}^2, s3 = <T^ z_{j+1}, z_{j+1}>
+  sc->iter += 1;                                  // launches since INIT = j
+  if (MODE == MODE_STEADY) {
+    sc->relres = sqrt(s0) / sc->bnorm;            // of x_{j-1}
+    if (sc->relres <= sc->rtol || sc->exact) { sc->iter -= 1; sc->status = DONE_CONV; return; }
+    if (sc->iter - 1 >= sc->maxit) { sc->iter -= 1; sc->status = DONE_MAXIT; return; }
+  }
+  if (s2 < 0.0 || !isfinite(s2)) { sc->iter -= 1; sc->status = DONE_NOTSPD; return; }
+  const double gn = sqrt(s2);
+  const double g = sc->gamma, dl = sc->delta;
+  const double a0 = sc->c * dl - sc->c_old * sc->s * g;
+  const double a1 = sqrt(a0 * a0 + gn * gn);
+  const double a2 = sc->s * dl + sc->c_old * sc->c * g;
+  const double a3 = sc->s_old * g;
+  if (a1 == 0.0) { sc->iter -= 1; sc->status = DONE_BREAKDOWN; return; }
+  sc->c_old = sc->c; sc->c = a0 / a1;
+  sc->s_old = sc->s; sc->s = gn / a1;
+  sc->a1 = a1; sc->a2 = a2; sc->a3 = a3;
+  sc->ceta = sc->c * sc->eta;
+  sc->eta = -sc->s * sc->eta;
+  sc->gamma_new = sc->zs;                         // 1/gamma_j for the lagged w_j (next launch)
+  sc->gamma_old = g;
+  sc->gamma = gn;
+  if (gn == 0.0) {                                // Krylov space exhausted: x_j is exact
+    sc->exact = 1;
+    sc->delta = 0.0; sc->va = 0.0; sc->vb = 0.0; sc->zs = 0.0;
+  } else {
+    sc->delta = s3 / s2;
+    sc->va = sc->delta / gn;
+    sc->vb = gn / g;
+    sc->zs = 1.0 / gn;
+  }
+}
+
+// GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
+// CT column tiles, ao[i][ct] += A_o[r] * U[:, ct] and ae[i][ct] += A_e[r] * D[:, ct] over the
+// k dimension.  One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps
+// 2q and 2q+1 side by side per lane, so each 16-byte load fetches two k-steps; loads run
+// two such pairs (four k-steps) ahead of the matrix cores.
+template <int HP, int C>
+__device__ __forceinline__ void gemm_tiles(const double *__restrict__ Ao, const double *__restrict__ Ae,
+                                           const double *U, const double *D, int wave, int lane,
+                                           d4 (&ao)[(HP / 16 + 3) / 4][C / 16], d4 (&ae)[(HP / 16 + 3) / 4][C / 16]) {
+  constexpr int LD = C + 1;
+  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
+  constexpr int KS = HP / 4, KP = KS / 2;         // k-steps, k-step pairs
+  const int bk = lane >> 4, bj = lane & 15;
+  const double2 *__restrict__ Ao2 = reinterpret_cast<const double2 *>(Ao);
+  const double2 *__restrict__ Ae2 = reinterpret_cast<const double2 *>(Ae);
+  double2 q0u[RPW], q0d[RPW], q1u[RPW], q1d[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + 4 * i;
+    const size_t base = (size_t)r * KP * 64 + lane;
+    const bool ok = r < RT;
+    q0u[i] = ok ? Ao2[base] : make_double2(0.0, 0.0);
+    q0d[i] = ok ? Ae2[base] : make_double2(0.0, 0.0);
+    q1u[i] = (ok && KP > 1) ? Ao2[base + 64] : make_double2(0.0, 0.0);
+    q1d[i] = (ok && KP > 1) ? Ae2[base + 64] : make_double2(0.0, 0.0);
+  }
+  for (int kp = 0; kp < KP; ++kp) {
+    double2 q2u[RPW], q2d[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wave + 4 * i;
+      const bool more = r < RT && kp + 2 < KP;
+      const size_t at = ((size_t)r * KP + kp + 2) * 64 + lane;
+      q2u[i] = more ? Ao2[at] : make_double2(0.0, 0.0);
+      q2d[i] = more ? Ae2[at] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = 2 * kp + h;
+      double bu[CT], bd[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        bu[ct] = U[(4 * kk + bk) * LD + 16 * ct + bj];
+        bd[ct] = D[(4 * kk + bk) * LD + 16 * ct + bj];
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        if (wave + 4 * i < RT) {
+          const double au = h ? q0u[i].y : q0u[i].x;
+          const double ad = h ? q0d[i].y : q0d[i].x;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            ao[i][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu[ct], ao[i][ct], 0, 0, 0);
+            ae[i][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd[ct], ae[i][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      q0u[i] = q1u[i]; q0d[i] = q1d[i];
+      q1u[i] = q2u[i]; q1d[i] = q2d[i];
+    }
+  }
+}
+
+template <int HP, int C, int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8))) void k_spec(SpecP P) {
+  Scal *sc = P.sc;
+  if (MODE != MODE_INIT && sc->status != RUNNING) return;
+  constexpr int LD = C + 1;
+  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
+  constexpr int G = kThreads / C;          // row groups when all 8 waves stream
+  constexpr int G2 = (kThreads / 2) / C;   // row groups of the 4 streaming waves
+  extern __shared__ double lds[];
+  double *U = lds;                         // [HP][LD]
+  double *D = lds + HP * LD;               // [HP][LD]
+  __shared__ double red[kWaves];
+  __shared__ int is_last;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = P.n, m = P.m, h1 = P.h1, h2 = P.h2;
+  const int col0 = blockIdx.x * C;
+  const double va = sc->va, vb = sc->vb, zs = sc->zs;
+  const double a1 = sc->a1, a2 = sc->a2, a3 = sc->a3, ceta = sc->ceta, zsl = sc->gamma_new;
+  const double *__restrict__ zcur = P.zcur;
+  const double *__restrict__ zprev = P.zprev;
+  const double *__restrict__ vcur = P.vcur;
+  const double *__restrict__ wa = P.wa;
+  const double *__restrict__ bh = P.bh;
+  double *__restrict__ vold = P.vold;
+  double *__restrict__ wb = P.wb;
+  double *__restrict__ xv = P.x;
+  double *__restrict__ znext = P.znext;
+
+  double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
+
+  // ---- A. v_{j+1}[o] (or v_1), o = n-1-t, streamed over time levels t in ascending order
+  //        so that the stencil's previous level is a register carry.  LDS mirror layout:
+  //        U[o] for o < h1, D[t] for o >= h1 (so that U[p] pairs with D[p] = row n-1-p).
+  {
+    const int c = tid % C, g = tid / C;
+    const int col = col0 + c;
+    const bool ok = col < m;
+    const int cc = ok ? col : m - 1;                 // clamped column for loads
+    const Coef k = coef_of(P, P.tmu[cc]);
+    const int R = (n + G - 1) / G;
+    const int t0 = g * R, t1 = min(n, t0 + R);
+    const double *__restrict__ src = (MODE == MODE_INIT) ? xv : zcur;
+    double y1 = t0 >= 1 ? src[(size_t)(t0 - 1) * m + cc] : 0.0;
+    double y2 = t0 >= 2 ? src[(size_t)(t0 - 2) * m + cc] : 0.0;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) {
+      const int o = n - 1 - t;
+      const size_t it = (size_t)t * m + cc, io = (size_t)o * m + cc;
+      const double y0 = src[it];
+      const double ty = k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
+      double v;
+      if (MODE == MODE_INIT) {
+        const double bt = bh[it];
+        v = bt - ty;                                 // (Y b)_o - ((Y T)^ x0)_o
+        if (ok) { acc_r += v * v; acc_b += bt * bt; }
+      } else {
+        v = zs * ty - va * vcur[io] - vb * vold[io];
+      }
+      if (ok) vold[io] = v;
+      if (o < h1) U[o * LD + c] = ok ? v : 0.0;
+      else D[t * LD + c] = ok ? v : 0.0;
+      y2 = y1;
+      y1 = y0;
+    }
+    // padding rows
+    for (int e = tid; e < (HP - h1) * C; e += kThreads) U[(h1 + e / C) * LD + e % C] = 0.0;
+    for (int e = tid; e < (HP - h2) * C; e += kThreads) D[(h2 + e / C) * LD + e % C] = 0.0;
+  }
+  __syncthreads();
+  // butterfly in place: (U[p], D[p]) <- (v_p + v_{n-1-p}, v_p - v_{n-1-p}); odd n: middle has d = 0
+  for (int e = tid; e < h1 * C; e += kThreads) {
+    const int pp = e / C, c = e % C;
+    const double a = U[pp * LD + c];
+    const double b = pp < h2 ? D[pp * LD + c] : 0.0;
+    U[pp * LD + c] = pp < h2 ? a + b : a;
+    if (pp < h2) D[pp * LD + c] = a - b;
+  }
+  __syncthreads();
+
+  d4 ao[RPW][CT], ae[RPW][CT];
+  if (wave < 4) {
+    // ---- C. the matrix-core waves: z = S_o^T D_o S_o u | S_e^T D_e S_e d
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = d4{0, 0, 0, 0}; ae[i][ct] = d4{0, 0, 0, 0}; }
+    gemm_tiles<HP, C>(P.So, P.Se, U, D, wave, lane, ao, ae);
+  } else if (MODE == MODE_STEADY) {
+    // ---- B. the streaming waves, part 1 of 2: lagged w_{j-1}, x_{j-1} and its true residual
+    //        over time levels t (x carried for the stencil); first half of the levels.
+    const int st = tid - kThreads / 2;
+    const int c = st % C, g = st / C;
+    const int col = col0 + c;
+    const bool ok = col < m;
+    const int cc = ok ? col : m - 1;
+    const Coef k = coef_of(P, P.tmu[cc]);
+    const int R = (n + G2 - 1) / G2;
+    const int t0 = g * R, t1 = min(n, t0 + R);
+    auto xnew = [&](int t) {
+      const size_t i = (size_t)t * m + cc;
+      return xv[i] + ceta * ((zsl * zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1);
+    };
+    double x1 = t0 >= 1 ? xnew(t0 - 1) : 0.0;
+    double x2 = t0 >= 2 ? xnew(t0 - 2) : 0.0;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) {
+      const size_t i = (size_t)t * m + cc;
+      const double w = (zsl * zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1;
+      const double x0 = xv[i] + ceta * w;
+      const double r = bh[i] - (k.l0 * x0 + k.l1 * x1 + k.l2 * x2);
+      if (ok) {
+        wb[i] = w;
+        xv[i] = x0;
+        acc_r += r * r;
+      }
+      x2 = x1;
+      x1 = x0;
+    }
+  }
+  __syncthreads();   // matrix-core waves are done reading U, D
+  if (wave < 4) {
+    // scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
+    const int bk = lane >> 4, bj = lane & 15;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wave + 4 * i;
+      if (r >= RT) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int cl = 16 * ct + bj, col = col0 + cl;
+        const double tm = P.tmu[col < m ? col : m - 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pp = 16 * r + 4 * q + bk;
+          double so = 0.0, se = 0.0;
+          if (col < m && pp < h1) {
+            so = ao[i][ct][q] * inv_sigma(P, 2 * pp, tm);
+            acc_g += ao[i][ct][q] * so;
+          }
+          if (col < m && pp < h2) {
+            se = ae[i][ct][q] * inv_sigma(P, 2 * pp + 1, tm);
+            acc_g += ae[i][ct][q] * se;
+          }
+          U[pp * LD + cl] = so;
+          D[pp * LD + cl] = se;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave < 4) {
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = d4{0, 0, 0, 0}; ae[i][ct] = d4{0, 0, 0, 0}; }
+    gemm_tiles<HP, C>(P.SoT, P.SeT, U, D, wave, lane, ao, ae);
+  }
+  __syncthreads();   // U, D free again
+  if (wave < 4) {
+    // z_p = u'_p + d'_p -> U[p]; z_{n-1-p} = u'_p - d'_p -> D[p]; odd n: middle z_p = u'_p
+    const int bk = lane >> 4, bj = lane & 15;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wave + 4 * i;
+      if (r >= RT) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int cl = 16 * ct + bj;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pp = 16 * r + 4 * q + bk;
+          if (pp < h2) {
+            U[pp * LD + cl] = ao[i][ct][q] + ae[i][ct][q];
+            D[pp * LD + cl] = ao[i][ct][q] - ae[i][ct][q];
+          } else if (pp < h1) {
+            U[pp * LD + cl] = ao[i][ct][q];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- D. store z_{j+1} and accumulate <(Y T)^ z, z> = sum_t (T z)_t z_{n-1-t}
+  {
+    const int c = tid % C, g = tid / C;
+    const int col = col0 + c;
+    const bool ok = col < m;
+    const Coef k = coef_of(P, P.tmu[ok ? col : m - 1]);
+    const int R = (n + G - 1) / G;
+    const int t0 = g * R, t1 = min(n, t0 + R);
+    auto zrow = [&](int t) { return t < h1 ? U[t * LD + c] : D[(n - 1 - t) * LD + c]; };
+    double y1 = t0 >= 1 ? zrow(t0 - 1) : 0.0;
+    double y2 = t0 >= 2 ? zrow(t0 - 2) : 0.0;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) {
+      const double y0 = zrow(t);
+      if (ok) {
+        znext[(size_t)t * m + col] = y0;
+        acc_d += (k.l0 * y0 + k.l1 * y1 + k.l2 * y2) * zrow(n - 1 - t);
+      }
+      y2 = y1;
+      y1 = y0;
+    }
+  }
+
+  // ---- E. block partials, last block reduces in a fixed order and steps the scalars
+  const double s0 = block_sum(acc_r, red);
+  const double s1 = block_sum(acc_b, red);
+  const double s2 = block_sum(acc_g, red);
+  const double s3 = block_sum(acc_d, red);
+  if (tid == 0) {
+    double *pp = P.part + 4 * (size_t)blockIdx.x;
+    pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3;
+    __threadfence();
+    const int ticket = atomicAdd(P.counter, 1);
+    is_last = (ticket == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += kThreads) {
+    const double *pp = P.part + 4 * (size_t)b;
+    t0 += ld_agent(pp + 0);
+    t1 += ld_agent(pp + 1);
+    t2 += ld_agent(pp + 2);
+    t3 += ld_agent(pp + 3);
+  }
+  t0 = block_sum(t0, red);
+  t1 = block_sum(t1, red);
+  t2 = block_sum(t2, red);
+  t3 = block_sum(t3, red);
+  if (tid == 0) {
+    scalar_update<MODE>(sc, t0, t1, t2, t3);
+    *P.counter = 0;
+  }
+}
+
+template <int HP, int C>
+hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks) {
+  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(double);
+  if (shmem > 65536) {
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  }
+  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  else hipLaunchKernelGGL((k_spec<HP, C, 2>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int spec_cols(const Plan *p) { return p->hp >= 256 ? 16 : 32; }
+
+int spec_blocks(const Plan *p) {
+  const int C = spec_cols(p);
+  return (p->m + C - 1) / C;
+}
+
+hipError_t launch_spec(Ctx c, int mode, const double *zprev, const double *zcur, double *znext, const double *vcur,
+                       double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter) {
+  const Plan *p = c.p;
+  SpecP P{};
+  P.n = p->n; P.m = p->m; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
+  P.So = p->So; P.SoT = p->SoT; P.Se = p->Se; P.SeT = p->SeT; P.tcoef = p->tcoef; P.tmu = p->tmu;
+  P.zprev = zprev; P.zcur = zcur; P.znext = znext; P.vcur = vcur; P.vold = vold; P.wa = wa; P.wb = wb;
+  P.x = x; P.bh = bh; P.part = p->part; P.counter = counter; P.sc = p->sc;
+  const int blocks = spec_blocks(p);
+  switch (p->hp) {
+    case 16: return run_spec<16, 32>(c.st, P, mode, blocks);
+    case 32: return run_spec<32, 32>(c.st, P, mode, blocks);
+    case 64: return run_spec<64, 32>(c.st, P, mode, blocks);
+    case 128: return run_spec<128, 32>(c.st, P, mode, blocks);
+    case 256: return run_spec<256, 16>(c.st, P, mode, blocks);
+    case 512: return run_spec<512, 16>(c.st, P, mode, blocks);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace smr

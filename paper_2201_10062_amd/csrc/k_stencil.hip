@@ -293,6 +293,10 @@ __global__ __launch_bounds__(256) void k_dot(size_t len, const double *__restric
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+__global__ __launch_bounds__(64) void k_zero_int(int count, int *__restrict__ x) {
+  for (int e = threadIdx.x; e < count; e += blockDim.x) x[e] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_scale_copy(int n, int m, const double *__restrict__ in,
                                                     double *__restrict__ out, double s, int flip) {
   const size_t len = (size_t)n * m;
@@ -489,6 +493,11 @@ hipError_t launch_scale_copy(Ctx c, const double *in, double *out, double s, int
 
 hipError_t launch_zero(Ctx c, double *x, size_t len) {
   hipLaunchKernelGGL(k_zero, dim3(grid_for(len, 1024)), dim3(256), 0, c.st, len, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_int(Ctx c, int *x, int count) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c.st, count, x);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct TimeP {
   int n, m, h1, h2;
-  const double *So, *SoT, *Se, *SeT;   // fragment order: [(r * HP/4 + kk) * 64 + lane]
+  const double *So, *SoT, *Se, *SeT;   // fragment order: [((r * HP/8 + kk/2) * 64 + lane) * 2 + kk%2]
   const double *tcoef;                 // 4 per time mode: sigma = |(A + t B) + i (C + t D)|
   const double *tmu;                   // per column: t = tau * mu
 };
@@ -33,6 +33,10 @@ __device__ __forceinline__ double inv_sigma(const TimeP &tp, int tmode, double t
   const double re = c[0] + t * c[1];
   const double im = c[2] + t * c[3];
   return 1.0 / sqrt(re * re + im * im);
+}
+
+__device__ __forceinline__ size_t frag_at(int r, int ks, int kk, int lane) {
+  return (((size_t)r * (ks / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
 }
 
 __device__ __forceinline__ double block_sum256(double v, double *red) {
@@ -99,8 +103,8 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
         const int r = tile / CT, ct = tile - r * CT;
         const double bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
         const double bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double au = tp.So[((size_t)r * KS + kk) * 64 + lane];
-        const double ad = tp.Se[((size_t)r * KS + kk) * 64 + lane];
+        const double au = tp.So[frag_at(r, KS, kk, lane)];
+        const double ad = tp.Se[frag_at(r, KS, kk, lane)];
         ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu, ao[t], 0, 0, 0);
         ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd, ae[t], 0, 0, 0);
       }
@@ -167,8 +171,8 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
         const int r = tile / CT, ct = tile - r * CT;
         const double bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
         const double bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double au = tp.SoT[((size_t)r * KS + kk) * 64 + lane];
-        const double ad = tp.SeT[((size_t)r * KS + kk) * 64 + lane];
+        const double au = tp.SoT[frag_at(r, KS, kk, lane)];
+        const double ad = tp.SeT[frag_at(r, KS, kk, lane)];
         ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu, ao[t], 0, 0, 0);
         ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd, ae[t], 0, 0, 0);
       }

@@ -42,7 +42,8 @@ smr_status fail(smr_status st, const char *fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------- event profiler
-enum ProfClass { PROF_TIME = 0, PROF_DST = 1, PROF_STENCIL = 2, PROF_VEC = 3, PROF_SCALAR = 4, PROF_NCLASS = 5 };
+enum ProfClass { PROF_TIME = 0, PROF_DST = 1, PROF_STENCIL = 2, PROF_VEC = 3, PROF_SCALAR = 4, PROF_SPEC = 5,
+                 PROF_NCLASS = 6 };
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;                     // free events
@@ -56,6 +57,24 @@ struct Profiler {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
+  }
+  struct Mark {
+    size_t n[PROF_NCLASS];
+  };
+  Mark mark() const {
+    Mark k;
+    for (int i = 0; i < PROF_NCLASS; ++i) k.n[i] = rec[i].size();
+    return k;
+  }
+  // drop the records made after mark k (launches that exited without work)
+  void truncate(const Mark &k) {
+    for (int i = 0; i < PROF_NCLASS; ++i) {
+      while (rec[i].size() > k.n[i]) {
+        pool.push_back(rec[i].back().first);
+        pool.push_back(rec[i].back().second);
+        rec[i].pop_back();
+      }
+    }
   }
   void clear() {
     for (auto &r : rec) {
@@ -130,7 +149,7 @@ smr_status validate(const smr_desc *d) {
   if (d->precond == SMR_P_THETA_CHEB && (d->cheb_k < 1 || d->cheb_k > 16))
     return fail(SMR_EINVAL, "cheb_k must be in [1, 16] (got %d)", d->cheb_k);
   if (d->pprec != SMR_FP64) return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
-  if (d->reserved != 0) return fail(SMR_EINVAL, "reserved field must be 0");
+  if ((d->flags & ~SMR_FLAG_GENERAL_PATH) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
   if (d->ax_host && d->dim == 2 && !d->ay_host) return fail(SMR_EINVAL, "dim 2 face values need ay");
@@ -139,7 +158,7 @@ smr_status validate(const smr_desc *d) {
 }
 
 struct Layout {
-  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, tw, gface, part, sc, vec0;
+  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, tw, gface, part, sc, cnt, vec0;
   int nvec;
   size_t total;
 };
@@ -169,8 +188,9 @@ Layout layout_of(const smr_desc *d) {
   l.SeT = take(sizeof(double) * hp * hp);
   l.tw = take(sizeof(double) * 2 * (size_t)L);
   l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
-  l.part = take(sizeof(double) * 4 * (size_t)kRedSlots);
+  l.part = take(sizeof(double) * 16 * (size_t)kRedSlots);
   l.sc = take(sizeof(Scal));
+  l.cnt = take(sizeof(int) * 64);
   // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve)
   l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0);
   l.vec0 = off;
@@ -257,6 +277,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.precond = d->precond;
   p.pprec = d->pprec;
   p.cheb_k = d->cheb_k;
+  p.flags = d->flags;
   p.T = d->T;
   p.tau = d->T / d->n;
   p.theta = d->scheme == SMR_THETA ? d->theta : 1.0;
@@ -366,7 +387,8 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     for (int kk = 0; kk < KS; ++kk)
       for (int lane = 0; lane < 64; ++lane) {
         const int i = 16 * r + (lane & 15), k = 4 * kk + (lane >> 4);
-        const size_t at = ((size_t)r * KS + kk) * 64 + lane;
+        // fragments of k-steps 2q and 2q+1 adjacent per lane: one 16-byte load fetches both
+        const size_t at = (((size_t)r * (KS / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
         fo[at] = So(i, k);
         foT[at] = So(k, i);
         fe[at] = Se(i, k);
@@ -394,6 +416,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.gface = (double *)(base_ptr + lay.gface);
   p.part = (double *)(base_ptr + lay.part);
   p.sc = (Scal *)(base_ptr + lay.sc);
+  p.counter = (int *)(base_ptr + lay.cnt);
   const size_t vstride = align256(sizeof(double) * p.len);
   double *vec[12] = {};
   for (int i = 0; i < lay.nvec; ++i) vec[i] = (double *)(base_ptr + lay.vec0 + (size_t)i * vstride);
@@ -435,6 +458,10 @@ smr_status smr_destroy(smr_plan *plan) {
 
 namespace smr {
 namespace {
+
+bool use_spectral(const Plan &p) {
+  return p.const_coef && p.precond == SMR_P_H && p.pprec == SMR_FP64 && !(p.flags & SMR_FLAG_GENERAL_PATH);
+}
 
 smr_status check_plan(const smr_plan *pl) {
   if (!pl) return fail(SMR_EINVAL, "plan is NULL");
@@ -493,6 +520,84 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   return SMR_OK;
 }
 
+// spatial sine transform of every time slice (involutory: the same call transforms back)
+smr_status spatial_dst(const Plan &p, hipStream_t s, const double *in, double *out) {
+  Ctx c{&p, s};
+  LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, nullptr));
+  if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, nullptr));
+  return SMR_OK;
+}
+
+smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
+  smr_status res = SMR_OK;
+  switch (h.status) {
+    case DONE_CONV: res = SMR_OK; break;
+    case DONE_NOTSPD: res = fail(SMR_ENOTSPD, "preconditioner not SPD on the residual (gamma^2 <= 0 or not finite)"); break;
+    case DONE_BREAKDOWN: res = fail(SMR_EBREAKDOWN, "MINRES breakdown (alpha1 = 0)"); break;
+    default: res = fail(SMR_ENOTCONV, "maxit = %d reached, relres = %g", maxit, h.relres); break;
+  }
+  if (info) {
+    info->iters = h.iter;
+    info->status = res;
+    info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
+    info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
+  }
+  return res;
+}
+
+// Constant coefficients: the whole MINRES runs in the spatial sine basis with one fused
+// kernel per iteration; b and x0 are transformed on entry, the iterate on exit.
+smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
+                           smr_info *info) {
+  Ctx c{&p, s};
+  double *Bh = p.T1, *Xh = p.T2;
+  double *Zb[3] = {p.Z[0], p.Z[1], p.Q};
+  smr_status st = spatial_dst(p, s, b, Bh);
+  if (st != SMR_OK) return st;
+  st = spatial_dst(p, s, x, Xh);
+  if (st != SMR_OK) return st;
+  Scal h{};
+  h.rtol = rtol;
+  h.maxit = maxit;
+  h.status = RUNNING;
+  HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
+  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+  LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
+  LAUNCH(PROF_SPEC, launch_spec(c, 0, nullptr, nullptr, Zb[0], nullptr, p.V[1], nullptr, nullptr, Xh, Bh, p.counter));
+  const Profiler::Mark m0 = g_prof.mark();
+  int issued = 0;            // launches j = 1..issued enqueued
+  int chunk = 4;
+  const int last = maxit + 1;
+  for (;;) {
+    HIP_TRY(hipMemcpyAsync(&h, p.sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.status != RUNNING || issued >= last) break;
+    const int todo = std::min(chunk, last - issued);
+    for (int it = 0; it < todo; ++it) {
+      const int j = issued + it + 1;
+      LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, Zb[(j + 1) % 3], Zb[(j - 1) % 3], Zb[j % 3], p.V[j % 2],
+                                    p.V[(j + 1) % 2], p.W[j % 2], p.W[(j + 1) % 2], Xh, Bh, p.counter));
+    }
+    issued += todo;
+    chunk = std::min(chunk * 2, 16);
+  }
+  if (g_prof.on) {   // keep the records of the launches that did work (j = 1 .. iter + 1)
+    Profiler::Mark k = m0;
+    k.n[PROF_SPEC] += (size_t)std::min(issued, h.iter + 1);
+    g_prof.truncate(k);
+  }
+  if (h.status == DONE_CONV && h.bnorm == 0.0) {
+    LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
+  } else {
+    st = spatial_dst(p, s, Xh, x);
+    if (st != SMR_OK) return st;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return finish_info(h, maxit, info);
+}
+
 const double *scal_field(const Plan &p, size_t off) { return (const double *)((const char *)p.sc + off); }
 
 // MINRES on (Y T) x = Y b from the initial x; b unpermuted.
@@ -519,12 +624,14 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, doub
   const double *zs = scal_field(p, offsetof(Scal, zs));
   int issued = 0;
   int chunk = 4;
+  std::vector<Profiler::Mark> marks;
   for (;;) {
     HIP_TRY(hipMemcpyAsync(&h, p.sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h.status != RUNNING || issued >= maxit) break;
     const int todo = std::min(chunk, maxit - issued);
     for (int it = 0; it < todo; ++it) {
+      marks.push_back(g_prof.mark());
       double *vj = p.V[cv], *vo = p.V[1 - cv], *zj = p.Z[cz], *zn = p.Z[1 - cz];
       double *w1 = p.W[cw], *w2 = p.W[1 - cw];
       LAUNCH(PROF_STENCIL, launch_apply_YT(c, zj, zs, p.Q, nullptr, part, &nb, gate));
@@ -543,6 +650,7 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, doub
     issued += todo;
     chunk = std::min(chunk * 2, 16);
   }
+  if (g_prof.on && h.iter < (int)marks.size()) g_prof.truncate(marks[h.iter]);
   if (h.status == DONE_CONV && h.bnorm == 0.0) LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
   HIP_TRY(hipStreamSynchronize(s));
   smr_status res = SMR_OK;
@@ -598,6 +706,7 @@ smr_status smr_minres_solve(const smr_plan *pl, const double *b, double *x, doub
   if (st != SMR_OK) return st;
   if (!b || !x) return fail(SMR_EINVAL, "b and x must be non-NULL");
   if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
+  if (use_spectral(pl->p)) return minres_spectral(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
   return minres(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
 }
 
@@ -624,7 +733,7 @@ smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, d
   // (Y T) mu = g  <=>  (Y T) mu = Y (Y g): solve with b' = Y g, then lambda = Y mu
   LAUNCH(PROF_VEC, launch_scale_copy(c, g, p.G, 1.0, 1));
   LAUNCH(PROF_VEC, launch_zero(c, lam, p.len));
-  st = minres(p, s, p.G, lam, rtol, maxit, info);
+  st = use_spectral(p) ? minres_spectral(p, s, p.G, lam, rtol, maxit, info) : minres(p, s, p.G, lam, rtol, maxit, info);
   if (st != SMR_OK && st != SMR_ENOTCONV) return st;
   LAUNCH(PROF_VEC, launch_scale_copy(c, lam, p.G, 1.0, 1));
   HIP_TRY(hipMemcpyAsync(lam, p.G, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -36,7 +36,7 @@ struct Scal {
 // Host-side plan: parameters plus device pointers into the caller's workspace.
 struct Plan {
   // parameters
-  int dim, N, n, m, scheme, precond, pprec, cheb_k;
+  int dim, N, n, m, scheme, precond, pprec, cheb_k, flags;
   size_t len;                 // n*m
   double T, tau, theta, h, h2inv;
   bool const_coef;            // every face value equal
@@ -57,7 +57,8 @@ struct Plan {
   double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *F1, *F2;             // float32 scratch for mixed precision
-  double *part;               // kRedSlots * 4 partial sums
+  double *part;               // 16 * kRedSlots partial sums
+  int *counter;               // last-block ticket of the fused iteration kernel
   Scal *sc;                   // device scalars
   Scal *sc_host;              // pinned host mirror
   size_t ws_bytes;
@@ -103,6 +104,13 @@ hipError_t launch_zero(Ctx c, double *x, size_t len);
 //        1 = delta, 2 = gamma_new + Givens, 3 = true residual / convergence
 hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, const double *part2,
                               int nb2);
+
+// Fused MINRES iteration in the spatial sine basis (constant coefficients, P_H / Phat, FP64).
+// mode 0 = initialise from x0, 1 = first iteration, 2 = steady iteration.
+hipError_t launch_spec(Ctx c, int mode, const double *zprev, const double *zcur, double *znext, const double *vcur,
+                       double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter);
+int spec_blocks(const Plan *p);
+hipError_t launch_zero_int(Ctx c, int *x, int count);
 
 // Chebyshev per-mode solve pieces (P_theta).
 hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, double a_d, double a_t,

@@ -29,14 +29,14 @@ EXPORTS = (
     "smr_minres_solve", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error",
 )
-PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4}
+PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5}
 
 
 class SmrDesc(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("pprec", ctypes.c_int32), ("cheb_k", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("T", ctypes.c_double), ("theta", ctypes.c_double),
+        ("flags", ctypes.c_int32), ("T", ctypes.c_double), ("theta", ctypes.c_double),
         ("ax_host", ctypes.c_void_p), ("ay_host", ctypes.c_void_p), ("a_nodal_host", ctypes.c_void_p),
     ]
 
@@ -97,8 +97,11 @@ def _check(st: int):
         raise SmrError(st, load().smr_last_error().decode())
 
 
+FLAG_GENERAL_PATH = 1
+
+
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
-              ax=None, ay=None, a_nodal=None):
+              ax=None, ay=None, a_nodal=None, general_path=False):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays."""
     keep = []
 
@@ -110,7 +113,7 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
         return arr.ctypes.data
 
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
-                cheb_k=cheb_k, reserved=0, T=T, theta=theta,
+                cheb_k=cheb_k, flags=FLAG_GENERAL_PATH if general_path else 0, T=T, theta=theta,
                 ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal))
     return d, keep
 
@@ -150,7 +153,7 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda"):
+                 device="cuda", general_path: bool = False):
         import torch
         self.lib = load()
         self.dim, self.N, self.n = dim, N, n
@@ -158,7 +161,7 @@ class Plan:
         self.scheme, self.theta, self.T = scheme, float(theta), float(T)
         self.precond, self.pprec = precond, pprec
         self.device = torch.device(device)
-        d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal)
+        d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value

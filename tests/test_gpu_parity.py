@@ -45,10 +45,11 @@ def _faces(kind, N, dim, seed=0):
         if dim == 2 else W.sample_faces(lambda x: 1.0 + 0.5 * np.sin(2 * np.pi * x), N, 1)
 
 
-def _pair(dim, N, n, scheme="theta", theta=1.0, precond="PH", kind="const", cheb_k=3):
+def _pair(dim, N, n, scheme="theta", theta=1.0, precond="PH", kind="const", cheb_k=3, general=False):
     from paper_2201_10062_amd import Plan
     ax, ay = _faces(kind, N, dim)
-    g = Plan(dim, N, n, scheme=scheme, theta=theta, precond=precond, cheb_k=cheb_k, ax=ax, ay=ay)
+    g = Plan(dim, N, n, scheme=scheme, theta=theta, precond=precond, cheb_k=cheb_k, ax=ax, ay=ay,
+             general_path=general)
     o = System(dim, N, n, scheme=scheme, theta=theta, ax=ax, ay=ay,
                precond={"PH": "PH", "PTHETA_CHEB": "PTHETA_CHEB", "NONE": "NONE"}[precond], cheb_k=cheb_k)
     return g, o
@@ -100,15 +101,24 @@ def test_build_rhs_parity():
     assert rel(b, o.rhs(p.f, p.u0)) < 1e-13
 
 
-@pytest.mark.parametrize("dim,N,n,scheme,theta,precond,kind", [
+MINRES_CASES = [
     (1, 63, 64, "theta", 1.0, "PH", "const"),
     (2, 31, 64, "theta", 0.5, "PH", "const"),
     (2, 31, 32, "theta", 1.0, "PH", "smooth"),
     (2, 31, 32, "bdf2", 1.0, "PH", "const"),
     (2, 15, 24, "theta", 1.0, "PTHETA_CHEB", "smooth"),
-])
-def test_minres_iterate_parity(dim, N, n, scheme, theta, precond, kind):
-    g, o = _pair(dim, N, n, scheme, theta, precond=precond, kind=kind)
+    (2, 63, 33, "theta", 0.5, "PH", "const"),
+    (1, 31, 7, "bdf2", 1.0, "PH", "const"),
+    (2, 7, 1, "theta", 1.0, "PH", "const"),
+]
+
+
+@pytest.mark.parametrize("general", [False, True], ids=["fused", "general"])
+@pytest.mark.parametrize("dim,N,n,scheme,theta,precond,kind", MINRES_CASES)
+def test_minres_iterate_parity(dim, N, n, scheme, theta, precond, kind, general):
+    """Constant-coefficient P_H runs on the fused sine-basis kernel unless the general path
+    is forced; both must reproduce the oracle's iteration count and iterate."""
+    g, o = _pair(dim, N, n, scheme, theta, precond=precond, kind=kind, general=general)
     rng = np.random.default_rng(4)
     if scheme == "theta":
         f = rng.standard_normal((n + 1, g.m))
@@ -124,6 +134,7 @@ def test_minres_iterate_parity(dim, N, n, scheme, theta, precond, kind):
     assert rel(x, ref.x) < 1e-10
     assert info["relres_true"] <= 1e-8
     assert abs(info["relres_true"] - ref.relres_true) <= 1e-6 * ref.relres_true + 1e-14
+    assert abs(info["relres_prec"] - ref.relres_prec) <= 1e-6 * ref.relres_prec + 1e-14
 
 
 def test_minres_unpreconditioned_iterates():
@@ -147,18 +158,25 @@ def test_minres_manufactured_1d_full_size():
     assert rel(_n(x), ref.x) < 1e-10
 
 
-def test_minres_warm_start_and_zero_rhs_and_maxit():
-    g, o = _pair(2, 15, 16, "theta", 0.5)
+@pytest.mark.parametrize("general", [False, True], ids=["fused", "general"])
+def test_minres_warm_start_and_zero_rhs_and_maxit(general):
+    g, o = _pair(2, 15, 16, "theta", 0.5, general=general)
     b = np.random.default_rng(5).standard_normal(16 * g.m)
     u = o.solve_direct(b)
     x, info = g.solve(_t(b), x0=_t(u), rtol=1e-8)
     assert info["iters"] == 0 and info["status"] == "ok"
     x, info = g.solve(_t(np.zeros_like(b)), rtol=1e-8)
     assert info["iters"] == 0 and float(np.abs(_n(x)).max()) == 0.0
-    x, info = g.solve(_t(b), rtol=1e-14, maxit=3)
-    assert info["iters"] == 3 and info["status"] == "enotconv"
-    ref = o.solve(b, rtol=1e-300, maxit=3)
-    assert rel(_n(x), ref.x) < 1e-12
+    for k in (1, 3):
+        x, info = g.solve(_t(b), rtol=1e-14, maxit=k)
+        assert info["iters"] == k and info["status"] == "enotconv"
+        ref = o.solve(b, rtol=1e-300, maxit=k)
+        assert rel(_n(x), ref.x) < 1e-12
+    # warm start away from the solution
+    x0 = 0.5 * u
+    ref = o.solve(b, rtol=1e-8, x0=x0)
+    x, info = g.solve(_t(b), x0=_t(x0), rtol=1e-8)
+    assert info["iters"] == ref.iters and rel(_n(x), ref.x) < 1e-10
 
 
 def test_adjoint_and_gradients_parity():
@@ -184,12 +202,13 @@ def test_adjoint_and_gradients_parity():
     assert rel(_n(gn), oadj.grad_nodal(rx, ry, N, 2).reshape(-1)) < 1e-12
 
 
-def test_cn_noisy_full_size_against_direct_solve():
+@pytest.mark.parametrize("general", [False, True], ids=["fused", "general"])
+def test_cn_noisy_full_size_against_direct_solve(general):
     """The 2D Crank-Nicolson workload at its full size (N = 127, n = 256): the GPU
     solution reaches the 1e-8 true residual (checked by the oracle's own matvec) and
     matches the sequential direct solve."""
     p = W.crank_nicolson_2d_noisy()
-    g, o = _pair(2, p.N, p.n, "theta", 0.5)
+    g, o = _pair(2, p.N, p.n, "theta", 0.5, general=general)
     b = o.rhs(p.f, p.u0)
     x, info = g.solve(_t(b), rtol=1e-8)
     x = _n(x)
