@@ -152,6 +152,22 @@ def main() -> int:
         "roofline_mfma": {"achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                           "frac": achieved_tf / PEAK_FP64_TFLOPS, "flops_per_launch": flops_per_launch},
     }
+    # the same workload with the float32 preconditioner (error vs the float64 solution reported)
+    mplan = Plan(2, p.N, p.n, theta=p.theta, pprec="fp32", device=dev)
+    x64, _ = plan.solve(b, rtol=args.rtol)
+    for _ in range(args.warmup):
+        mplan.solve(b, rtol=args.rtol)
+    torch.cuda.synchronize()
+    tm0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.build_rhs(f, u0, out=b)
+        xm, minfo = mplan.solve(b, rtol=args.rtol)
+    torch.cuda.synchronize()
+    tm1 = time.perf_counter()
+    out["mixed_fp32"] = {"time_to_1e-8_ms": (tm1 - tm0) / args.steps * 1e3, "iters_per_solve": minfo["iters"],
+                         "iters_per_s": minfo["iters"] * args.steps / (tm1 - tm0),
+                         "relres_true": minfo["relres_true"],
+                         "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

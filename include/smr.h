@@ -66,8 +66,10 @@ typedef enum {
 
 typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;
 typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
-/* Arithmetic inside P^{-1}.  The matvec, the Lanczos recurrences, the MINRES scalars
- * and the true residual are always float64. */
+/* Arithmetic inside P^{-1} during the solves.  The matvec, the Lanczos recurrences, the
+ * MINRES scalars and the true residual are always float64.  SMR_FP32 (time transform on the
+ * float32 matrix cores, z stored in float32) is available for constant a with P_H / Phat,
+ * i.e. for the sine-basis solve; smr_apply_P_inv always applies P^{-1} in float64. */
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 /* Constant a with P_H / Phat in float64: the solve runs in the spatial sine basis, where
  * Y T and P^{-1} act per spatial mode (one fused kernel per MINRES iteration, b and x0

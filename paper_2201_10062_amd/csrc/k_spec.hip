@@ -21,22 +21,48 @@
 // is the same (first iteration whose true residual is <= rtol), one launch later.
 #include "smr_internal.h"
 
+#include <type_traits>
+
 namespace smr {
 
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 512;         // 8 waves
+
+// Arithmetic of the time transform: PR 0 = float64 (v_mfma_f64_16x16x4f64), PR 1 = float32
+// (v_mfma_f32_16x16x4f32).  Fragment layouts (checked on gfx950): A[i][k] in lane i + 16k and
+// B[k][j] in lane j + 16k for both; accumulator register r of lane l holds D[4r + l/16][l%16]
+// for float64 but D[4(l/16) + r][l%16] for float32.
+template <int PR> struct Prec;
+template <> struct Prec<0> {
+  typedef double T;
+  typedef d4 Acc;
+  static __device__ __forceinline__ Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int bk) { return 4 * q + bk; }
+};
+template <> struct Prec<1> {
+  typedef float T;
+  typedef f4 Acc;
+  static __device__ __forceinline__ Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int bk) { return 4 * bk + q; }
+};
 constexpr int kWaves = kThreads / 64;
 
 struct SpecP {
   int n, m, h1, h2, scheme;
   double theta;
-  const double *So, *SoT, *Se, *SeT, *tcoef, *tmu;
-  // vectors (spatial-sine basis)
-  const double *zprev;   // z_{j-1}
-  const double *zcur;    // z_j (INIT: unused)
-  double *znext;         // z_{j+1} (INIT: z_1)
+  const void *So, *SoT, *Se, *SeT;   // folded sine tables in the transform's precision
+  const double *tcoef, *tmu;
+  // vectors (spatial-sine basis); z in the transform's precision
+  const void *zprev;     // z_{j-1}
+  const void *zcur;      // z_j (INIT: unused)
+  void *znext;           // z_{j+1} (INIT: z_1)
   const double *vcur;    // v_j
   double *vold;          // in v_{j-1}, out v_{j+1} (INIT: out v_1)
   const double *wa;      // w_{j-2}
@@ -158,43 +184,49 @@ __device__ void scalar_update(Scal *sc, double s0, double s1, double s2, double 
 // GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
 // CT column tiles, ao[i][ct] += A_o[r] * U[:, ct] and ae[i][ct] += A_e[r] * D[:, ct] over the
 // k dimension.  One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps
-// 2q and 2q+1 side by side per lane, so each 16-byte load fetches two k-steps; loads run
-// two such pairs (four k-steps) ahead of the matrix cores.
-template <int HP, int C>
-__device__ __forceinline__ void gemm_tiles(const double *__restrict__ Ao, const double *__restrict__ Ae,
-                                           const double *U, const double *D, int wave, int lane,
-                                           d4 (&ao)[(HP / 16 + 3) / 4][C / 16], d4 (&ae)[(HP / 16 + 3) / 4][C / 16]) {
+// 2q and 2q+1 side by side per lane, so one load fetches two k-steps; loads run two such
+// pairs (four k-steps) ahead of the matrix cores.
+template <int HP, int C, int PR>
+__device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ Ao,
+                                           const typename Prec<PR>::T *__restrict__ Ae,
+                                           const typename Prec<PR>::T *U, const typename Prec<PR>::T *D,
+                                           int wave, int lane,
+                                           typename Prec<PR>::Acc (&ao)[(HP / 16 + 3) / 4][C / 16],
+                                           typename Prec<PR>::Acc (&ae)[(HP / 16 + 3) / 4][C / 16]) {
+  typedef typename Prec<PR>::T T;
+  typedef typename std::conditional<PR == 0, double2, float2>::type T2;
   constexpr int LD = C + 1;
   constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
   constexpr int KS = HP / 4, KP = KS / 2;         // k-steps, k-step pairs
   const int bk = lane >> 4, bj = lane & 15;
-  const double2 *__restrict__ Ao2 = reinterpret_cast<const double2 *>(Ao);
-  const double2 *__restrict__ Ae2 = reinterpret_cast<const double2 *>(Ae);
-  double2 q0u[RPW], q0d[RPW], q1u[RPW], q1d[RPW];
+  const T2 *__restrict__ Ao2 = reinterpret_cast<const T2 *>(Ao);
+  const T2 *__restrict__ Ae2 = reinterpret_cast<const T2 *>(Ae);
+  const T2 zero2 = {T(0), T(0)};
+  T2 q0u[RPW], q0d[RPW], q1u[RPW], q1d[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int r = wave + 4 * i;
     const size_t base = (size_t)r * KP * 64 + lane;
     const bool ok = r < RT;
-    q0u[i] = ok ? Ao2[base] : make_double2(0.0, 0.0);
-    q0d[i] = ok ? Ae2[base] : make_double2(0.0, 0.0);
-    q1u[i] = (ok && KP > 1) ? Ao2[base + 64] : make_double2(0.0, 0.0);
-    q1d[i] = (ok && KP > 1) ? Ae2[base + 64] : make_double2(0.0, 0.0);
+    q0u[i] = ok ? Ao2[base] : zero2;
+    q0d[i] = ok ? Ae2[base] : zero2;
+    q1u[i] = (ok && KP > 1) ? Ao2[base + 64] : zero2;
+    q1d[i] = (ok && KP > 1) ? Ae2[base + 64] : zero2;
   }
   for (int kp = 0; kp < KP; ++kp) {
-    double2 q2u[RPW], q2d[RPW];
+    T2 q2u[RPW], q2d[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int r = wave + 4 * i;
       const bool more = r < RT && kp + 2 < KP;
       const size_t at = ((size_t)r * KP + kp + 2) * 64 + lane;
-      q2u[i] = more ? Ao2[at] : make_double2(0.0, 0.0);
-      q2d[i] = more ? Ae2[at] : make_double2(0.0, 0.0);
+      q2u[i] = more ? Ao2[at] : zero2;
+      q2d[i] = more ? Ae2[at] : zero2;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int kk = 2 * kp + h;
-      double bu[CT], bd[CT];
+      T bu[CT], bd[CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         bu[ct] = U[(4 * kk + bk) * LD + 16 * ct + bj];
@@ -203,12 +235,12 @@ __device__ __forceinline__ void gemm_tiles(const double *__restrict__ Ao, const 
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         if (wave + 4 * i < RT) {
-          const double au = h ? q0u[i].y : q0u[i].x;
-          const double ad = h ? q0d[i].y : q0d[i].x;
+          const T au = h ? q0u[i].y : q0u[i].x;
+          const T ad = h ? q0d[i].y : q0d[i].x;
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
-            ao[i][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu[ct], ao[i][ct], 0, 0, 0);
-            ae[i][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd[ct], ae[i][ct], 0, 0, 0);
+            ao[i][ct] = Prec<PR>::mfma(au, bu[ct], ao[i][ct]);
+            ae[i][ct] = Prec<PR>::mfma(ad, bd[ct], ae[i][ct]);
           }
         }
       }
@@ -221,17 +253,19 @@ __device__ __forceinline__ void gemm_tiles(const double *__restrict__ Ao, const 
   }
 }
 
-template <int HP, int C, int MODE>
+template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8))) void k_spec(SpecP P) {
+  typedef typename Prec<PR>::T T;
+  typedef typename Prec<PR>::Acc Acc;
   Scal *sc = P.sc;
   if (MODE != MODE_INIT && sc->status != RUNNING) return;
   constexpr int LD = C + 1;
   constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
   constexpr int G = kThreads / C;          // row groups when all 8 waves stream
   constexpr int G2 = (kThreads / 2) / C;   // row groups of the 4 streaming waves
-  extern __shared__ double lds[];
-  double *U = lds;                         // [HP][LD]
-  double *D = lds + HP * LD;               // [HP][LD]
+  extern __shared__ double lds_raw[];
+  T *U = reinterpret_cast<T *>(lds_raw);   // [HP][LD]
+  T *D = U + HP * LD;                      // [HP][LD]
   __shared__ double red[kWaves];
   __shared__ int is_last;
 
@@ -240,15 +274,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
   const int col0 = blockIdx.x * C;
   const double va = sc->va, vb = sc->vb, zs = sc->zs;
   const double a1 = sc->a1, a2 = sc->a2, a3 = sc->a3, ceta = sc->ceta, zsl = sc->gamma_new;
-  const double *__restrict__ zcur = P.zcur;
-  const double *__restrict__ zprev = P.zprev;
+  const T *__restrict__ zcur = reinterpret_cast<const T *>(P.zcur);
+  const T *__restrict__ zprev = reinterpret_cast<const T *>(P.zprev);
   const double *__restrict__ vcur = P.vcur;
   const double *__restrict__ wa = P.wa;
   const double *__restrict__ bh = P.bh;
   double *__restrict__ vold = P.vold;
   double *__restrict__ wb = P.wb;
   double *__restrict__ xv = P.x;
-  double *__restrict__ znext = P.znext;
+  T *__restrict__ znext = reinterpret_cast<T *>(P.znext);
 
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
 
@@ -263,14 +297,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
     const Coef k = coef_of(P, P.tmu[cc]);
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
-    const double *__restrict__ src = (MODE == MODE_INIT) ? xv : zcur;
-    double y1 = t0 >= 1 ? src[(size_t)(t0 - 1) * m + cc] : 0.0;
-    double y2 = t0 >= 2 ? src[(size_t)(t0 - 2) * m + cc] : 0.0;
+    auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? xv[i] : (double)zcur[i]; };
+    double y1 = t0 >= 1 ? src((size_t)(t0 - 1) * m + cc) : 0.0;
+    double y2 = t0 >= 2 ? src((size_t)(t0 - 2) * m + cc) : 0.0;
 #pragma unroll 4
     for (int t = t0; t < t1; ++t) {
       const int o = n - 1 - t;
       const size_t it = (size_t)t * m + cc, io = (size_t)o * m + cc;
-      const double y0 = src[it];
+      const double y0 = src(it);
       const double ty = k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
       double v;
       if (MODE == MODE_INIT) {
@@ -281,34 +315,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
         v = zs * ty - va * vcur[io] - vb * vold[io];
       }
       if (ok) vold[io] = v;
-      if (o < h1) U[o * LD + c] = ok ? v : 0.0;
-      else D[t * LD + c] = ok ? v : 0.0;
+      if (o < h1) U[o * LD + c] = ok ? (T)v : T(0);
+      else D[t * LD + c] = ok ? (T)v : T(0);
       y2 = y1;
       y1 = y0;
     }
     // padding rows
-    for (int e = tid; e < (HP - h1) * C; e += kThreads) U[(h1 + e / C) * LD + e % C] = 0.0;
-    for (int e = tid; e < (HP - h2) * C; e += kThreads) D[(h2 + e / C) * LD + e % C] = 0.0;
+    for (int e = tid; e < (HP - h1) * C; e += kThreads) U[(h1 + e / C) * LD + e % C] = T(0);
+    for (int e = tid; e < (HP - h2) * C; e += kThreads) D[(h2 + e / C) * LD + e % C] = T(0);
   }
   __syncthreads();
   // butterfly in place: (U[p], D[p]) <- (v_p + v_{n-1-p}, v_p - v_{n-1-p}); odd n: middle has d = 0
   for (int e = tid; e < h1 * C; e += kThreads) {
     const int pp = e / C, c = e % C;
-    const double a = U[pp * LD + c];
-    const double b = pp < h2 ? D[pp * LD + c] : 0.0;
+    const T a = U[pp * LD + c];
+    const T b = pp < h2 ? D[pp * LD + c] : T(0);
     U[pp * LD + c] = pp < h2 ? a + b : a;
     if (pp < h2) D[pp * LD + c] = a - b;
   }
   __syncthreads();
 
-  d4 ao[RPW][CT], ae[RPW][CT];
+  Acc ao[RPW][CT], ae[RPW][CT];
+  const Acc zacc = {0, 0, 0, 0};
+  const T *So = reinterpret_cast<const T *>(P.So), *Se = reinterpret_cast<const T *>(P.Se);
+  const T *SoT = reinterpret_cast<const T *>(P.SoT), *SeT = reinterpret_cast<const T *>(P.SeT);
   if (wave < 4) {
     // ---- C. the matrix-core waves: z = S_o^T D_o S_o u | S_e^T D_e S_e d
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = d4{0, 0, 0, 0}; ae[i][ct] = d4{0, 0, 0, 0}; }
-    gemm_tiles<HP, C>(P.So, P.Se, U, D, wave, lane, ao, ae);
+      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
+    gemm_tiles<HP, C, PR>(So, Se, U, D, wave, lane, ao, ae);
   } else if (MODE == MODE_STEADY) {
     // ---- B. the streaming waves, part 1 of 2: lagged w_{j-1}, x_{j-1} and its true residual
     //        over time levels t (x carried for the stencil); first half of the levels.
@@ -322,14 +359,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
     const int t0 = g * R, t1 = min(n, t0 + R);
     auto xnew = [&](int t) {
       const size_t i = (size_t)t * m + cc;
-      return xv[i] + ceta * ((zsl * zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1);
+      return xv[i] + ceta * ((zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1);
     };
     double x1 = t0 >= 1 ? xnew(t0 - 1) : 0.0;
     double x2 = t0 >= 2 ? xnew(t0 - 2) : 0.0;
 #pragma unroll 4
     for (int t = t0; t < t1; ++t) {
       const size_t i = (size_t)t * m + cc;
-      const double w = (zsl * zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1;
+      const double w = (zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1;
       const double x0 = xv[i] + ceta * w;
       const double r = bh[i] - (k.l0 * x0 + k.l1 * x1 + k.l2 * x2);
       if (ok) {
@@ -355,18 +392,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
         const double tm = P.tmu[col < m ? col : m - 1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int pp = 16 * r + 4 * q + bk;
+          const int pp = 16 * r + Prec<PR>::row(q, bk);
           double so = 0.0, se = 0.0;
           if (col < m && pp < h1) {
-            so = ao[i][ct][q] * inv_sigma(P, 2 * pp, tm);
-            acc_g += ao[i][ct][q] * so;
+            const double a = (double)ao[i][ct][q];
+            so = a * inv_sigma(P, 2 * pp, tm);
+            acc_g += a * so;
           }
           if (col < m && pp < h2) {
-            se = ae[i][ct][q] * inv_sigma(P, 2 * pp + 1, tm);
-            acc_g += ae[i][ct][q] * se;
+            const double a = (double)ae[i][ct][q];
+            se = a * inv_sigma(P, 2 * pp + 1, tm);
+            acc_g += a * se;
           }
-          U[pp * LD + cl] = so;
-          D[pp * LD + cl] = se;
+          U[pp * LD + cl] = (T)so;
+          D[pp * LD + cl] = (T)se;
         }
       }
     }
@@ -376,8 +415,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = d4{0, 0, 0, 0}; ae[i][ct] = d4{0, 0, 0, 0}; }
-    gemm_tiles<HP, C>(P.SoT, P.SeT, U, D, wave, lane, ao, ae);
+      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
+    gemm_tiles<HP, C, PR>(SoT, SeT, U, D, wave, lane, ao, ae);
   }
   __syncthreads();   // U, D free again
   if (wave < 4) {
@@ -392,7 +431,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
         const int cl = 16 * ct + bj;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int pp = 16 * r + 4 * q + bk;
+          const int pp = 16 * r + Prec<PR>::row(q, bk);
           if (pp < h2) {
             U[pp * LD + cl] = ao[i][ct][q] + ae[i][ct][q];
             D[pp * LD + cl] = ao[i][ct][q] - ae[i][ct][q];
@@ -413,14 +452,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
     const Coef k = coef_of(P, P.tmu[ok ? col : m - 1]);
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
-    auto zrow = [&](int t) { return t < h1 ? U[t * LD + c] : D[(n - 1 - t) * LD + c]; };
+    auto zrow = [&](int t) -> double { return (double)(t < h1 ? U[t * LD + c] : D[(n - 1 - t) * LD + c]); };
     double y1 = t0 >= 1 ? zrow(t0 - 1) : 0.0;
     double y2 = t0 >= 2 ? zrow(t0 - 2) : 0.0;
 #pragma unroll 4
     for (int t = t0; t < t1; ++t) {
       const double y0 = zrow(t);
       if (ok) {
-        znext[(size_t)t * m + col] = y0;
+        znext[(size_t)t * m + col] = (T)y0;
         acc_d += (k.l0 * y0 + k.l1 * y1 + k.l2 * y2) * zrow(n - 1 - t);
       }
       y2 = y1;
@@ -461,18 +500,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
   }
 }
 
-template <int HP, int C>
+template <int HP, int C, int PR>
 hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks) {
-  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(double);
+  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
-  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0>), dim3(blocks), dim3(kThreads), shmem, st, P);
-  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1>), dim3(blocks), dim3(kThreads), shmem, st, P);
-  else hipLaunchKernelGGL((k_spec<HP, C, 2>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
   return hipGetLastError();
+}
+
+template <int PR>
+hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp) {
+  switch (hp) {
+    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks);
+    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks);
+    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks);
+    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks);
+    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks);
+    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks);
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -484,25 +537,21 @@ int spec_blocks(const Plan *p) {
   return (p->m + C - 1) / C;
 }
 
-hipError_t launch_spec(Ctx c, int mode, const double *zprev, const double *zcur, double *znext, const double *vcur,
+hipError_t launch_spec(Ctx c, int mode, const void *zprev, const void *zcur, void *znext, const double *vcur,
                        double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter) {
   const Plan *p = c.p;
   SpecP P{};
   P.n = p->n; P.m = p->m; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
-  P.So = p->So; P.SoT = p->SoT; P.Se = p->Se; P.SeT = p->SeT; P.tcoef = p->tcoef; P.tmu = p->tmu;
+  const bool f32 = p->pprec == SMR_FP32;
+  P.So = f32 ? (const void *)p->Sof : (const void *)p->So;
+  P.SoT = f32 ? (const void *)p->SoTf : (const void *)p->SoT;
+  P.Se = f32 ? (const void *)p->Sef : (const void *)p->Se;
+  P.SeT = f32 ? (const void *)p->SeTf : (const void *)p->SeT;
+  P.tcoef = p->tcoef; P.tmu = p->tmu;
   P.zprev = zprev; P.zcur = zcur; P.znext = znext; P.vcur = vcur; P.vold = vold; P.wa = wa; P.wb = wb;
   P.x = x; P.bh = bh; P.part = p->part; P.counter = counter; P.sc = p->sc;
   const int blocks = spec_blocks(p);
-  switch (p->hp) {
-    case 16: return run_spec<16, 32>(c.st, P, mode, blocks);
-    case 32: return run_spec<32, 32>(c.st, P, mode, blocks);
-    case 64: return run_spec<64, 32>(c.st, P, mode, blocks);
-    case 128: return run_spec<128, 32>(c.st, P, mode, blocks);
-    case 256: return run_spec<256, 16>(c.st, P, mode, blocks);
-    case 512: return run_spec<512, 16>(c.st, P, mode, blocks);
-    default: break;
-  }
-  return hipErrorInvalidValue;
+  return f32 ? run_spec_hp<1>(c.st, P, mode, blocks, p->hp) : run_spec_hp<0>(c.st, P, mode, blocks, p->hp);
 }
 
 }  // namespace smr

@@ -148,7 +148,10 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EINVAL, "P_theta is defined for the theta scheme only");
   if (d->precond == SMR_P_THETA_CHEB && (d->cheb_k < 1 || d->cheb_k > 16))
     return fail(SMR_EINVAL, "cheb_k must be in [1, 16] (got %d)", d->cheb_k);
-  if (d->pprec != SMR_FP64) return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
+  if (d->pprec != SMR_FP64 && d->pprec != SMR_FP32)
+    return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
+  if (d->pprec == SMR_FP32 && (d->precond != SMR_P_H || (d->flags & SMR_FLAG_GENERAL_PATH)))
+    return fail(SMR_EUNSUPPORTED, "float32 preconditioning is available for the sine-basis P_H solve only");
   if ((d->flags & ~SMR_FLAG_GENERAL_PATH) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
@@ -158,7 +161,7 @@ smr_status validate(const smr_desc *d) {
 }
 
 struct Layout {
-  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, tw, gface, part, sc, cnt, vec0;
+  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, cnt, vec0;
   int nvec;
   size_t total;
 };
@@ -186,6 +189,12 @@ Layout layout_of(const smr_desc *d) {
   l.SoT = take(sizeof(double) * hp * hp);
   l.Se = take(sizeof(double) * hp * hp);
   l.SeT = take(sizeof(double) * hp * hp);
+  const bool f32 = d->pprec == SMR_FP32;
+  l.Sof = take(f32 ? sizeof(float) * hp * hp : 0);
+  l.SoTf = take(f32 ? sizeof(float) * hp * hp : 0);
+  l.Sef = take(f32 ? sizeof(float) * hp * hp : 0);
+  l.SeTf = take(f32 ? sizeof(float) * hp * hp : 0);
+  l.zf = take(f32 ? 3 * align256(sizeof(float) * len) : 0);
   l.tw = take(sizeof(double) * 2 * (size_t)L);
   l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
   l.part = take(sizeof(double) * 16 * (size_t)kRedSlots);
@@ -330,6 +339,10 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.a_min = amin;
   p.a_max = amax;
   p.const_coef = (amin == amax);
+  if (p.pprec == SMR_FP32 && !p.const_coef) {
+    delete pl;
+    return fail(SMR_EUNSUPPORTED, "float32 preconditioning needs a constant coefficient (sine-basis solve)");
+  }
   p.abar = 0.5 * (amin + amax);
   p.cheb_lo = std::min(1.0, amin / p.abar);
   p.cheb_hi = std::max(1.0, amax / p.abar);
@@ -394,6 +407,13 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
         fe[at] = Se(i, k);
         feT[at] = Se(k, i);
       }
+  std::vector<float> fof, foTf, fef, feTf;
+  if (p.pprec == SMR_FP32) {
+    fof.assign(fo.begin(), fo.end());
+    foTf.assign(foT.begin(), foT.end());
+    fef.assign(fe.begin(), fe.end());
+    feTf.assign(feT.begin(), feT.end());
+  }
   // ---- FFT twiddles exp(-2 pi i t / (2L)), t < L
   std::vector<double> tw(2 * (size_t)p.L);
   for (int t = 0; t < p.L; ++t) {
@@ -413,6 +433,12 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.Se = (double *)(base_ptr + lay.Se);
   p.SeT = (double *)(base_ptr + lay.SeT);
   p.tw = (double *)(base_ptr + lay.tw);
+  p.Sof = (float *)(base_ptr + lay.Sof);
+  p.SoTf = (float *)(base_ptr + lay.SoTf);
+  p.Sef = (float *)(base_ptr + lay.Sef);
+  p.SeTf = (float *)(base_ptr + lay.SeTf);
+  for (int i = 0; i < 3; ++i)
+    p.ZF[i] = (float *)(base_ptr + lay.zf + (size_t)i * align256(sizeof(float) * p.len));
   p.gface = (double *)(base_ptr + lay.gface);
   p.part = (double *)(base_ptr + lay.part);
   p.sc = (Scal *)(base_ptr + lay.sc);
@@ -440,6 +466,12 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   if (e == hipSuccess) e = up(p.Se, fe.data(), fe.size() * sizeof(double));
   if (e == hipSuccess) e = up(p.SeT, feT.data(), feT.size() * sizeof(double));
   if (e == hipSuccess) e = up(p.tw, tw.data(), tw.size() * sizeof(double));
+  if (e == hipSuccess && p.pprec == SMR_FP32) {
+    e = up(p.Sof, fof.data(), fof.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p.SoTf, foTf.data(), foTf.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p.Sef, fef.data(), fef.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p.SeTf, feTf.data(), feTf.size() * sizeof(float));
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete pl;
@@ -460,7 +492,7 @@ namespace smr {
 namespace {
 
 bool use_spectral(const Plan &p) {
-  return p.const_coef && p.precond == SMR_P_H && p.pprec == SMR_FP64 && !(p.flags & SMR_FLAG_GENERAL_PATH);
+  return p.const_coef && p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH);
 }
 
 smr_status check_plan(const smr_plan *pl) {
@@ -551,7 +583,9 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
                            smr_info *info) {
   Ctx c{&p, s};
   double *Bh = p.T1, *Xh = p.T2;
-  double *Zb[3] = {p.Z[0], p.Z[1], p.Q};
+  void *Zb[3] = {p.Z[0], p.Z[1], p.Q};
+  if (p.pprec == SMR_FP32)
+    for (int i = 0; i < 3; ++i) Zb[i] = p.ZF[i];
   smr_status st = spatial_dst(p, s, b, Bh);
   if (st != SMR_OK) return st;
   st = spatial_dst(p, s, x, Xh);

@@ -56,7 +56,7 @@ struct Plan {
   // vectors (device), each len doubles
   double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
   double *gface;              // 2 (N+1)^2 face-gradient scratch
-  float *F1, *F2;             // float32 scratch for mixed precision
+  float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
   double *part;               // 16 * kRedSlots partial sums
   int *counter;               // last-block ticket of the fused iteration kernel
   Scal *sc;                   // device scalars
@@ -107,7 +107,8 @@ hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, cons
 
 // Fused MINRES iteration in the spatial sine basis (constant coefficients, P_H / Phat, FP64).
 // mode 0 = initialise from x0, 1 = first iteration, 2 = steady iteration.
-hipError_t launch_spec(Ctx c, int mode, const double *zprev, const double *zcur, double *znext, const double *vcur,
+// z vectors are float64 for pprec FP64 and float32 for pprec FP32.
+hipError_t launch_spec(Ctx c, int mode, const void *zprev, const void *zcur, void *znext, const double *vcur,
                        double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter);
 int spec_blocks(const Plan *p);
 hipError_t launch_zero_int(Ctx c, int *x, int count);

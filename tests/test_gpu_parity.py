@@ -217,3 +217,39 @@ def test_cn_noisy_full_size_against_direct_solve(general):
     assert r <= 1e-8 and abs(r - info["relres_true"]) <= 1e-3 * r
     u = o.solve_direct(b)
     assert rel(x, u) < 1e-6
+
+
+# ---------------------------------------------------------------- mixed precision
+# Parity unpinned by design: a float32 P^{-1} is a rounding-perturbed preconditioner, so the
+# iterates differ from the float64 oracle.  The checks are the ones the method fixes: the
+# float64 true residual reaches the tolerance, the iteration count stays within 10% (+1) of
+# the oracle's, and the solution's error against the oracle is small and reported.
+@pytest.mark.parametrize("dim,N,n,scheme,theta", [(2, 31, 64, "theta", 0.5), (2, 63, 128, "theta", 1.0),
+                                                  (2, 31, 64, "bdf2", 1.0), (1, 63, 64, "theta", 1.0)])
+def test_mixed_fp32_solve(dim, N, n, scheme, theta):
+    from paper_2201_10062_amd import Plan
+    g = Plan(dim, N, n, scheme=scheme, theta=theta, pprec="fp32")
+    o = System(dim, N, n, scheme=scheme, theta=theta)
+    rng = np.random.default_rng(8)
+    b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m)) if scheme == "theta" \
+        else rng.standard_normal(n * g.m)
+    ref = o.solve(b, rtol=1e-8)
+    x, info = g.solve(_t(b), rtol=1e-8)
+    x = _n(x)
+    r = np.linalg.norm(b - o.apply_T(x)) / np.linalg.norm(b)
+    err = rel(x, ref.x)
+    print(f"mixed fp32 {dim}D N={N} n={n} {scheme}: iters {info['iters']} (fp64 {ref.iters}) "
+          f"relres {r:.2e} err vs oracle {err:.2e}")
+    assert info["status"] == "ok" and r <= 1e-8 and abs(r - info["relres_true"]) <= 1e-3 * r
+    assert info["iters"] <= int(1.1 * ref.iters) + 1
+    assert err < 1e-6
+    # the float32 transform really ran: the iterate is not the float64 one to rounding level
+    x64, _ = Plan(dim, N, n, scheme=scheme, theta=theta).solve(_t(b), rtol=1e-8)
+    assert rel(x, _n(x64)) > 1e-13
+
+
+def test_mixed_fp32_rejects_variable_coefficients():
+    from paper_2201_10062_amd import Plan, SmrError
+    ax, ay = _faces("var", 7, 2)
+    with pytest.raises(SmrError):
+        Plan(2, 7, 8, pprec="fp32", ax=ax, ay=ay)
