@@ -142,14 +142,23 @@ smr_status smr_apply_P_inv(const smr_plan *plan, const double *d_v, double *d_z,
 smr_status smr_minres_solve(const smr_plan *plan, const double *d_b, double *d_x, double rtol,
                             int32_t maxit, smr_info *info_host, void *stream);
 
-/* The same solve for `count` independent plans/right-hand sides at once, each with its
- * own (N, n, coefficient, scheme); all plans must share pprec and the library drives
- * every instance's iteration in the same kernel launches, masking converged ones.
- * plans, d_b, d_x, infos_host are host arrays of length count.  Returns SMR_OK when all
- * converged, else the first failing status; each info holds its own. */
+/* Device workspace (bytes, 256-byte aligned) that smr_minres_solve_batched needs for this
+ * set of plans: the per-instance descriptor table and status array of the batched launch. */
+smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans, size_t *bytes);
+
+/* The same solve for `count` independent plans at once, each with its own (N, n, scheme,
+ * coefficient, preconditioner) and right-hand side.  Instances that take the sine-basis path
+ * (constant a, P_H / Phat) iterate together: every MINRES iteration is one launch per
+ * (time-size class, pprec) covering all of their column tiles, each instance with its own
+ * device scalars; converged instances are masked on the device.  The remaining instances are
+ * solved one after another on the general path.  plans, d_b, d_x and infos_host are host
+ * arrays of length count; d_b[i] / d_x[i] follow the conventions of smr_minres_solve.
+ * d_ws: caller-owned device workspace of smr_batch_workspace_size bytes.  Returns SMR_OK when
+ * every instance converged, else the first failing status (each info holds its own). */
 smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
                                     const double *const *d_b, double *const *d_x, double rtol,
-                                    int32_t maxit, smr_info *infos_host, void *stream);
+                                    int32_t maxit, void *d_ws, size_t ws_bytes,
+                                    smr_info *infos_host, void *stream);
 
 /* Adjoint solve T^T lambda = g: since T^T = Y T Y, MINRES on (Y T) mu = g with the same
  * preconditioner, then lambda = Y mu.  d_g, d_lambda: n*m.  d_lambda is zeroed first. */

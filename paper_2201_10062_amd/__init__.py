@@ -5,6 +5,6 @@ The solver lives in libsmr.so (HIP kernels + C ABI, include/smr.h); ``smr`` is i
 ctypes binding.
 """
 from . import smr  # noqa: F401
-from .smr import Plan, SmrError, load, solve_batched  # noqa: F401
+from .smr import Batch, Plan, SmrError, load, solve_batched  # noqa: F401
 
-__all__ = ["smr", "Plan", "SmrError", "load", "solve_batched"]
+__all__ = ["smr", "Batch", "Plan", "SmrError", "load", "solve_batched"]

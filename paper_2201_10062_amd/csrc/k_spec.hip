@@ -54,26 +54,6 @@ template <> struct Prec<1> {
 };
 constexpr int kWaves = kThreads / 64;
 
-struct SpecP {
-  int n, m, h1, h2, scheme;
-  double theta;
-  const void *So, *SoT, *Se, *SeT;   // folded sine tables in the transform's precision
-  const double *tcoef, *tmu;
-  // vectors (spatial-sine basis); z in the transform's precision
-  const void *zprev;     // z_{j-1}
-  const void *zcur;      // z_j (INIT: unused)
-  void *znext;           // z_{j+1} (INIT: z_1)
-  const double *vcur;    // v_j
-  double *vold;          // in v_{j-1}, out v_{j+1} (INIT: out v_1)
-  const double *wa;      // w_{j-2}
-  double *wb;            // in w_{j-3}, out w_{j-1}
-  double *x;             // x (INIT: x0, read only)
-  const double *bh;      // transformed right-hand side b^ (unpermuted)
-  double *part;          // 4 partial sums per block
-  int *counter;          // last-block ticket
-  Scal *sc;
-};
-
 enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2 };
 
 // per-column stencil coefficients of (T y)_t = l0 y_t + l1 y_{t-1} + l2 y_{t-2}
@@ -254,7 +234,7 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
 }
 
 template <int HP, int C, int MODE, int PR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8))) void k_spec(SpecP P) {
+__device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const int tile) {
   typedef typename Prec<PR>::T T;
   typedef typename Prec<PR>::Acc Acc;
   Scal *sc = P.sc;
@@ -271,18 +251,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = P.n, m = P.m, h1 = P.h1, h2 = P.h2;
-  const int col0 = blockIdx.x * C;
+  const int col0 = tile * C;
   const double va = sc->va, vb = sc->vb, zs = sc->zs;
   const double a1 = sc->a1, a2 = sc->a2, a3 = sc->a3, ceta = sc->ceta, zsl = sc->gamma_new;
-  const T *__restrict__ zcur = reinterpret_cast<const T *>(P.zcur);
-  const T *__restrict__ zprev = reinterpret_cast<const T *>(P.zprev);
-  const double *__restrict__ vcur = P.vcur;
-  const double *__restrict__ wa = P.wa;
+  const int j = jph;   // launch index modulo 6 (rotation phase); INIT uses the j = 0 slots
+  const T *__restrict__ zcur = reinterpret_cast<const T *>(P.Z[(j + 2) % 3]);
+  const T *__restrict__ zprev = reinterpret_cast<const T *>(P.Z[(j + 1) % 3]);
+  T *__restrict__ znext = reinterpret_cast<T *>(MODE == MODE_INIT ? P.Z[0] : P.Z[j % 3]);
+  const double *__restrict__ vcur = P.V[j % 2];
+  double *__restrict__ vold = MODE == MODE_INIT ? P.V[1] : P.V[(j + 1) % 2];
+  const double *__restrict__ wa = P.W[j % 2];
+  double *__restrict__ wb = P.W[(j + 1) % 2];
   const double *__restrict__ bh = P.bh;
-  double *__restrict__ vold = P.vold;
-  double *__restrict__ wb = P.wb;
   double *__restrict__ xv = P.x;
-  T *__restrict__ znext = reinterpret_cast<T *>(P.znext);
 
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
 
@@ -473,17 +454,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
   const double s2 = block_sum(acc_g, red);
   const double s3 = block_sum(acc_d, red);
   if (tid == 0) {
-    double *pp = P.part + 4 * (size_t)blockIdx.x;
+    double *pp = P.part + 4 * (size_t)tile;
     pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3;
     __threadfence();
     const int ticket = atomicAdd(P.counter, 1);
-    is_last = (ticket == (int)gridDim.x - 1);
+    is_last = (ticket == P.tiles - 1);
   }
   __syncthreads();
   if (!is_last) return;
   __threadfence();
   double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-  for (int b = tid; b < (int)gridDim.x; b += kThreads) {
+  for (int b = tid; b < P.tiles; b += kThreads) {
     const double *pp = P.part + 4 * (size_t)b;
     t0 += ld_agent(pp + 0);
     t1 += ld_agent(pp + 1);
@@ -500,29 +481,80 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 
   }
 }
 
+template <int HP, int C, int MODE, int PR>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
+void k_spec(SpecP P, int jph) {
+  spec_body<HP, C, MODE, PR>(P, jph, blockIdx.x);
+}
+
+// Batched launch: the blocks of every instance in the table, instance found by its first block.
+template <int HP, int C, int MODE, int PR>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
+void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].tile0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const SpecP P = table[lo];
+  spec_body<HP, C, MODE, PR>(P, jph, (int)blockIdx.x - P.tile0);
+}
+
 template <int HP, int C, int PR>
-hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks) {
+hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jph) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
     hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
-  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
-  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
-  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P);
+  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
+  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
+  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
+  return hipGetLastError();
+}
+
+template <int HP, int C, int PR>
+hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int jph) {
+  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
+  if (shmem > 65536) {
+    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  }
+  if (mode == 0)
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
+  else
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
   return hipGetLastError();
 }
 
 template <int PR>
-hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp) {
+hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph) {
   switch (hp) {
-    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks);
-    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks);
-    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks);
-    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks);
-    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks);
-    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks);
+    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks, jph);
+    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks, jph);
+    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks, jph);
+    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks, jph);
+    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks, jph);
+    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks, jph);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int PR>
+hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph) {
+  switch (hp) {
+    case 16: return run_spec_multi<16, 32, PR>(st, table, ninst, mode, blocks, jph);
+    case 32: return run_spec_multi<32, 32, PR>(st, table, ninst, mode, blocks, jph);
+    case 64: return run_spec_multi<64, 32, PR>(st, table, ninst, mode, blocks, jph);
+    case 128: return run_spec_multi<128, 32, PR>(st, table, ninst, mode, blocks, jph);
+    case 256: return run_spec_multi<256, 16, PR>(st, table, ninst, mode, blocks, jph);
+    case 512: return run_spec_multi<512, 16, PR>(st, table, ninst, mode, blocks, jph);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -537,21 +569,46 @@ int spec_blocks(const Plan *p) {
   return (p->m + C - 1) / C;
 }
 
-hipError_t launch_spec(Ctx c, int mode, const void *zprev, const void *zcur, void *znext, const double *vcur,
-                       double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter) {
-  const Plan *p = c.p;
+SpecP spec_desc(const Plan *p, double *x, const double *bh) {
   SpecP P{};
   P.n = p->n; P.m = p->m; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
+  P.tiles = spec_blocks(p);
+  P.tile0 = 0;
   const bool f32 = p->pprec == SMR_FP32;
   P.So = f32 ? (const void *)p->Sof : (const void *)p->So;
   P.SoT = f32 ? (const void *)p->SoTf : (const void *)p->SoT;
   P.Se = f32 ? (const void *)p->Sef : (const void *)p->Se;
   P.SeT = f32 ? (const void *)p->SeTf : (const void *)p->SeT;
   P.tcoef = p->tcoef; P.tmu = p->tmu;
-  P.zprev = zprev; P.zcur = zcur; P.znext = znext; P.vcur = vcur; P.vold = vold; P.wa = wa; P.wb = wb;
-  P.x = x; P.bh = bh; P.part = p->part; P.counter = counter; P.sc = p->sc;
-  const int blocks = spec_blocks(p);
-  return f32 ? run_spec_hp<1>(c.st, P, mode, blocks, p->hp) : run_spec_hp<0>(c.st, P, mode, blocks, p->hp);
+  for (int i = 0; i < 3; ++i) P.Z[i] = f32 ? (void *)p->ZF[i] : (void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
+  P.V[0] = p->V[0]; P.V[1] = p->V[1]; P.W[0] = p->W[0]; P.W[1] = p->W[1];
+  P.x = x; P.bh = bh; P.part = p->part; P.counter = p->counter; P.sc = p->sc;
+  return P;
+}
+
+hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh) {
+  const Plan *p = c.p;
+  const SpecP P = spec_desc(p, x, bh);
+  const int jph = j % 6;
+  return p->pprec == SMR_FP32 ? run_spec_hp<1>(c.st, P, mode, P.tiles, p->hp, jph)
+                              : run_spec_hp<0>(c.st, P, mode, P.tiles, p->hp, jph);
+}
+
+hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
+                             int j) {
+  const int jph = j % 6;
+  return pprec == SMR_FP32 ? run_multi_hp<1>(st, table, ninst, mode, blocks, hp, jph)
+                           : run_multi_hp<0>(st, table, ninst, mode, blocks, hp, jph);
+}
+
+__global__ void k_gather_scal(const SpecP *__restrict__ table, int ninst, Scal *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) out[i] = *table[i].sc;
+}
+
+hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, Scal *out) {
+  hipLaunchKernelGGL(k_gather_scal, dim3((ninst + 63) / 64), dim3(64), 0, st, table, ninst, out);
+  return hipGetLastError();
 }
 
 }  // namespace smr

@@ -583,9 +583,6 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
                            smr_info *info) {
   Ctx c{&p, s};
   double *Bh = p.T1, *Xh = p.T2;
-  void *Zb[3] = {p.Z[0], p.Z[1], p.Q};
-  if (p.pprec == SMR_FP32)
-    for (int i = 0; i < 3; ++i) Zb[i] = p.ZF[i];
   smr_status st = spatial_dst(p, s, b, Bh);
   if (st != SMR_OK) return st;
   st = spatial_dst(p, s, x, Xh);
@@ -599,7 +596,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
   LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
   LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
-  LAUNCH(PROF_SPEC, launch_spec(c, 0, nullptr, nullptr, Zb[0], nullptr, p.V[1], nullptr, nullptr, Xh, Bh, p.counter));
+  LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
   const Profiler::Mark m0 = g_prof.mark();
   int issued = 0;            // launches j = 1..issued enqueued
   int chunk = 4;
@@ -611,8 +608,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
     const int todo = std::min(chunk, last - issued);
     for (int it = 0; it < todo; ++it) {
       const int j = issued + it + 1;
-      LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, Zb[(j + 1) % 3], Zb[(j - 1) % 3], Zb[j % 3], p.V[j % 2],
-                                    p.V[(j + 1) % 2], p.W[j % 2], p.W[(j + 1) % 2], Xh, Bh, p.counter));
+      LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, j, Xh, Bh));
     }
     issued += todo;
     chunk = std::min(chunk * 2, 16);
@@ -744,15 +740,113 @@ smr_status smr_minres_solve(const smr_plan *pl, const double *b, double *x, doub
   return minres(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
 }
 
+smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans, size_t *bytes) {
+  if (count < 0 || (count > 0 && !plans) || !bytes) return fail(SMR_EINVAL, "bad batch arguments");
+  *bytes = align256(sizeof(SpecP) * (size_t)std::max(count, 1)) + align256(sizeof(Scal) * (size_t)std::max(count, 1));
+  return SMR_OK;
+}
+
 smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans, const double *const *b,
-                                    double *const *x, double rtol, int32_t maxit, smr_info *infos, void *stream) {
+                                    double *const *x, double rtol, int32_t maxit, void *d_ws, size_t ws_bytes,
+                                    smr_info *infos, void *stream) {
   if (count < 0 || (count > 0 && (!plans || !b || !x || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
-  smr_status first = SMR_OK;
+  if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
+  size_t need = 0;
+  smr_batch_workspace_size(count, plans, &need);
+  if (count > 0 && (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < need))
+    return fail(SMR_EWORKSPACE, "batch workspace missing, misaligned or smaller than %zu bytes", need);
   for (int i = 0; i < count; ++i) {
-    smr_status st = smr_minres_solve(plans[i], b[i], x[i], rtol, maxit, &infos[i], stream);
-    if (st != SMR_OK && first == SMR_OK) first = st;
+    if (!plans[i] || !b[i] || !x[i]) return fail(SMR_EINVAL, "instance %d: NULL plan or vector", i);
   }
-  return first;
+  hipStream_t s = (hipStream_t)stream;
+  SpecP *d_table = (SpecP *)d_ws;
+  Scal *d_scal = (Scal *)((char *)d_ws + align256(sizeof(SpecP) * (size_t)std::max(count, 1)));
+  // sine-basis instances, grouped by (time-size class, transform precision)
+  std::vector<int> spec_ids, general_ids;
+  for (int i = 0; i < count; ++i) (use_spectral(plans[i]->p) ? spec_ids : general_ids).push_back(i);
+  std::stable_sort(spec_ids.begin(), spec_ids.end(), [&](int a, int c) {
+    const Plan &pa = plans[a]->p, &pc = plans[c]->p;
+    return pa.hp != pc.hp ? pa.hp < pc.hp : pa.pprec < pc.pprec;
+  });
+  struct Class { int first, count, blocks, hp, pprec; };
+  std::vector<Class> classes;
+  std::vector<SpecP> table(spec_ids.size());
+  for (size_t k = 0; k < spec_ids.size(); ++k) {
+    const Plan &p = plans[spec_ids[k]]->p;
+    if (classes.empty() || classes.back().hp != p.hp || classes.back().pprec != p.pprec)
+      classes.push_back(Class{(int)k, 0, 0, p.hp, p.pprec});
+    Class &cl = classes.back();
+    table[k] = spec_desc(&p, p.T2, p.T1);
+    table[k].tile0 = cl.blocks;
+    cl.blocks += table[k].tiles;
+    cl.count += 1;
+  }
+  const int ns = (int)spec_ids.size();
+  smr_status first_bad = SMR_OK;
+  if (ns > 0) {
+    for (int k = 0; k < ns; ++k) {
+      const Plan &p = plans[spec_ids[k]]->p;
+      Ctx c{&p, s};
+      smr_status st = spatial_dst(p, s, b[spec_ids[k]], p.T1);
+      if (st != SMR_OK) return st;
+      st = spatial_dst(p, s, x[spec_ids[k]], p.T2);
+      if (st != SMR_OK) return st;
+      Scal h{};
+      h.rtol = rtol;
+      h.maxit = maxit;
+      h.status = RUNNING;
+      HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
+      LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
+      LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
+      LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+      LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
+    }
+    HIP_TRY(hipMemcpyAsync(d_table, table.data(), sizeof(SpecP) * ns, hipMemcpyHostToDevice, s));
+    Ctx c0{&plans[spec_ids[0]]->p, s};
+    Ctx &c = c0;
+    for (const Class &cl : classes)
+      LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, 0, 0));
+    std::vector<Scal> hs(ns);
+    int issued = 0, chunk = 4;
+    const int last = maxit + 1;
+    for (;;) {
+      HIP_TRY(launch_gather_scal(s, d_table, ns, d_scal));
+      HIP_TRY(hipMemcpyAsync(hs.data(), d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      bool running = false;
+      for (const Scal &h : hs) running |= (h.status == RUNNING);
+      if (!running || issued >= last) break;
+      const int todo = std::min(chunk, last - issued);
+      for (int it = 0; it < todo; ++it) {
+        const int j = issued + it + 1;
+        for (const Class &cl : classes)
+          LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec,
+                                              j == 1 ? 1 : 2, j));
+      }
+      issued += todo;
+      chunk = std::min(chunk * 2, 16);
+    }
+    for (int k = 0; k < ns; ++k) {
+      const int i = spec_ids[k];
+      const Plan &p = plans[i]->p;
+      Ctx ci{&p, s};
+      Ctx &c = ci;
+      if (hs[k].status == DONE_CONV && hs[k].bnorm == 0.0) {
+        LAUNCH(PROF_VEC, launch_zero(c, x[i], p.len));
+      } else {
+        smr_status st = spatial_dst(p, s, p.T2, x[i]);
+        if (st != SMR_OK) return st;
+      }
+      smr_status st = finish_info(hs[k], maxit, &infos[i]);
+      if (st != SMR_OK && first_bad == SMR_OK) first_bad = st;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  for (int i : general_ids) {
+    smr_status st = minres(plans[i]->p, s, b[i], x[i], rtol, maxit, &infos[i]);
+    if (st != SMR_OK && first_bad == SMR_OK) first_bad = st;
+  }
+  return first_bad;
 }
 
 smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, double rtol, int32_t maxit,

@@ -105,11 +105,33 @@ hipError_t launch_zero(Ctx c, double *x, size_t len);
 hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, const double *part2,
                               int nb2);
 
-// Fused MINRES iteration in the spatial sine basis (constant coefficients, P_H / Phat, FP64).
-// mode 0 = initialise from x0, 1 = first iteration, 2 = steady iteration.
-// z vectors are float64 for pprec FP64 and float32 for pprec FP32.
-hipError_t launch_spec(Ctx c, int mode, const void *zprev, const void *zcur, void *znext, const double *vcur,
-                       double *vold, const double *wa, double *wb, double *x, const double *bh, int *counter);
+// Fused MINRES iteration in the spatial sine basis (constant coefficients, P_H / Phat).
+// mode 0 = initialise from x0, 1 = first iteration, 2 = steady iteration; j = launch index
+// (selects the rotating z / v / w buffers).  x and bh are the transformed iterate and rhs.
+// One instance of the sine-basis solve as the fused kernel sees it (also the element of the
+// device descriptor table of a batched launch).
+struct SpecP {
+  int n, m, h1, h2, scheme, tiles, tile0, pad;
+  double theta;
+  const void *So, *SoT, *Se, *SeT;   // folded sine tables in the transform's precision
+  const double *tcoef, *tmu;
+  // vectors (spatial-sine basis); z in the transform's precision.  Launch j uses
+  // z_j = Z[(j-1)%3], z_{j+1} = Z[j%3], z_{j-1} = Z[(j+1)%3], v_j = V[j%2], v_{j-1} = V[(j+1)%2]
+  // (overwritten by v_{j+1}), w_{j-2} = W[j%2], w_{j-3} = W[(j+1)%2] (overwritten by w_{j-1}).
+  void *Z[3];
+  double *V[2], *W[2];
+  double *x;             // x (INIT: x0, read only)
+  const double *bh;      // transformed right-hand side b^ (unpermuted)
+  double *part;          // 4 partial sums per column tile
+  int *counter;          // last-tile ticket
+  Scal *sc;
+};
+
+hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh);
+SpecP spec_desc(const Plan *p, double *x, const double *bh);
+hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
+                             int j);
+hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, Scal *out);
 int spec_blocks(const Plan *p);
 hipError_t launch_zero_int(Ctx c, int *x, int count);
 

@@ -26,7 +26,7 @@ PPRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
 # Every entry point of include/smr.h.
 EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
-    "smr_minres_solve", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_rhs_adjoint", "smr_grad_a",
+    "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error",
 )
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5}
@@ -75,9 +75,10 @@ def load() -> ctypes.CDLL:
     lib.smr_apply_A.argtypes = [P, P, P, P]
     lib.smr_apply_P_inv.argtypes = [P, P, P, P]
     lib.smr_minres_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
+    lib.smr_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]
     lib.smr_minres_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
-                                             ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32,
-                                             ctypes.POINTER(SmrInfo), P]
+                                             ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, P,
+                                             ctypes.c_size_t, ctypes.POINTER(SmrInfo), P]
     lib.smr_solve_adjoint.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
     lib.smr_rhs_adjoint.argtypes = [P, P, P, P, P]
     lib.smr_grad_a.argtypes = [P, P, P, P, P, P, P, P]
@@ -254,18 +255,41 @@ class Plan:
         return gax, gay, gn
 
 
+class Batch:
+    """A fixed set of plans solved together; owns the batch workspace (descriptor table)."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        import torch
+        self.plans = list(plans)
+        n = len(self.plans)
+        P = ctypes.c_void_p
+        self._hp = (P * n)(*[p.handle.value for p in self.plans])
+        nbytes = ctypes.c_size_t(0)
+        _check(load().smr_batch_workspace_size(n, self._hp, ctypes.byref(nbytes)))
+        dev = self.plans[0].ws.device if n else torch.device("cuda")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes.value]
+
+    def solve(self, bs, x0s=None, rtol=1e-8, maxit=500):
+        """Solve every (plan, b) pair; returns (xs, infos)."""
+        n = len(self.plans)
+        xs = [p.empty().zero_() if x0s is None else x0.clone() for p, x0 in zip(self.plans, x0s or [None] * n)]
+        for p, b, x in zip(self.plans, bs, xs):
+            p._vec(b)
+            p._vec(x)
+        P = ctypes.c_void_p
+        bp = (P * n)(*[b.data_ptr() for b in bs])
+        xp = (P * n)(*[x.data_ptr() for x in xs])
+        infos = (SmrInfo * n)()
+        st = load().smr_minres_solve_batched(n, self._hp, bp, xp, float(rtol), int(maxit),
+                                             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), infos, _stream())
+        if st not in (SMR_OK, SMR_ENOTCONV):
+            _check(st)
+        return xs, [i.as_dict() for i in infos]
+
+
 def solve_batched(plans: Sequence[Plan], bs, rtol=1e-8, maxit=500):
-    """Solve every (plan, b) pair; returns (xs, infos)."""
-    n = len(plans)
-    xs = [p.empty().zero_() for p in plans]
-    for p, b in zip(plans, bs):
-        p._vec(b)
-    P = ctypes.c_void_p
-    hp = (P * n)(*[p.handle.value for p in plans])
-    bp = (P * n)(*[b.data_ptr() for b in bs])
-    xp = (P * n)(*[x.data_ptr() for x in xs])
-    infos = (SmrInfo * n)()
-    st = load().smr_minres_solve_batched(n, hp, bp, xp, float(rtol), int(maxit), infos, _stream())
-    if st not in (SMR_OK, SMR_ENOTCONV):
-        _check(st)
-    return xs, [i.as_dict() for i in infos]
+    """Solve every (plan, b) pair in one batched call; returns (xs, infos)."""
+    return Batch(plans).solve(bs, rtol=rtol, maxit=maxit)

@@ -253,3 +253,53 @@ def test_mixed_fp32_rejects_variable_coefficients():
     ax, ay = _faces("var", 7, 2)
     with pytest.raises(SmrError):
         Plan(2, 7, 8, pprec="fp32", ax=ax, ay=ay)
+
+
+# ---------------------------------------------------------------- batched solves
+def _bdf2_batch_small(count=12):
+    """The BDF2 batch recipe at reduced sizes: N in (7, 15, 31), n in (16, 32, 64),
+    a = 1 or 1 + 0.5 cos(pi x), b ~ N(0, 1)."""
+    return W.bdf2_batch(count=count, Ns=(7, 15, 31), ns=(16, 32, 64))
+
+
+def test_batched_matches_oracle_per_instance():
+    from paper_2201_10062_amd import Batch, Plan
+    probs = _bdf2_batch_small(24)
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    xs, infos = Batch(plans).solve([_t(p.b) for p in probs], rtol=1e-8)
+    for p, x, info in zip(probs, xs, infos):
+        o = System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay)
+        ref = o.solve(p.b.reshape(-1), rtol=1e-8, maxit=500)
+        assert info["status"] == "ok" and info["iters"] == ref.iters, (p.name, info, ref.iters)
+        assert rel(_n(x), ref.x) < 1e-10, p.name
+
+
+def test_batched_fp32_and_masking():
+    """Constant-coefficient instances in float32 with very different iteration counts: each
+    stops at its own iteration (converged instances are masked while others run)."""
+    from paper_2201_10062_amd import Batch, Plan
+    probs = [q for q in _bdf2_batch_small(18) if q.ax is None]
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", pprec="fp32") for p in probs]
+    rtols = 1e-8
+    bs = [_t(p.b) for p in probs]
+    bs[0] = bs[0] * 0.0                       # a zero right-hand side converges at once
+    xs, infos = Batch(plans).solve(bs, rtol=rtols)
+    assert infos[0]["iters"] == 0 and float(_n(xs[0]).__abs__().max()) == 0.0
+    for p, b, x, info in zip(probs[1:], bs[1:], xs[1:], infos[1:]):
+        o = System(2, p.N, p.n, scheme="bdf2")
+        ref = o.solve(p.b.reshape(-1), rtol=1e-8)
+        r = np.linalg.norm(p.b.reshape(-1) - o.apply_T(_n(x))) / np.linalg.norm(p.b)
+        assert info["status"] == "ok" and r <= 1e-8
+        assert info["iters"] <= int(1.1 * ref.iters) + 1
+
+
+def test_batched_single_and_empty():
+    from paper_2201_10062_amd import Batch, Plan
+    p = W.crank_nicolson_2d_noisy(N=15, n=16)
+    plan = Plan(2, 15, 16, theta=0.5)
+    b = plan.build_rhs(_t(p.f), _t(p.u0))
+    xs, infos = Batch([plan]).solve([b], rtol=1e-8)
+    x1, info1 = plan.solve(b, rtol=1e-8)
+    assert infos[0]["iters"] == info1["iters"] and rel(_n(xs[0]), _n(x1)) < 1e-13
+    xs, infos = Batch([]).solve([], rtol=1e-8)
+    assert xs == [] and infos == []
