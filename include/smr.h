@@ -165,6 +165,13 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
 smr_status smr_solve_adjoint(const smr_plan *plan, const double *d_g, double *d_lambda,
                              double rtol, int32_t maxit, smr_info *info_host, void *stream);
 
+/* Batched adjoint solves T_i^T lambda_i = g_i for `count` plans (same flip-solve-flip as
+ * smr_solve_adjoint, iterating together like smr_minres_solve_batched; same workspace). */
+smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans,
+                                     const double *const *d_g, double *const *d_lambda, double rtol,
+                                     int32_t maxit, void *d_ws, size_t ws_bytes, smr_info *infos_host,
+                                     void *stream);
+
 /* Adjoint of smr_build_rhs (theta scheme): d_grad_f[(n+1)*m] with
  * grad f^(k) = theta tau lambda_k + (1-theta) tau lambda_{k+1} (lambda_0 = lambda_{n+1} = 0)
  * and d_grad_u0[m] = (I - (1-theta) tau K) lambda_1 (may be NULL). */

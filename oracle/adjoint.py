@@ -29,6 +29,23 @@ def adjoint_solve(system, g: np.ndarray, rtol: float = 1e-8, maxit: int = 500):
     return system.flip(res.x), res
 
 
+def adjoint_direct(system, g: np.ndarray) -> np.ndarray:
+    """T^T lambda = g by backward block substitution: T^T is block upper-banded with A_l^T = A_l
+    (K symmetric) on the l-th block superdiagonal, one sparse SPD solve per level."""
+    import scipy.sparse.linalg as spla
+    n = system.n
+    G = np.asarray(g, dtype=np.float64).reshape(n, -1)
+    lu = spla.splu(system.blocks[0].tocsc())
+    L = np.zeros_like(G)
+    for k in range(n - 1, -1, -1):
+        r = G[k].copy()
+        for l in range(1, len(system.blocks)):
+            if k + l < n:
+                r -= system.blocks[l].T @ L[k + l]
+        L[k] = lu.solve(r)
+    return L.reshape(-1)
+
+
 def adjoint_dense(system, g: np.ndarray) -> np.ndarray:
     T = system.assemble_T().toarray()
     return np.linalg.solve(T.T, g)

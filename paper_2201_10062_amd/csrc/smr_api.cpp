@@ -869,6 +869,32 @@ smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, d
   return st;
 }
 
+smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans, const double *const *g,
+                                     double *const *lam, double rtol, int32_t maxit, void *d_ws, size_t ws_bytes,
+                                     smr_info *infos, void *stream) {
+  if (count < 0 || (count > 0 && (!plans || !g || !lam || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<const double *> bs(count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !g[i] || !lam[i] || g[i] == lam[i]) return fail(SMR_EINVAL, "instance %d: bad pointers", i);
+    const Plan &p = plans[i]->p;
+    Ctx c{&p, s};
+    LAUNCH(PROF_VEC, launch_scale_copy(c, g[i], p.G, 1.0, 1));   // (Y T) mu = g  <=>  solve with b' = Y g
+    LAUNCH(PROF_VEC, launch_zero(c, lam[i], p.len));
+    bs[i] = p.G;
+  }
+  smr_status st = smr_minres_solve_batched(count, plans, bs.data(), lam, rtol, maxit, d_ws, ws_bytes, infos, stream);
+  if (st != SMR_OK && st != SMR_ENOTCONV) return st;
+  for (int i = 0; i < count; ++i) {                           // lambda = Y mu
+    const Plan &p = plans[i]->p;
+    Ctx c{&p, s};
+    LAUNCH(PROF_VEC, launch_scale_copy(c, lam[i], p.G, 1.0, 1));
+    HIP_TRY(hipMemcpyAsync(lam[i], p.G, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return st;
+}
+
 smr_status smr_rhs_adjoint(const smr_plan *pl, const double *lam, double *gf, double *gu0, void *stream) {
   smr_status st = check_plan(pl);
   if (st != SMR_OK) return st;

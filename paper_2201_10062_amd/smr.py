@@ -26,7 +26,7 @@ PPRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
 # Every entry point of include/smr.h.
 EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
-    "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_rhs_adjoint", "smr_grad_a",
+    "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_solve_adjoint_batched", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error",
 )
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5}
@@ -80,6 +80,9 @@ def load() -> ctypes.CDLL:
                                              ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, P,
                                              ctypes.c_size_t, ctypes.POINTER(SmrInfo), P]
     lib.smr_solve_adjoint.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
+    lib.smr_solve_adjoint_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
+                                              ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, P,
+                                              ctypes.c_size_t, ctypes.POINTER(SmrInfo), P]
     lib.smr_rhs_adjoint.argtypes = [P, P, P, P, P]
     lib.smr_grad_a.argtypes = [P, P, P, P, P, P, P, P]
     lib.smr_profile_enable.argtypes = [ctypes.c_int32]
@@ -288,6 +291,23 @@ class Batch:
         if st not in (SMR_OK, SMR_ENOTCONV):
             _check(st)
         return xs, [i.as_dict() for i in infos]
+
+
+    def solve_adjoint(self, gs, rtol=1e-8, maxit=500):
+        """Solve T_i^T lambda_i = g_i for every plan; returns (lambdas, infos)."""
+        n = len(self.plans)
+        lams = [p.empty() for p in self.plans]
+        for p, g in zip(self.plans, gs):
+            p._vec(g)
+        P = ctypes.c_void_p
+        gp = (P * n)(*[g.data_ptr() for g in gs])
+        lp = (P * n)(*[x.data_ptr() for x in lams])
+        infos = (SmrInfo * n)()
+        st = load().smr_solve_adjoint_batched(n, self._hp, gp, lp, float(rtol), int(maxit),
+                                              ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), infos, _stream())
+        if st not in (SMR_OK, SMR_ENOTCONV):
+            _check(st)
+        return lams, [i.as_dict() for i in infos]
 
 
 def solve_batched(plans: Sequence[Plan], bs, rtol=1e-8, maxit=500):

@@ -1,0 +1,101 @@
+"""GPU checks of the differentiable solve (torch.autograd.Function over the C ABI): gradients
+w.r.t. f, u0 and the nodal coefficient against the oracle's adjoint gradients and against
+central finite differences of the oracle's direct solves."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle.system import System
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def _oracle_grads(N, n, theta, a_nodal, f, u0, uobs):
+    gf_all, ga, gu0 = [], None, None
+    for b in range(f.shape[0]):
+        s = System(2, N, n, theta=theta, a_nodal=a_nodal)
+        u = s.solve_direct(s.rhs(f[b], u0))
+        lam = oadj.adjoint_direct(s, 2 * (u - uobs[b].reshape(-1)))
+        gf, gu = oadj.rhs_adjoint(s, lam)
+        gx, gy = oadj.grad_faces(s, u, u0, lam)
+        gn = oadj.grad_nodal(gx, gy, N, 2)
+        gf_all.append(gf)
+        ga = gn if ga is None else ga + gn
+        gu0 = gu if gu0 is None else gu0 + gu
+    return np.stack(gf_all), ga, gu0
+
+
+def _loss_oracle(N, n, theta, a_nodal, f, u0, uobs):
+    L = 0.0
+    for b in range(f.shape[0]):
+        s = System(2, N, n, theta=theta, a_nodal=a_nodal)
+        L += float(np.sum((s.solve_direct(s.rhs(f[b], u0)) - uobs[b].reshape(-1)) ** 2))
+    return L
+
+
+@pytest.mark.parametrize("variable", [False, True], ids=["a_const", "a_var"])
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_gradients_match_oracle_and_fd(variable, theta):
+    from paper_2201_10062_amd.autograd import heat_solve
+    dev = _dev()
+    N, n, B = 7, 8, 3
+    rng = np.random.default_rng(10)
+    a = rng.uniform(0.7, 1.3, (N + 2, N + 2)) if variable else np.ones((N + 2, N + 2))
+    f = rng.standard_normal((B, n + 1, N * N))
+    u0 = rng.standard_normal(N * N)
+    uobs = rng.standard_normal((B, n, N * N))
+    ft = torch.tensor(f, device=dev, requires_grad=True)
+    at = torch.tensor(a, device=dev, requires_grad=True)
+    u0t = torch.tensor(u0, device=dev, requires_grad=True)
+    u = heat_solve(ft, at, u0t, theta=theta, rtol=1e-13)
+    loss = ((u - torch.tensor(uobs, device=dev)) ** 2).sum()
+    loss.backward()
+    gf, ga, gu0 = _oracle_grads(N, n, theta, a, f, u0, uobs)
+
+    def rel(x, y):
+        return float(np.abs(x - y).max() / np.abs(y).max())
+
+    assert rel(ft.grad.cpu().numpy(), gf) < 1e-9
+    assert rel(at.grad.cpu().numpy(), ga) < 1e-9
+    assert rel(u0t.grad.cpu().numpy(), gu0) < 1e-9
+    # central differences of the oracle's direct-solve loss along random directions
+    h = 1e-6
+    for grad, base, which in ((at.grad, a, "a"), (ft.grad, f, "f"), (u0t.grad, u0, "u0")):
+        d = rng.standard_normal(base.shape)
+        args = lambda e: dict(a_nodal=a + e * d if which == "a" else a, f=f + e * d if which == "f" else f,
+                              u0=u0 + e * d if which == "u0" else u0)
+        fd = (_loss_oracle(N, n, theta, uobs=uobs, **args(h)) - _loss_oracle(N, n, theta, uobs=uobs, **args(-h))) / (2 * h)
+        assert abs(fd - float(np.sum(grad.cpu().numpy() * d))) <= 1e-6 * max(1.0, abs(fd)), which
+
+
+def test_inverse_problem_full_size_sampled():
+    """The differentiable-solve workload at full size (N = 127, n = 256) for two of its 16
+    Gaussian-bump sources: gradients at a = 1 against the oracle's direct adjoint."""
+    from paper_2201_10062_amd.autograd import heat_solve
+    dev = _dev()
+    probs, a_truth = W.inverse_problem_2d(batch=2)
+    N, n = probs[0].N, probs[0].n
+    f = np.stack([p.f for p in probs])
+    u0 = np.zeros(N * N)
+    uobs = []
+    for p in probs:
+        s = System(2, N, n, theta=1.0, a_nodal=a_truth)
+        uobs.append(s.solve_direct(s.rhs(p.f, u0)).reshape(n, N * N))
+    uobs = np.stack(uobs)
+    a1 = np.ones((N + 2, N + 2))
+    ft = torch.tensor(f, device=dev, requires_grad=True)
+    at = torch.tensor(a1, device=dev, requires_grad=True)
+    u = heat_solve(ft, at, None, theta=1.0, rtol=1e-12)
+    loss = ((u - torch.tensor(uobs, device=dev)) ** 2).sum()
+    loss.backward()
+    gf, ga, _ = _oracle_grads(N, n, 1.0, a1, f, u0, uobs)
+    assert float(np.abs(at.grad.cpu().numpy() - ga).max() / np.abs(ga).max()) < 1e-7
+    assert float(np.abs(ft.grad.cpu().numpy() - gf).max() / np.abs(gf).max()) < 1e-7

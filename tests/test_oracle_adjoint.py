@@ -94,3 +94,14 @@ def test_nodal_gradient_is_face_scatter():
     da = rng.standard_normal((N + 2, N + 2))
     fx, fy = spatial.faces_from_nodal(da, 2)
     assert abs(np.sum(gn * da) - np.sum(gx * fx) - np.sum(gy * fy)) < 1e-12
+
+
+def test_adjoint_direct_matches_dense():
+    for scheme, theta in (("theta", 0.5), ("theta", 1.0), ("bdf2", 1.0)):
+        N, n = 4, 7
+        rng = np.random.default_rng(5)
+        ax, ay = rng.uniform(0.5, 2, (N, N + 1)), rng.uniform(0.5, 2, (N + 1, N))
+        s = System(2, N, n, scheme=scheme, theta=theta, ax=ax, ay=ay)
+        g = rng.standard_normal(n * s.m)
+        ld = adj.adjoint_dense(s, g)
+        assert np.abs(adj.adjoint_direct(s, g) - ld).max() < 1e-12 * np.abs(ld).max()
