@@ -73,6 +73,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB three times "
+                         "(the known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -84,6 +87,16 @@ def main() -> int:
     from paper_2201_10062_amd import Plan, smr
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.full((nel,), 1.0, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration_mib,
+                          "bytes_read": nel * 8, "bytes_written": nel * 8}), flush=True)
+        return 0
     p = W.crank_nicolson_2d_noisy()          # N = 127, n = 256, theta = 1/2, seed 0
     f = torch.from_numpy(p.f.reshape(-1)).to(dev)
     u0 = torch.from_numpy(p.u0).to(dev)
