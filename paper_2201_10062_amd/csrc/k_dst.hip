@@ -7,7 +7,7 @@
 // held in LDS (bit-reversed load, in-place decimation-in-time butterflies).  With
 // Z = FFT(z): (S_N a)_k = -Im(Z_k) / sqrt(2L) and (S_N b)_k = Re(Z_k) / sqrt(2L).
 // Each block owns `ppb` line pairs; all of its loads finish before any store, so the
-// transform may run in place.
+// transform may run in place (with equal input and output slice strides).
 #include "smr_internal.h"
 
 namespace smr {
@@ -16,6 +16,8 @@ namespace {
 
 struct DstP {
   int N, L, M, logM, m, nslices, ppb, tpp, dim, n;
+  int rows;                   // lines per slice: N (2D) or 1 (1D)
+  long sin, sout;             // slice strides of the input and the output (>= m)
   long nlines;
   double scale;               // 1/sqrt(2L)
   const double2 *tw;          // exp(-2 pi i t / M), t < M/2
@@ -32,13 +34,12 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Element address of line r, position j.
+// Offset of element j of line r inside its slice, and the slice of line r.
 template <int DIR>
-__device__ __forceinline__ size_t elem_addr(const DstP &d, long r, int j) {
-  if (DIR == 0) return (size_t)r * d.N + j;                 // rows are contiguous across slices
-  const long s = r / d.N;
-  const int i = (int)(r - s * d.N);
-  return (size_t)s * d.m + (size_t)j * d.N + i;             // column i of slice s
+__device__ __forceinline__ size_t in_slice(const DstP &d, long r, int j, long &s) {
+  s = r / d.rows;
+  const int i = (int)(r - s * d.rows);
+  return DIR == 0 ? (size_t)i * d.N + j : (size_t)j * d.N + i;   // row i, or column i
 }
 
 template <int DIR>
@@ -65,7 +66,12 @@ __global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ 
     if (DIR == 0) { c = e / d.N; j = e - c * d.N; }
     else { j = e / lpb; c = e - j * lpb; }
     const long r = r0 + c;
-    const double v = (r < d.nlines) ? in[elem_addr<DIR>(d, r, j)] : 0.0;
+    double v = 0.0;
+    if (r < d.nlines) {
+      long s;
+      const size_t q = in_slice<DIR>(d, r, j, s);
+      v = in[(size_t)s * d.sin + q];
+    }
     double2 *Xp = X + (size_t)(c >> 1) * d.M;
     const int i1 = bitrev(j + 1, d.logM), i2 = bitrev(d.M - (j + 1), d.logM);
     if (c & 1) { Xp[i1].y = v; Xp[i2].y = -v; }
@@ -98,13 +104,10 @@ __global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ 
     if (r >= d.nlines) continue;
     const double2 Z = X[(size_t)(c >> 1) * d.M + j + 1];
     double v = (c & 1) ? Z.x * d.scale : -Z.y * d.scale;
-    const size_t a = elem_addr<DIR>(d, r, j);
-    if (d.scale_mode == 1) {
-      const long s = (long)(a / d.m);
-      const size_t q = a - (size_t)s * d.m;
-      v /= d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q];
-    }
-    out[a] = v;
+    long s;
+    const size_t q = in_slice<DIR>(d, r, j, s);
+    if (d.scale_mode == 1) v /= d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q];
+    out[(size_t)s * d.sout + q] = v;
   }
 }
 
@@ -118,7 +121,9 @@ DstP make_dst(const Plan *p, int dir, int nslices) {
   d.n = p->n;
   d.dim = p->dim;
   d.nslices = nslices;
-  d.nlines = (long)nslices * (p->dim == 1 ? 1 : p->N);
+  d.rows = p->dim == 1 ? 1 : p->N;
+  d.nlines = (long)nslices * d.rows;
+  d.sin = d.sout = p->m;
   const int half = d.M / 2;
   if (dir == 0) {
     d.ppb = half >= 256 ? 1 : 256 / half;
@@ -141,9 +146,11 @@ DstP make_dst(const Plan *p, int dir, int nslices) {
 }  // namespace
 
 static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                          const Scal *gate) {
+                          const Scal *gate, long in_stride, long out_stride) {
   DstP d = make_dst(c.p, dir, nslices);
   d.scale_mode = scale_mode;
+  if (in_stride) d.sin = in_stride;
+  if (out_stride) d.sout = out_stride;
   const long lpb = 2L * d.ppb;
   const long nblocks = (d.nlines + lpb - 1) / lpb;
   const size_t shmem = ((size_t)d.ppb * d.M + d.M / 2) * sizeof(double2);
@@ -160,8 +167,8 @@ static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nsl
 }
 
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                      const Scal *gate) {
-  return run_dst(c, dir, in, out, nslices, scale_mode, gate);
+                      const Scal *gate, long in_stride, long out_stride) {
+  return run_dst(c, dir, in, out, nslices, scale_mode, gate, in_stride, out_stride);
 }
 
 }  // namespace smr

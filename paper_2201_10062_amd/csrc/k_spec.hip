@@ -65,13 +65,9 @@ __device__ __forceinline__ Coef coef_of(const SpecP &P, double tm) {
   return Coef{1.5 + tm, -2.0, 0.5};
 }
 
-// (T y)_t for one column of a row-major (n, m) array
-__device__ __forceinline__ double Tt(const double *__restrict__ y, int t, int m, int col, const Coef &k) {
-  double r = k.l0 * y[(size_t)t * m + col];
-  if (t >= 1) r += k.l1 * y[(size_t)(t - 1) * m + col];
-  if (t >= 2 && k.l2 != 0.0) r += k.l2 * y[(size_t)(t - 2) * m + col];
-  return r;
-}
+// Sine-basis vectors are (n, ld) row-major with the row stride ld a multiple of 32, so a
+// 32-mode column tile covers whole 256-byte (float64) or 128-byte (float32) lines per level.
+__device__ __forceinline__ size_t vat(int ld, int t, int q) { return (size_t)t * ld + q; }
 
 // 1/|re + i im| from a float reciprocal square root refined by two Newton steps in float64
 // (relative error ~1e-16, well inside the 1e-12 parity bound of the preconditioner).
@@ -250,7 +246,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   __shared__ int is_last;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n = P.n, m = P.m, h1 = P.h1, h2 = P.h2;
+  const int n = P.n, m = P.m, ld = P.ld, h1 = P.h1, h2 = P.h2;
   const int col0 = tile * C;
   const double va = sc->va, vb = sc->vb, zs = sc->zs;
   const double a1 = sc->a1, a2 = sc->a2, a3 = sc->a3, ceta = sc->ceta, zsl = sc->gamma_new;
@@ -267,6 +263,41 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
 
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
 
+  // ---- B (steady launches, streaming waves 4..7): lagged w_{j-1}, x_{j-1} and the true
+  //      residual of x_{j-1}, streamed over time levels with x carried for the stencil.  Each
+  //      group's levels are split between the two matrix-core windows.  The carries read the
+  //      previous group's last levels, so they are taken here, before any wave writes w or x.
+  const bool bwave = MODE == MODE_STEADY && wave >= 4;
+  const int bc = (tid - kThreads / 2) % C, bg = (tid - kThreads / 2) / C;
+  const bool bok = col0 + bc < m;
+  const int bcc = bok ? col0 + bc : m - 1;
+  const int bR = (n + G2 - 1) / G2;
+  const int bt0 = bwave ? min(n, bg * bR) : 0, bt1 = bwave ? min(n, bt0 + bR) : 0;
+  const int bmid = bt0 + (bt1 - bt0 + 1) / 2;
+  auto wnew = [&](size_t i) { return (zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1; };
+  double bx1 = 0.0, bx2 = 0.0;
+  if (bwave) {
+    if (bt0 >= 1) { const size_t i = vat(ld, bt0 - 1, bcc); bx1 = xv[i] + ceta * wnew(i); }
+    if (bt0 >= 2) { const size_t i = vat(ld, bt0 - 2, bcc); bx2 = xv[i] + ceta * wnew(i); }
+  }
+  auto bstream = [&](int ta, int tb) {
+    const Coef k = coef_of(P, P.tmu[bcc]);
+#pragma unroll 4
+    for (int t = ta; t < tb; ++t) {
+      const size_t i = vat(ld, t, bcc);
+      const double w = wnew(i);
+      const double x0 = xv[i] + ceta * w;
+      const double r = bh[i] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
+      if (bok) {
+        wb[i] = w;
+        xv[i] = x0;
+        acc_r += r * r;
+      }
+      bx2 = bx1;
+      bx1 = x0;
+    }
+  };
+
   // ---- A. v_{j+1}[o] (or v_1), o = n-1-t, streamed over time levels t in ascending order
   //        so that the stencil's previous level is a register carry.  LDS mirror layout:
   //        U[o] for o < h1, D[t] for o >= h1 (so that U[p] pairs with D[p] = row n-1-p).
@@ -279,12 +310,12 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
     auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? xv[i] : (double)zcur[i]; };
-    double y1 = t0 >= 1 ? src((size_t)(t0 - 1) * m + cc) : 0.0;
-    double y2 = t0 >= 2 ? src((size_t)(t0 - 2) * m + cc) : 0.0;
+    double y1 = t0 >= 1 ? src(vat(ld, t0 - 1, cc)) : 0.0;
+    double y2 = t0 >= 2 ? src(vat(ld, t0 - 2, cc)) : 0.0;
 #pragma unroll 4
     for (int t = t0; t < t1; ++t) {
       const int o = n - 1 - t;
-      const size_t it = (size_t)t * m + cc, io = (size_t)o * m + cc;
+      const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
       const double y0 = src(it);
       const double ty = k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
       double v;
@@ -328,36 +359,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
       for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
     gemm_tiles<HP, C, PR>(So, Se, U, D, wave, lane, ao, ae);
   } else if (MODE == MODE_STEADY) {
-    // ---- B. the streaming waves, part 1 of 2: lagged w_{j-1}, x_{j-1} and its true residual
-    //        over time levels t (x carried for the stencil); first half of the levels.
-    const int st = tid - kThreads / 2;
-    const int c = st % C, g = st / C;
-    const int col = col0 + c;
-    const bool ok = col < m;
-    const int cc = ok ? col : m - 1;
-    const Coef k = coef_of(P, P.tmu[cc]);
-    const int R = (n + G2 - 1) / G2;
-    const int t0 = g * R, t1 = min(n, t0 + R);
-    auto xnew = [&](int t) {
-      const size_t i = (size_t)t * m + cc;
-      return xv[i] + ceta * ((zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1);
-    };
-    double x1 = t0 >= 1 ? xnew(t0 - 1) : 0.0;
-    double x2 = t0 >= 2 ? xnew(t0 - 2) : 0.0;
-#pragma unroll 4
-    for (int t = t0; t < t1; ++t) {
-      const size_t i = (size_t)t * m + cc;
-      const double w = (zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1;
-      const double x0 = xv[i] + ceta * w;
-      const double r = bh[i] - (k.l0 * x0 + k.l1 * x1 + k.l2 * x2);
-      if (ok) {
-        wb[i] = w;
-        xv[i] = x0;
-        acc_r += r * r;
-      }
-      x2 = x1;
-      x1 = x0;
-    }
+    bstream(bt0, bmid);   // B, first half of each group's levels
   }
   __syncthreads();   // matrix-core waves are done reading U, D
   if (wave < 4) {
@@ -398,6 +400,8 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
     gemm_tiles<HP, C, PR>(SoT, SeT, U, D, wave, lane, ao, ae);
+  } else if (MODE == MODE_STEADY) {
+    bstream(bmid, bt1);   // B, second half
   }
   __syncthreads();   // U, D free again
   if (wave < 4) {
@@ -440,7 +444,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     for (int t = t0; t < t1; ++t) {
       const double y0 = zrow(t);
       if (ok) {
-        znext[(size_t)t * m + col] = (T)y0;
+        znext[vat(ld, t, col)] = (T)y0;
         acc_d += (k.l0 * y0 + k.l1 * y1 + k.l2 * y2) * zrow(n - 1 - t);
       }
       y2 = y1;
@@ -481,24 +485,35 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin in block order.  Give each XCD a
+// contiguous range of tiles instead, so that the tiles sharing a cache line at a row-segment
+// boundary (rows of m doubles are not line aligned) run side by side under the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  constexpr int kXcd = 8;
+  const int x = bid % kXcd, local = bid / kXcd;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
 void k_spec(SpecP P, int jph) {
-  spec_body<HP, C, MODE, PR>(P, jph, blockIdx.x);
+  spec_body<HP, C, MODE, PR>(P, jph, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched launch: the blocks of every instance in the table, instance found by its first block.
 template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
 void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (table[mid].tile0 <= (int)blockIdx.x) lo = mid;
+    if (table[mid].tile0 <= b) lo = mid;
     else hi = mid - 1;
   }
   const SpecP P = table[lo];
-  spec_body<HP, C, MODE, PR>(P, jph, (int)blockIdx.x - P.tile0);
+  spec_body<HP, C, MODE, PR>(P, jph, b - P.tile0);
 }
 
 template <int HP, int C, int PR>
@@ -571,7 +586,7 @@ int spec_blocks(const Plan *p) {
 
 SpecP spec_desc(const Plan *p, double *x, const double *bh) {
   SpecP P{};
-  P.n = p->n; P.m = p->m; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
+  P.n = p->n; P.m = p->m; P.ld = p->ld; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
   P.tiles = spec_blocks(p);
   P.tile0 = 0;
   const bool f32 = p->pprec == SMR_FP32;

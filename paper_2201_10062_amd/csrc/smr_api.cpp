@@ -125,6 +125,9 @@ int ilog2(int x) {
 }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// row stride of the sine-basis work vectors: whole 256-byte lines per 32-column tile
+int ld_of(size_t m) { return (int)((m + 31) / 32 * 32); }
+
 int hp_of(int h1) {
   int hp = 16;
   while (hp < h1) hp *= 2;
@@ -169,7 +172,7 @@ struct Layout {
 Layout layout_of(const smr_desc *d) {
   const int N = d->N, n = d->n, dim = d->dim;
   const size_t m = dim == 1 ? (size_t)N : (size_t)N * N;
-  const size_t len = m * n;
+  const size_t len = (size_t)ld_of(m) * n;   // every work vector holds n rows of ld
   const int hp = hp_of((n + 1) / 2);
   const int L = N + 1;
   Layout l{};
@@ -282,6 +285,8 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.n = d->n;
   p.m = d->dim == 1 ? d->N : d->N * d->N;
   p.len = (size_t)p.m * p.n;
+  p.ld = ld_of((size_t)p.m);
+  p.vlen = (size_t)p.ld * p.n;
   p.scheme = d->scheme;
   p.precond = d->precond;
   p.pprec = d->pprec;
@@ -438,12 +443,12 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.Sef = (float *)(base_ptr + lay.Sef);
   p.SeTf = (float *)(base_ptr + lay.SeTf);
   for (int i = 0; i < 3; ++i)
-    p.ZF[i] = (float *)(base_ptr + lay.zf + (size_t)i * align256(sizeof(float) * p.len));
+    p.ZF[i] = (float *)(base_ptr + lay.zf + (size_t)i * align256(sizeof(float) * p.vlen));
   p.gface = (double *)(base_ptr + lay.gface);
   p.part = (double *)(base_ptr + lay.part);
   p.sc = (Scal *)(base_ptr + lay.sc);
   p.counter = (int *)(base_ptr + lay.cnt);
-  const size_t vstride = align256(sizeof(double) * p.len);
+  const size_t vstride = align256(sizeof(double) * p.vlen);
   double *vec[12] = {};
   for (int i = 0; i < lay.nvec; ++i) vec[i] = (double *)(base_ptr + lay.vec0 + (size_t)i * vstride);
   p.V[0] = vec[0]; p.V[1] = vec[1];
@@ -552,12 +557,19 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   return SMR_OK;
 }
 
-// spatial sine transform of every time slice (involutory: the same call transforms back)
-smr_status spatial_dst(const Plan &p, hipStream_t s, const double *in, double *out) {
+// spatial sine transform of every time slice (involutory: the same call transforms back);
+// slice strides of in and out (m for physical vectors, ld for sine-basis ones)
+smr_status spatial_dst(const Plan &p, hipStream_t s, const double *in, double *out, long in_ld, long out_ld) {
   Ctx c{&p, s};
-  LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, nullptr));
-  if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, nullptr));
+  LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, nullptr, in_ld, out_ld));
+  if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, nullptr, out_ld, out_ld));
   return SMR_OK;
+}
+smr_status to_sine_basis(const Plan &p, hipStream_t s, const double *in, double *out) {
+  return spatial_dst(p, s, in, out, p.m, p.ld);
+}
+smr_status from_sine_basis(const Plan &p, hipStream_t s, const double *in, double *out) {
+  return spatial_dst(p, s, in, out, p.ld, p.m);
 }
 
 smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
@@ -583,18 +595,18 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
                            smr_info *info) {
   Ctx c{&p, s};
   double *Bh = p.T1, *Xh = p.T2;
-  smr_status st = spatial_dst(p, s, b, Bh);
+  smr_status st = to_sine_basis(p, s, b, Bh);
   if (st != SMR_OK) return st;
-  st = spatial_dst(p, s, x, Xh);
+  st = to_sine_basis(p, s, x, Xh);
   if (st != SMR_OK) return st;
   Scal h{};
   h.rtol = rtol;
   h.maxit = maxit;
   h.status = RUNNING;
   HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
-  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
   LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
   LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
   const Profiler::Mark m0 = g_prof.mark();
@@ -621,7 +633,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   if (h.status == DONE_CONV && h.bnorm == 0.0) {
     LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
   } else {
-    st = spatial_dst(p, s, Xh, x);
+    st = from_sine_basis(p, s, Xh, x);
     if (st != SMR_OK) return st;
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -639,9 +651,9 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, doub
   h.maxit = maxit;
   h.status = RUNNING;
   HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
-  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
+  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
   double *part = p.part, *part2 = p.part + 2 * kRedSlots;
   int nb = 0, nb2 = 0;
   // v_1 = Y b - Y T x0, ||v_1||^2, ||b||^2
@@ -787,18 +799,18 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     for (int k = 0; k < ns; ++k) {
       const Plan &p = plans[spec_ids[k]]->p;
       Ctx c{&p, s};
-      smr_status st = spatial_dst(p, s, b[spec_ids[k]], p.T1);
+      smr_status st = to_sine_basis(p, s, b[spec_ids[k]], p.T1);
       if (st != SMR_OK) return st;
-      st = spatial_dst(p, s, x[spec_ids[k]], p.T2);
+      st = to_sine_basis(p, s, x[spec_ids[k]], p.T2);
       if (st != SMR_OK) return st;
       Scal h{};
       h.rtol = rtol;
       h.maxit = maxit;
       h.status = RUNNING;
       HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
-      LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.len));
-      LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.len));
-      LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.len));
+      LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
+      LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
+      LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
       LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
     }
     HIP_TRY(hipMemcpyAsync(d_table, table.data(), sizeof(SpecP) * ns, hipMemcpyHostToDevice, s));
@@ -834,7 +846,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       if (hs[k].status == DONE_CONV && hs[k].bnorm == 0.0) {
         LAUNCH(PROF_VEC, launch_zero(c, x[i], p.len));
       } else {
-        smr_status st = spatial_dst(p, s, p.T2, x[i]);
+        smr_status st = from_sine_basis(p, s, p.T2, x[i]);
         if (st != SMR_OK) return st;
       }
       smr_status st = finish_info(hs[k], maxit, &infos[i]);

@@ -38,6 +38,8 @@ struct Plan {
   // parameters
   int dim, N, n, m, scheme, precond, pprec, cheb_k, flags;
   size_t len;                 // n*m
+  int ld;                     // row stride of the sine-basis vectors: m rounded up to 32
+  size_t vlen;                // n*ld: elements of every work vector
   double T, tau, theta, h, h2inv;
   bool const_coef;            // every face value equal
   double a_min, a_max, abar, cheb_lo, cheb_hi;
@@ -53,7 +55,7 @@ struct Plan {
   double *So, *SoT, *Se, *SeT;  // folded time sine blocks in MFMA fragment order (hp*hp)
   float *Sof, *SoTf, *Sef, *SeTf;  // the same in float32 (mixed precision)
   double *tw;                 // complex twiddles exp(-2 pi i t / (2L)), t < L (interleaved)
-  // vectors (device), each len doubles
+  // vectors (device), each vlen doubles (physical-basis use: stride m; sine basis: stride ld)
   double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
@@ -82,10 +84,11 @@ hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const dou
                              double *gax, double *gay, double *gnodal);
 
 // Spatial sine transform (orthonormal DST-I) along x (dir 0) or y (dir 1) of nslices
-// slices; in-place allowed.  scale_mode 1 divides the result by the Chebyshev inner
-// diagonal eta_s + zeta_s * abar * tau * mu_lap.
+// slices; in-place allowed when the strides agree.  Slice strides of in and out default
+// (0) to m.  scale_mode 1 divides the result by the Chebyshev inner diagonal
+// eta_s + zeta_s * abar * tau * mu_lap.
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                      const Scal *gate);
+                      const Scal *gate, long in_stride = 0, long out_stride = 0);
 // Time transform: mode 0: out = (S_n (x) I) in; mode 1: out = (S_n (x) I) diag(1/sigma) (S_n (x) I) in
 // with partial sums of <D vhat, vhat> into part when part != null.
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nblocks_out,
@@ -111,11 +114,11 @@ hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, cons
 // One instance of the sine-basis solve as the fused kernel sees it (also the element of the
 // device descriptor table of a batched launch).
 struct SpecP {
-  int n, m, h1, h2, scheme, tiles, tile0, pad;
+  int n, m, ld, h1, h2, scheme, tiles, tile0;   // ld: row stride of the vectors below
   double theta;
   const void *So, *SoT, *Se, *SeT;   // folded sine tables in the transform's precision
   const double *tcoef, *tmu;
-  // vectors (spatial-sine basis); z in the transform's precision.  Launch j uses
+  // vectors (spatial-sine basis, (n, ld) row-major); z in the transform's precision.  Launch j uses
   // z_j = Z[(j-1)%3], z_{j+1} = Z[j%3], z_{j-1} = Z[(j+1)%3], v_j = V[j%2], v_{j-1} = V[(j+1)%2]
   // (overwritten by v_{j+1}), w_{j-2} = W[j%2], w_{j-3} = W[(j+1)%2] (overwritten by w_{j-1}).
   void *Z[3];
