@@ -85,25 +85,38 @@ __device__ __forceinline__ double inv_sigma(const SpecP &P, int tmode, double t)
   return rsqrt64(re * re + im * im);
 }
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// A block-uniform float64 moved to scalar registers (keeps the vector registers for the
+// matrix-core accumulators and the streaming carries).
+__device__ __forceinline__ double uni(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sums of four values over the block, in a fixed order; the result is valid in thread 0.
+__device__ __forceinline__ void block_sum4(double (&v)[4], double (*red)[kWaves]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x >> 6] = v[q];
   __syncthreads();
-  double s = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < kWaves; ++w) s += red[w];
-  return s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += red[q][w];
+      v[q] = s;
+    }
 }
 
-__device__ __forceinline__ double ld_agent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// MINRES scalar recurrence for one launch (thread 0 of the last block).
-template <int MODE>
-__device__ void scalar_update(Scal *sc, double s0, double s1, double s2, double s3) {
-  if (MODE == MODE_INIT) {
+// MINRES scalar recurrence after launch j-1, whose mode was pmode, from the block sums of
+// that launch (run by thread 0 of every block of launch j).
+__device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double s2, double s3) {
+  if (pmode == MODE_INIT) {
     // s0 = ||v_1||^2, s1 = ||b||^2, s2 = gamma_1^2, s3 = <T^ z_1, z_1>
     sc->bnorm = sqrt(s1);
     sc->iter = 0;
@@ -125,7 +138,7 @@ __device__ void scalar_update(Scal *sc, double s0, double s1, double s2, double 
   }
   // s0 = ||r(x_{j-1})||^2 (STEADY), s2 = gamma_{j+1}^2, s3 = <T^ z_{j+1}, z_{j+1}>
   sc->iter += 1;                                  // launches since INIT = j
-  if (MODE == MODE_STEADY) {
+  if (pmode == MODE_STEADY) {
     sc->relres = sqrt(s0) / sc->bnorm;            // of x_{j-1}
     if (sc->relres <= sc->rtol || sc->exact) { sc->iter -= 1; sc->status = DONE_CONV; return; }
     if (sc->iter - 1 >= sc->maxit) { sc->iter -= 1; sc->status = DONE_MAXIT; return; }
@@ -158,83 +171,84 @@ __device__ void scalar_update(Scal *sc, double s0, double s1, double s2, double 
 }
 
 // GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
-// CT column tiles, ao[i][ct] += A_o[r] * U[:, ct] and ae[i][ct] += A_e[r] * D[:, ct] over the
-// k dimension.  One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps
-// 2q and 2q+1 side by side per lane, so one load fetches two k-steps; loads run two such
-// pairs (four k-steps) ahead of the matrix cores.
+// CT column tiles, acc[i][ct] += A[r] * B[:, ct] over the k dimension, with B the LDS block.
+// One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps 2q and 2q+1 side
+// by side per lane, so one load fetches two k-steps; loads run one such pair ahead.
 template <int HP, int C, int PR>
-__device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ Ao,
-                                           const typename Prec<PR>::T *__restrict__ Ae,
-                                           const typename Prec<PR>::T *U, const typename Prec<PR>::T *D,
-                                           int wave, int lane,
-                                           typename Prec<PR>::Acc (&ao)[(HP / 16 + 3) / 4][C / 16],
-                                           typename Prec<PR>::Acc (&ae)[(HP / 16 + 3) / 4][C / 16]) {
+__device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ A,
+                                           const typename Prec<PR>::T *Bs, int wave, int lane,
+                                           typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16]) {
   typedef typename Prec<PR>::T T;
   typedef typename std::conditional<PR == 0, double2, float2>::type T2;
   constexpr int LD = C + 1;
   constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
   constexpr int KS = HP / 4, KP = KS / 2;         // k-steps, k-step pairs
   const int bk = lane >> 4, bj = lane & 15;
-  const T2 *__restrict__ Ao2 = reinterpret_cast<const T2 *>(Ao);
-  const T2 *__restrict__ Ae2 = reinterpret_cast<const T2 *>(Ae);
+  const T2 *__restrict__ A2 = reinterpret_cast<const T2 *>(A);
   const T2 zero2 = {T(0), T(0)};
-  T2 q0u[RPW], q0d[RPW], q1u[RPW], q1d[RPW];
+  const typename Prec<PR>::Acc zacc = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[i][ct] = zacc;
+  T2 q0[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int r = wave + 4 * i;
-    const size_t base = (size_t)r * KP * 64 + lane;
-    const bool ok = r < RT;
-    q0u[i] = ok ? Ao2[base] : zero2;
-    q0d[i] = ok ? Ae2[base] : zero2;
-    q1u[i] = (ok && KP > 1) ? Ao2[base + 64] : zero2;
-    q1d[i] = (ok && KP > 1) ? Ae2[base + 64] : zero2;
+    q0[i] = r < RT ? A2[(size_t)r * KP * 64 + lane] : zero2;
   }
   for (int kp = 0; kp < KP; ++kp) {
-    T2 q2u[RPW], q2d[RPW];
+    T2 q1[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int r = wave + 4 * i;
-      const bool more = r < RT && kp + 2 < KP;
-      const size_t at = ((size_t)r * KP + kp + 2) * 64 + lane;
-      q2u[i] = more ? Ao2[at] : zero2;
-      q2d[i] = more ? Ae2[at] : zero2;
+      q1[i] = (r < RT && kp + 1 < KP) ? A2[((size_t)r * KP + kp + 1) * 64 + lane] : zero2;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int kk = 2 * kp + h;
-      T bu[CT], bd[CT];
+      T b[CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        bu[ct] = U[(4 * kk + bk) * LD + 16 * ct + bj];
-        bd[ct] = D[(4 * kk + bk) * LD + 16 * ct + bj];
-      }
+      for (int ct = 0; ct < CT; ++ct) b[ct] = Bs[(4 * kk + bk) * LD + 16 * ct + bj];
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         if (wave + 4 * i < RT) {
-          const T au = h ? q0u[i].y : q0u[i].x;
-          const T ad = h ? q0d[i].y : q0d[i].x;
+          const T a = h ? q0[i].y : q0[i].x;
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            ao[i][ct] = Prec<PR>::mfma(au, bu[ct], ao[i][ct]);
-            ae[i][ct] = Prec<PR>::mfma(ad, bd[ct], ae[i][ct]);
-          }
+          for (int ct = 0; ct < CT; ++ct) acc[i][ct] = Prec<PR>::mfma(a, b[ct], acc[i][ct]);
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      q0u[i] = q1u[i]; q0d[i] = q1d[i];
-      q1u[i] = q2u[i]; q1d[i] = q2d[i];
+    for (int i = 0; i < RPW; ++i) q0[i] = q1[i];
+  }
+}
+
+// Accumulator tiles of the four matrix-core waves -> LDS rows, in the accumulator layout of
+// the transform's precision.
+template <int HP, int C, int PR>
+__device__ __forceinline__ void store_acc(const typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16],
+                                          typename Prec<PR>::T *Dst, int wave, int lane) {
+  constexpr int LD = C + 1;
+  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
+  const int bk = lane >> 4, bj = lane & 15;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + 4 * i;
+    if (r >= RT) continue;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int cl = 16 * ct + bj;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Dst[(16 * r + Prec<PR>::row(q, bk)) * LD + cl] = acc[i][ct][q];
     }
   }
 }
 
 template <int HP, int C, int MODE, int PR>
-__device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const int tile) {
+__device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const int pmode, const int tile) {
   typedef typename Prec<PR>::T T;
   typedef typename Prec<PR>::Acc Acc;
-  Scal *sc = P.sc;
-  if (MODE != MODE_INIT && sc->status != RUNNING) return;
   constexpr int LD = C + 1;
   constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
   constexpr int G = kThreads / C;          // row groups when all 8 waves stream
@@ -242,15 +256,42 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   extern __shared__ double lds_raw[];
   T *U = reinterpret_cast<T *>(lds_raw);   // [HP][LD]
   T *D = U + HP * LD;                      // [HP][LD]
-  __shared__ double red[kWaves];
-  __shared__ int is_last;
+  __shared__ double red[4][kWaves];
+  __shared__ Scal S;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = P.n, m = P.m, ld = P.ld, h1 = P.h1, h2 = P.h2;
   const int col0 = tile * C;
-  const double va = sc->va, vb = sc->vb, zs = sc->zs;
-  const double a1 = sc->a1, a2 = sc->a2, a3 = sc->a3, ceta = sc->ceta, zsl = sc->gamma_new;
   const int j = jph;   // launch index modulo 6 (rotation phase); INIT uses the j = 0 slots
+
+  // ---- 0. the scalars of this launch: every block reduces the partial sums of launch j-1 (in
+  //         the same fixed order, so all blocks agree bit for bit) and steps the recurrence;
+  //         the block of tile 0 publishes the new state.  Scalar states and partial sums
+  //         alternate between two slots by launch parity.
+  if (MODE != MODE_INIT) {
+    const Scal *sprev = P.sc + ((j + 1) & 1);
+    Scal *snew = P.sc + (j & 1);
+    if (sprev->status != RUNNING) {             // stopped earlier: pass the state on
+      if (tile == 0 && tid == 0) *snew = *sprev;
+      return;
+    }
+    const double *pp = P.part + (size_t)((j + 1) & 1) * 4 * P.tiles;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = tid; b < P.tiles; b += kThreads) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] += pp[4 * (size_t)b + q];
+    }
+    block_sum4(t, red);
+    if (tid == 0) {
+      S = *sprev;
+      scalar_update(&S, pmode, t[0], t[1], t[2], t[3]);
+      if (tile == 0) *snew = S;
+    }
+    __syncthreads();
+    if (S.status != RUNNING) return;
+  }
+  const double va = uni(S.va), vb = uni(S.vb), zs = uni(S.zs);
+  const double a1 = uni(S.a1), a2 = uni(S.a2), a3 = uni(S.a3), ceta = uni(S.ceta), zsl = uni(S.gamma_new);
   const T *__restrict__ zcur = reinterpret_cast<const T *>(P.Z[(j + 2) % 3]);
   const T *__restrict__ zprev = reinterpret_cast<const T *>(P.Z[(j + 1) % 3]);
   T *__restrict__ znext = reinterpret_cast<T *>(MODE == MODE_INIT ? P.Z[0] : P.Z[j % 3]);
@@ -265,7 +306,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
 
   // ---- B (steady launches, streaming waves 4..7): lagged w_{j-1}, x_{j-1} and the true
   //      residual of x_{j-1}, streamed over time levels with x carried for the stencil.  Each
-  //      group's levels are split between the two matrix-core windows.  The carries read the
+  //      group's levels are split between the four matrix-core passes.  The carries read the
   //      previous group's last levels, so they are taken here, before any wave writes w or x.
   const bool bwave = MODE == MODE_STEADY && wave >= 4;
   const int bc = (tid - kThreads / 2) % C, bg = (tid - kThreads / 2) / C;
@@ -273,7 +314,9 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   const int bcc = bok ? col0 + bc : m - 1;
   const int bR = (n + G2 - 1) / G2;
   const int bt0 = bwave ? min(n, bg * bR) : 0, bt1 = bwave ? min(n, bt0 + bR) : 0;
-  const int bmid = bt0 + (bt1 - bt0 + 1) / 2;
+  int bq[5];                                   // B's levels split in four, one per GEMM pass
+#pragma unroll
+  for (int q = 0; q <= 4; ++q) bq[q] = bt0 + ((bt1 - bt0) * q + 3) / 4;
   auto wnew = [&](size_t i) { return (zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1; };
   double bx1 = 0.0, bx2 = 0.0;
   if (bwave) {
@@ -282,7 +325,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
   auto bstream = [&](int ta, int tb) {
     const Coef k = coef_of(P, P.tmu[bcc]);
-#pragma unroll 4
+#pragma unroll 2
     for (int t = ta; t < tb; ++t) {
       const size_t i = vat(ld, t, bcc);
       const double w = wnew(i);
@@ -312,7 +355,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? xv[i] : (double)zcur[i]; };
     double y1 = t0 >= 1 ? src(vat(ld, t0 - 1, cc)) : 0.0;
     double y2 = t0 >= 2 ? src(vat(ld, t0 - 2, cc)) : 0.0;
-#pragma unroll 4
+#pragma unroll 2
     for (int t = t0; t < t1; ++t) {
       const int o = n - 1 - t;
       const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
@@ -347,86 +390,56 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
   __syncthreads();
 
-  Acc ao[RPW][CT], ae[RPW][CT];
-  const Acc zacc = {0, 0, 0, 0};
+  // ---- C. the matrix-core waves: z = S_o^T D_o S_o u | S_e^T D_e S_e d, one table per pass
+  //         (each result goes back to LDS once every wave is done reading that block); the
+  //         streaming waves run a quarter of B beside each pass.
+  Acc acc[RPW][CT];
   const T *So = reinterpret_cast<const T *>(P.So), *Se = reinterpret_cast<const T *>(P.Se);
   const T *SoT = reinterpret_cast<const T *>(P.SoT), *SeT = reinterpret_cast<const T *>(P.SeT);
-  if (wave < 4) {
-    // ---- C. the matrix-core waves: z = S_o^T D_o S_o u | S_e^T D_e S_e d
-#pragma unroll
-    for (int i = 0; i < RPW; ++i)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
-    gemm_tiles<HP, C, PR>(So, Se, U, D, wave, lane, ao, ae);
-  } else if (MODE == MODE_STEADY) {
-    bstream(bt0, bmid);   // B, first half of each group's levels
-  }
-  __syncthreads();   // matrix-core waves are done reading U, D
-  if (wave < 4) {
-    // scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
-    const int bk = lane >> 4, bj = lane & 15;
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int r = wave + 4 * i;
-      if (r >= RT) continue;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int cl = 16 * ct + bj, col = col0 + cl;
-        const double tm = P.tmu[col < m ? col : m - 1];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int pp = 16 * r + Prec<PR>::row(q, bk);
-          double so = 0.0, se = 0.0;
-          if (col < m && pp < h1) {
-            const double a = (double)ao[i][ct][q];
-            so = a * inv_sigma(P, 2 * pp, tm);
-            acc_g += a * so;
-          }
-          if (col < m && pp < h2) {
-            const double a = (double)ae[i][ct][q];
-            se = a * inv_sigma(P, 2 * pp + 1, tm);
-            acc_g += a * se;
-          }
-          U[pp * LD + cl] = (T)so;
-          D[pp * LD + cl] = (T)se;
-        }
-      }
-    }
-  }
+  if (wave < 4) gemm_tiles<HP, C, PR>(So, U, wave, lane, acc);
+  else if (MODE == MODE_STEADY) bstream(bq[0], bq[1]);
   __syncthreads();
   if (wave < 4) {
-#pragma unroll
-    for (int i = 0; i < RPW; ++i)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) { ao[i][ct] = zacc; ae[i][ct] = zacc; }
-    gemm_tiles<HP, C, PR>(SoT, SeT, U, D, wave, lane, ao, ae);
+    store_acc<HP, C, PR>(acc, U, wave, lane);     // S_o u -> U
+    gemm_tiles<HP, C, PR>(Se, D, wave, lane, acc);
   } else if (MODE == MODE_STEADY) {
-    bstream(bmid, bt1);   // B, second half
+    bstream(bq[1], bq[2]);
   }
-  __syncthreads();   // U, D free again
-  if (wave < 4) {
-    // z_p = u'_p + d'_p -> U[p]; z_{n-1-p} = u'_p - d'_p -> D[p]; odd n: middle z_p = u'_p
-    const int bk = lane >> 4, bj = lane & 15;
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int r = wave + 4 * i;
-      if (r >= RT) continue;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int cl = 16 * ct + bj;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int pp = 16 * r + Prec<PR>::row(q, bk);
-          if (pp < h2) {
-            U[pp * LD + cl] = ao[i][ct][q] + ae[i][ct][q];
-            D[pp * LD + cl] = ao[i][ct][q] - ae[i][ct][q];
-          } else if (pp < h1) {
-            U[pp * LD + cl] = ao[i][ct][q];
-          }
-        }
-      }
+  __syncthreads();
+  if (wave < 4) store_acc<HP, C, PR>(acc, D, wave, lane);   // S_e d -> D
+  __syncthreads();
+  // scale by 1/sigma (time mode 2p+1 is row p of U, mode 2p+2 row p of D) and the Parseval
+  // partial of gamma^2, all waves; rows past h1 / h2 and columns past m stay zero
+  for (int e = tid; e < HP * C; e += kThreads) {
+    const int pp = e / C, cl = e - pp * C, col = col0 + cl;
+    const bool okc = col < m;
+    const double tm = P.tmu[okc ? col : m - 1];
+    double so = 0.0, se = 0.0;
+    if (okc && pp < h1) {
+      const double a = (double)U[pp * LD + cl];
+      so = a * inv_sigma(P, 2 * pp, tm);
+      acc_g += a * so;
     }
+    if (okc && pp < h2) {
+      const double a = (double)D[pp * LD + cl];
+      se = a * inv_sigma(P, 2 * pp + 1, tm);
+      acc_g += a * se;
+    }
+    U[pp * LD + cl] = (T)so;
+    D[pp * LD + cl] = (T)se;
   }
+  __syncthreads();
+  if (wave < 4) gemm_tiles<HP, C, PR>(SoT, U, wave, lane, acc);
+  else if (MODE == MODE_STEADY) bstream(bq[2], bq[3]);
+  __syncthreads();
+  if (wave < 4) {
+    store_acc<HP, C, PR>(acc, U, wave, lane);     // u' -> U
+    gemm_tiles<HP, C, PR>(SeT, D, wave, lane, acc);
+  } else if (MODE == MODE_STEADY) {
+    bstream(bq[3], bq[4]);
+  }
+  __syncthreads();
+  if (wave < 4) store_acc<HP, C, PR>(acc, D, wave, lane);   // d' -> D
   __syncthreads();
 
   // ---- D. store z_{j+1} and accumulate <(Y T)^ z, z> = sum_t (T z)_t z_{n-1-t}
@@ -437,10 +450,15 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const Coef k = coef_of(P, P.tmu[ok ? col : m - 1]);
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
-    auto zrow = [&](int t) -> double { return (double)(t < h1 ? U[t * LD + c] : D[(n - 1 - t) * LD + c]); };
+    // z_p = u'_p + d'_p and z_{n-1-p} = u'_p - d'_p (p < h2); odd n: the middle z_p = u'_p
+    auto zrow = [&](int t) -> double {
+      if (t < h1) return t < h2 ? (double)(T)(U[t * LD + c] + D[t * LD + c]) : (double)U[t * LD + c];
+      const int p = n - 1 - t;
+      return (double)(T)(U[p * LD + c] - D[p * LD + c]);
+    };
     double y1 = t0 >= 1 ? zrow(t0 - 1) : 0.0;
     double y2 = t0 >= 2 ? zrow(t0 - 2) : 0.0;
-#pragma unroll 4
+#pragma unroll 2
     for (int t = t0; t < t1; ++t) {
       const double y0 = zrow(t);
       if (ok) {
@@ -452,42 +470,18 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     }
   }
 
-  // ---- E. block partials, last block reduces in a fixed order and steps the scalars
-  const double s0 = block_sum(acc_r, red);
-  const double s1 = block_sum(acc_b, red);
-  const double s2 = block_sum(acc_g, red);
-  const double s3 = block_sum(acc_d, red);
+  // ---- E. block partials of this launch (reduced at the start of the next one)
+  double t[4] = {acc_r, acc_b, acc_g, acc_d};
+  block_sum4(t, red);
   if (tid == 0) {
-    double *pp = P.part + 4 * (size_t)tile;
-    pp[0] = s0; pp[1] = s1; pp[2] = s2; pp[3] = s3;
-    __threadfence();
-    const int ticket = atomicAdd(P.counter, 1);
-    is_last = (ticket == P.tiles - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-  for (int b = tid; b < P.tiles; b += kThreads) {
-    const double *pp = P.part + 4 * (size_t)b;
-    t0 += ld_agent(pp + 0);
-    t1 += ld_agent(pp + 1);
-    t2 += ld_agent(pp + 2);
-    t3 += ld_agent(pp + 3);
-  }
-  t0 = block_sum(t0, red);
-  t1 = block_sum(t1, red);
-  t2 = block_sum(t2, red);
-  t3 = block_sum(t3, red);
-  if (tid == 0) {
-    scalar_update<MODE>(sc, t0, t1, t2, t3);
-    *P.counter = 0;
+    double *pp = P.part + (size_t)(j & 1) * 4 * P.tiles + 4 * (size_t)tile;
+    pp[0] = t[0]; pp[1] = t[1]; pp[2] = t[2]; pp[3] = t[3];
   }
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin in block order.  Give each XCD a
-// contiguous range of tiles instead, so that the tiles sharing a cache line at a row-segment
-// boundary (rows of m doubles are not line aligned) run side by side under the same L2.
+// contiguous range of tiles instead, so that neighbouring tiles run side by side under the
+// same L2.
 __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   constexpr int kXcd = 8;
   const int x = bid % kXcd, local = bid / kXcd;
@@ -497,14 +491,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 
 template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
-void k_spec(SpecP P, int jph) {
-  spec_body<HP, C, MODE, PR>(P, jph, xcd_tile(blockIdx.x, gridDim.x));
+void k_spec(SpecP P, int jph, int pmode) {
+  spec_body<HP, C, MODE, PR>(P, jph, pmode, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched launch: the blocks of every instance in the table, instance found by its first block.
 template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HP >= 256 ? 2 : 4, 8)))
-void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph) {
+void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph, int pmode) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
@@ -513,25 +507,25 @@ void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph) {
     else hi = mid - 1;
   }
   const SpecP P = table[lo];
-  spec_body<HP, C, MODE, PR>(P, jph, b - P.tile0);
+  spec_body<HP, C, MODE, PR>(P, jph, pmode, b - P.tile0);
 }
 
 template <int HP, int C, int PR>
-hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jph) {
+hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
     hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
-  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
-  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
-  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph);
+  if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
+  else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
+  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
   return hipGetLastError();
 }
 
 template <int HP, int C, int PR>
-hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int jph) {
+hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
     hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
@@ -539,37 +533,37 @@ hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mod
     hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0)
-    hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_spec_multi<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
   else
-    hipLaunchKernelGGL((k_spec_multi<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph);
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
   return hipGetLastError();
 }
 
 template <int PR>
-hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph) {
+hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
-    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks, jph);
-    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks, jph);
-    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks, jph);
-    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks, jph);
-    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks, jph);
-    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks, jph);
+    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks, jph, pmode);
+    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks, jph, pmode);
+    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks, jph, pmode);
+    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks, jph, pmode);
+    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks, jph, pmode);
+    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks, jph, pmode);
     default: break;
   }
   return hipErrorInvalidValue;
 }
 
 template <int PR>
-hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph) {
+hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
-    case 16: return run_spec_multi<16, 32, PR>(st, table, ninst, mode, blocks, jph);
-    case 32: return run_spec_multi<32, 32, PR>(st, table, ninst, mode, blocks, jph);
-    case 64: return run_spec_multi<64, 32, PR>(st, table, ninst, mode, blocks, jph);
-    case 128: return run_spec_multi<128, 32, PR>(st, table, ninst, mode, blocks, jph);
-    case 256: return run_spec_multi<256, 16, PR>(st, table, ninst, mode, blocks, jph);
-    case 512: return run_spec_multi<512, 16, PR>(st, table, ninst, mode, blocks, jph);
+    case 16: return run_spec_multi<16, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 32: return run_spec_multi<32, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 64: return run_spec_multi<64, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 128: return run_spec_multi<128, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 256: return run_spec_multi<256, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 512: return run_spec_multi<512, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -597,32 +591,35 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh) {
   P.tcoef = p->tcoef; P.tmu = p->tmu;
   for (int i = 0; i < 3; ++i) P.Z[i] = f32 ? (void *)p->ZF[i] : (void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
   P.V[0] = p->V[0]; P.V[1] = p->V[1]; P.W[0] = p->W[0]; P.W[1] = p->W[1];
-  P.x = x; P.bh = bh; P.part = p->part; P.counter = p->counter; P.sc = p->sc;
+  P.x = x; P.bh = bh; P.part = p->part; P.sc = p->sc;
   return P;
 }
+
+// mode of launch j - 1, whose partial sums launch j reduces
+static int prev_mode(int mode, int j) { return mode == MODE_FIRST ? MODE_INIT : (j == 2 ? MODE_FIRST : MODE_STEADY); }
 
 hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh) {
   const Plan *p = c.p;
   const SpecP P = spec_desc(p, x, bh);
-  const int jph = j % 6;
-  return p->pprec == SMR_FP32 ? run_spec_hp<1>(c.st, P, mode, P.tiles, p->hp, jph)
-                              : run_spec_hp<0>(c.st, P, mode, P.tiles, p->hp, jph);
+  const int jph = j % 6, pmode = prev_mode(mode, j);
+  return p->pprec == SMR_FP32 ? run_spec_hp<1>(c.st, P, mode, P.tiles, p->hp, jph, pmode)
+                              : run_spec_hp<0>(c.st, P, mode, P.tiles, p->hp, jph, pmode);
 }
 
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
                              int j) {
-  const int jph = j % 6;
-  return pprec == SMR_FP32 ? run_multi_hp<1>(st, table, ninst, mode, blocks, hp, jph)
-                           : run_multi_hp<0>(st, table, ninst, mode, blocks, hp, jph);
+  const int jph = j % 6, pmode = prev_mode(mode, j);
+  return pprec == SMR_FP32 ? run_multi_hp<1>(st, table, ninst, mode, blocks, hp, jph, pmode)
+                           : run_multi_hp<0>(st, table, ninst, mode, blocks, hp, jph, pmode);
 }
 
-__global__ void k_gather_scal(const SpecP *__restrict__ table, int ninst, Scal *__restrict__ out) {
+__global__ void k_gather_scal(const SpecP *__restrict__ table, int ninst, int slot, Scal *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ninst) out[i] = *table[i].sc;
+  if (i < ninst) out[i] = table[i].sc[slot];
 }
 
-hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, Scal *out) {
-  hipLaunchKernelGGL(k_gather_scal, dim3((ninst + 63) / 64), dim3(64), 0, st, table, ninst, out);
+hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int slot, Scal *out) {
+  hipLaunchKernelGGL(k_gather_scal, dim3((ninst + 63) / 64), dim3(64), 0, st, table, ninst, slot, out);
   return hipGetLastError();
 }
 

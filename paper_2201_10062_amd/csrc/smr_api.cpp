@@ -164,7 +164,7 @@ smr_status validate(const smr_desc *d) {
 }
 
 struct Layout {
-  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, cnt, vec0;
+  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, vec0;
   int nvec;
   size_t total;
 };
@@ -201,8 +201,7 @@ Layout layout_of(const smr_desc *d) {
   l.tw = take(sizeof(double) * 2 * (size_t)L);
   l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
   l.part = take(sizeof(double) * 16 * (size_t)kRedSlots);
-  l.sc = take(sizeof(Scal));
-  l.cnt = take(sizeof(int) * 64);
+  l.sc = take(2 * sizeof(Scal));
   // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve)
   l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0);
   l.vec0 = off;
@@ -447,7 +446,6 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.gface = (double *)(base_ptr + lay.gface);
   p.part = (double *)(base_ptr + lay.part);
   p.sc = (Scal *)(base_ptr + lay.sc);
-  p.counter = (int *)(base_ptr + lay.cnt);
   const size_t vstride = align256(sizeof(double) * p.vlen);
   double *vec[12] = {};
   for (int i = 0; i < lay.nvec; ++i) vec[i] = (double *)(base_ptr + lay.vec0 + (size_t)i * vstride);
@@ -603,18 +601,18 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   h.rtol = rtol;
   h.maxit = maxit;
   h.status = RUNNING;
-  HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
+  const Scal h2[2] = {h, h};
+  HIP_TRY(hipMemcpyAsync(p.sc, h2, sizeof(h2), hipMemcpyHostToDevice, s));
   LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
   LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
   LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
-  LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
   LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
   const Profiler::Mark m0 = g_prof.mark();
-  int issued = 0;            // launches j = 1..issued enqueued
+  int issued = 0;            // launches j = 1..issued enqueued; sc[issued & 1] is the latest state
   int chunk = 4;
-  const int last = maxit + 1;
+  const int last = maxit + 2;   // launch maxit + 2 takes the stop decision on iteration maxit
   for (;;) {
-    HIP_TRY(hipMemcpyAsync(&h, p.sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h, p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h.status != RUNNING || issued >= last) break;
     const int todo = std::min(chunk, last - issued);
@@ -807,11 +805,11 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       h.rtol = rtol;
       h.maxit = maxit;
       h.status = RUNNING;
-      HIP_TRY(hipMemcpyAsync(p.sc, &h, sizeof(Scal), hipMemcpyHostToDevice, s));
+      const Scal h2[2] = {h, h};
+      HIP_TRY(hipMemcpyAsync(p.sc, h2, sizeof(h2), hipMemcpyHostToDevice, s));
       LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
       LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
       LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
-      LAUNCH(PROF_VEC, launch_zero_int(c, p.counter, 1));
     }
     HIP_TRY(hipMemcpyAsync(d_table, table.data(), sizeof(SpecP) * ns, hipMemcpyHostToDevice, s));
     Ctx c0{&plans[spec_ids[0]]->p, s};
@@ -820,9 +818,9 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, 0, 0));
     std::vector<Scal> hs(ns);
     int issued = 0, chunk = 4;
-    const int last = maxit + 1;
+    const int last = maxit + 2;
     for (;;) {
-      HIP_TRY(launch_gather_scal(s, d_table, ns, d_scal));
+      HIP_TRY(launch_gather_scal(s, d_table, ns, issued & 1, d_scal));
       HIP_TRY(hipMemcpyAsync(hs.data(), d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       bool running = false;

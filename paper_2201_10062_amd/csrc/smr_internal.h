@@ -60,8 +60,7 @@ struct Plan {
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
   double *part;               // 16 * kRedSlots partial sums
-  int *counter;               // last-block ticket of the fused iteration kernel
-  Scal *sc;                   // device scalars
+  Scal *sc;                   // device scalars (2 slots; the physical-basis path uses slot 0)
   Scal *sc_host;              // pinned host mirror
   size_t ws_bytes;
 };
@@ -125,16 +124,15 @@ struct SpecP {
   double *V[2], *W[2];
   double *x;             // x (INIT: x0, read only)
   const double *bh;      // transformed right-hand side b^ (unpermuted)
-  double *part;          // 4 partial sums per column tile
-  int *counter;          // last-tile ticket
-  Scal *sc;
+  double *part;          // 2 slots (launch parity) of 4 partial sums per column tile
+  Scal *sc;              // 2 scalar states: sc[j & 1] is the state after launch j
 };
 
 hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh);
 SpecP spec_desc(const Plan *p, double *x, const double *bh);
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
                              int j);
-hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, Scal *out);
+hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int slot, Scal *out);
 int spec_blocks(const Plan *p);
 hipError_t launch_zero_int(Ctx c, int *x, int count);
 
