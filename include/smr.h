@@ -68,13 +68,16 @@ typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;
 typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
 /* Arithmetic inside P^{-1} during the solves.  The matvec, the Lanczos recurrences, the
  * MINRES scalars and the true residual are always float64.  SMR_FP32 (time transform on the
- * float32 matrix cores, z stored in float32) is available for constant a with P_H / Phat,
- * i.e. for the sine-basis solve; smr_apply_P_inv always applies P^{-1} in float64. */
+ * float32 matrix cores, z stored in float32) is available wherever the solve runs in the
+ * sine basis (see SMR_FLAG_GENERAL_PATH); smr_apply_P_inv always applies P^{-1} in float64. */
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
-/* Constant a with P_H / Phat in float64: the solve runs in the spatial sine basis, where
- * Y T and P^{-1} act per spatial mode (one fused kernel per MINRES iteration, b and x0
- * transformed on entry, x on exit; same iterates in exact arithmetic).  This flag forces
- * the general physical-basis iteration instead (stencil matvec and 3D transforms). */
+/* P_H / Phat solves run in the spatial sine basis (b and x0 transformed on entry, x on exit;
+ * the same iterates in exact arithmetic): for constant a, Y T and P^{-1} act per spatial mode
+ * and one fused kernel does a MINRES iteration; for a variable a in 2D with N + 1 in
+ * {32, 64, 128} (Kbar inside P, Sec. 3.1.1), a per-time-level kernel first applies
+ * U K(a) U (sine transforms held in LDS) and the fused kernel takes that matvec.  Other
+ * variable-coefficient cases, P_theta and P = I run the general physical-basis iteration
+ * (stencil matvec and 3D transforms), which this flag forces for every plan. */
 #define SMR_FLAG_GENERAL_PATH 1
 
 typedef struct {
@@ -143,15 +146,16 @@ smr_status smr_minres_solve(const smr_plan *plan, const double *d_b, double *d_x
                             int32_t maxit, smr_info *info_host, void *stream);
 
 /* Device workspace (bytes, 256-byte aligned) that smr_minres_solve_batched needs for this
- * set of plans: the per-instance descriptor table and status array of the batched launch. */
+ * set of plans: the per-instance descriptor tables and status array of the batched launches. */
 smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans, size_t *bytes);
 
 /* The same solve for `count` independent plans at once, each with its own (N, n, scheme,
  * coefficient, preconditioner) and right-hand side.  Instances that take the sine-basis path
- * (constant a, P_H / Phat) iterate together: every MINRES iteration is one launch per
- * (time-size class, pprec) covering all of their column tiles, each instance with its own
- * device scalars; converged instances are masked on the device.  The remaining instances are
- * solved one after another on the general path.  plans, d_b, d_x and infos_host are host
+ * iterate together: every MINRES iteration is one per-level matvec launch per (N + 1, pprec)
+ * over all variable-coefficient instances, then one fused launch per (time-size class, pprec)
+ * covering all column tiles, each instance with its own device scalars; converged instances
+ * are masked on the device.  The remaining instances are solved one after another on the
+ * general path.  plans, d_b, d_x and infos_host are host
  * arrays of length count; d_b[i] / d_x[i] follow the conventions of smr_minres_solve.
  * d_ws: caller-owned device workspace of smr_batch_workspace_size bytes.  Returns SMR_OK when
  * every instance converged, else the first failing status (each info holds its own). */
@@ -192,7 +196,8 @@ smr_status smr_grad_a(const smr_plan *plan, const double *d_u, const double *d_u
  * before and after every launch of a kernel class while enabled.  Classes:
  * 0 = time-axis sine transform (MFMA), 1 = spatial sine transform, 2 = space-time
  * stencil (matvec / residual), 3 = vector updates and dots, 4 = MINRES scalar steps,
- * 5 = fused sine-basis MINRES iteration.  Launches that a solve enqueues past its
+ * 5 = fused sine-basis MINRES iteration, 6 = per-time-level sine-basis matvec of a variable
+ * coefficient.  Launches that a solve enqueues past its
  * convergence (they exit on the device status word) are not recorded.
  * smr_profile_enable(1) clears the records and starts recording, (0) stops it.
  * smr_profile_read synchronises the recorded events and returns the launch count and

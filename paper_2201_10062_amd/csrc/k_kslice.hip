@@ -1,0 +1,371 @@
+// All-at-once matvec in the spatial sine basis for a variable coefficient (gfx950).
+//
+// With U the orthonormal 2D sine transform (symmetric, U U = I) and K(a) the 5-point
+// stiffness matrix of eqn:matrix_Km_va built from face values, the blocks of T
+// (Sec. 1: theta method A0 = I + theta tau K, A1 = -I + (1-theta) tau K; BDF2
+// A0 = 1.5 I + tau K, A1 = -2 I, A2 = 0.5 I, Sec. 4) act on sine-basis levels z_t as
+//   (T z)^_t = c0 z_t + c1 z_{t-1} + c2 z_{t-2} + tau U K(a) U (b0 z_t + b1 z_{t-1}),
+// (c0, c1, c2) = (1, -1, 0), (b0, b1) = (theta, 1 - theta) for theta; (1.5, -2, 0.5), (1, 0)
+// for BDF2.  For constant a the last term is diagonal and the fused iteration kernel
+// applies it itself; here one block takes one time level through U, K(a), U with the
+// level held in LDS, and writes q_t = (T z)^_t for the fused kernel, plus the partial sums
+// that the MINRES scalars need from the matvec:
+//   delta = <(Y T)^ z, z> = sum_t q_t . z_{n-1-t}, and (when asked) the true residual
+//   ||b^ - (T x)^||^2 of the latest iterate x, by a second pass on x.
+//
+// Each 1D sine transform of two lines a, b (N = L - 1 points, L a power of two) packs
+// z = a + i b, extends it oddly to M = 2L points and takes an M-point DFT in registers of
+// one wave: M = R * 64, lane l holds z[64 j1 + l] (j1 < R); an R-point DFT in the lane,
+// twiddles W_M^{l k1}, then a 64-point decimation-in-frequency DFT across lanes, after
+// which lane l holds Z[k1 + R bitrev6(l)].  (S a)_k = -Im Z_{k+1} / sqrt(2L) and
+// (S b)_k = Re Z_{k+1} / sqrt(2L).
+#include "smr_internal.h"
+
+#include <type_traits>
+
+namespace smr {
+
+namespace {
+
+constexpr int kKT = 512;                 // 8 waves per block
+constexpr int kKW = kKT / 64;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ int brev6(int l) { return (int)(__brev((unsigned)l) >> 26); }
+
+// W_M^t for 0 <= t < M from the half table tw[t] = exp(-2 pi i t / M), t < M/2
+__device__ __forceinline__ double2 twid(const double2 *__restrict__ tw, int t, int M) {
+  if (t < M / 2) return tw[t];
+  const double2 w = tw[t - M / 2];
+  return make_double2(-w.x, -w.y);
+}
+
+// In-register M-point DFT (M = 64 R) of the values v[j1] = z[64 j1 + lane]; on return
+// v[k1] = Z[k1 + R brev6(lane)].
+template <int R>
+__device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const double2 *__restrict__ tw) {
+  constexpr int M = 64 * R;
+  if (R == 2) {
+    const double2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  } else if (R == 4) {
+    const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const double2 a2 = cadd(v[1], v[3]), a3 = csub(v[1], v[3]);
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = make_double2(a1.x + a3.y, a1.y - a3.x);   // a1 - i a3
+    v[3] = make_double2(a1.x - a3.y, a1.y + a3.x);   // a1 + i a3
+  }
+#pragma unroll
+  for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], twid(tw, lane * k1, M));
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const bool top = (lane & d) == 0;
+    const double2 w = tw[(lane & (d - 1)) * (M / (2 * d))];
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      double2 p;
+      p.x = __shfl_xor(v[k1].x, d, 64);
+      p.y = __shfl_xor(v[k1].y, d, 64);
+      v[k1] = top ? cadd(v[k1], p) : cmul(csub(p, v[k1]), w);
+    }
+  }
+}
+
+// Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS
+// (row pitch LP), in place; each wave takes pairs of lines.
+template <int R, int DIR>
+__device__ __forceinline__ void dst_level(double *X, int N, int LP, const double2 *__restrict__ tw, double scale,
+                                          int wave, int lane) {
+  constexpr int M = 64 * R, L = M / 2;
+  auto at = [&](int line, int pos) { return DIR == 0 ? line * LP + pos : pos * LP + line; };
+  const int npairs = (N + 1) / 2;
+  for (int pr = wave; pr < npairs; pr += kKW) {
+    const int la = 2 * pr, lb = 2 * pr + 1;
+    const bool hb = lb < N;
+    double2 v[R];
+#pragma unroll
+    for (int j1 = 0; j1 < R; ++j1) {
+      const int jn = 64 * j1 + lane;             // index into the odd extension
+      int src = -1;
+      double sg = 1.0;
+      if (jn >= 1 && jn <= N) src = jn - 1;
+      else if (jn > L) { src = M - jn - 1; sg = -1.0; }
+      double a = 0.0, b = 0.0;
+      if (src >= 0) {
+        a = sg * X[at(la, src)];
+        if (hb) b = sg * X[at(lb, src)];
+      }
+      v[j1] = make_double2(a, b);
+    }
+    wave_dft<R>(v, lane, tw);
+    const int k2 = brev6(lane);
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      const int K = k1 + R * k2;
+      if (K >= 1 && K <= N) {
+        X[at(la, K - 1)] = -v[k1].y * scale;
+        if (hb) X[at(lb, K - 1)] = v[k1].x * scale;
+      }
+    }
+  }
+}
+
+// X <- U K(a) U X for the level in LDS (U applied as DST along rows, then columns).
+template <int R, int KMAX>
+__device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int wave, int lane) {
+  const int N = K.N, LP = N + 2;
+  const double2 *tw = reinterpret_cast<const double2 *>(K.tw);
+  dst_level<R, 0>(X, N, LP, tw, K.scale, wave, lane);
+  __syncthreads();
+  dst_level<R, 1>(X, N, LP, tw, K.scale, wave, lane);
+  __syncthreads();
+  double kv[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int e = tid + k * kKT;
+    kv[k] = 0.0;
+    if (e < N * N) {
+      const int j = e / N, i = e - j * N;
+      const double uc = X[j * LP + i];
+      const double uw = i > 0 ? X[j * LP + i - 1] : 0.0;
+      const double ue = i < N - 1 ? X[j * LP + i + 1] : 0.0;
+      const double us = j > 0 ? X[(j - 1) * LP + i] : 0.0;
+      const double un = j < N - 1 ? X[(j + 1) * LP + i] : 0.0;
+      const double aw = K.ax[j * (N + 1) + i], ae = K.ax[j * (N + 1) + i + 1];
+      const double as = K.ay[j * N + i], an = K.ay[(j + 1) * N + i];
+      kv[k] = K.h2inv * (aw * (uc - uw) + ae * (uc - ue) + as * (uc - us) + an * (uc - un));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int e = tid + k * kKT;
+    if (e < N * N) {
+      const int j = e / N, i = e - j * N;
+      X[j * LP + i] = kv[k];
+    }
+  }
+  __syncthreads();
+  dst_level<R, 0>(X, N, LP, tw, K.scale, wave, lane);
+  __syncthreads();
+  dst_level<R, 1>(X, N, LP, tw, K.scale, wave, lane);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_sum4(double (&v)[4], double (*red)[kKW]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x >> 6] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kKW; ++w) s += red[q][w];
+      v[q] = s;
+    }
+}
+
+// MODE 0: q = (T x0)^ (initialising launch).  MODE 1: q = (T z_j)^, the delta partial and,
+// when the scalars of launch j-1 cannot exclude convergence, the true residual of the iterate
+// that launch j-1 formed.  j = jfull is the index of the fused launch that consumes q.
+template <int R, int PR, int MODE>
+__device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
+  typedef typename std::conditional<PR == 0 || MODE == 0, double, float>::type T;   // source type
+  constexpr int KMAX = (R == 4 ? 32 : R == 2 ? 8 : 2);   // ceil(N^2 / 512) for N = 64 R / 2 - 1
+  extern __shared__ double X[];
+  __shared__ double red[4][kKW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = K.N, n = K.n, m = K.m, LP = N + 2;
+  const size_t ld = (size_t)K.ld;
+  const int j = jfull % 6;   // rotation phase of the z buffers
+  bool do_res = false;
+  if (MODE == 1) {
+    const Scal *sprev = K.sc + ((j + 1) & 1);   // state after launch j-1
+    if (sprev->status != RUNNING) return;
+    // the iterate that launch j-1 formed exists from j-1 >= 2 on; its true residual is needed
+    // unless sqrt(min sigma) |eta| (a lower bound of ||r||_2, since |eta| = ||r||_{P^-1})
+    // still exceeds the tolerance with a margin, or the iteration limit is due
+    do_res = jfull >= 3 &&
+             (K.sqsigmin * fabs(sprev->eta) <= 2.0 * sprev->rtol * sprev->bnorm || sprev->iter >= sprev->maxit);
+  }
+  double c0, c1, c2, b0, b1;
+  if (K.scheme == SMR_THETA) { c0 = 1.0; c1 = -1.0; c2 = 0.0; b0 = K.theta; b1 = 1.0 - K.theta; }
+  else { c0 = 1.5; c1 = -2.0; c2 = 0.5; b0 = 1.0; b1 = 0.0; }
+
+  double acc_r = 0.0, acc_d = 0.0;
+  // ---- q = (T s)^ on level t for the source s (x0 or z_j)
+  {
+    const T *s = MODE == 0 ? reinterpret_cast<const T *>(K.x)
+                           : reinterpret_cast<const T *>(K.Z[(j + 2) % 3]);
+    const T *st = s + (size_t)t * ld;
+    const T *s1 = t >= 1 ? st - ld : nullptr;
+    const T *s2 = t >= 2 ? st - 2 * ld : nullptr;
+    double id[KMAX], zf[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int e = tid + k * kKT;
+      id[k] = 0.0;
+      zf[k] = 0.0;
+      if (e < m) {
+        const double v0 = (double)st[e];
+        const double v1 = s1 ? (double)s1[e] : 0.0;
+        const double v2 = s2 ? (double)s2[e] : 0.0;
+        id[k] = c0 * v0 + c1 * v1 + c2 * v2;
+        const int jr = e / N, ir = e - jr * N;
+        X[jr * LP + ir] = b0 * v0 + b1 * v1;
+        if (MODE == 1) zf[k] = (double)s[(size_t)(n - 1 - t) * ld + e];
+      }
+    }
+    __syncthreads();
+    uku_level<R, KMAX>(X, K, tid, wave, lane);
+    double *q = K.q + (size_t)t * ld;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int e = tid + k * kKT;
+      if (e < m) {
+        const int jr = e / N, ir = e - jr * N;
+        const double v = id[k] + K.tau * X[jr * LP + ir];
+        q[e] = v;
+        if (MODE == 1) acc_d += v * zf[k];
+      }
+    }
+  }
+  // ---- true residual ||b^ - (T x)^||^2 on level t
+  if (do_res) {
+    __syncthreads();
+    const double *xt = K.x + (size_t)t * ld;
+    const double *x1 = t >= 1 ? xt - ld : nullptr;
+    const double *x2 = t >= 2 ? xt - 2 * ld : nullptr;
+    const double *bt = K.bh + (size_t)t * ld;
+    double rb[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int e = tid + k * kKT;
+      rb[k] = 0.0;
+      if (e < m) {
+        const double v0 = xt[e];
+        const double v1 = x1 ? x1[e] : 0.0;
+        const double v2 = x2 ? x2[e] : 0.0;
+        rb[k] = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2);
+        const int jr = e / N, ir = e - jr * N;
+        X[jr * LP + ir] = b0 * v0 + b1 * v1;
+      }
+    }
+    __syncthreads();
+    uku_level<R, KMAX>(X, K, tid, wave, lane);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int e = tid + k * kKT;
+      if (e < m) {
+        const int jr = e / N, ir = e - jr * N;
+        const double r = rb[k] - K.tau * X[jr * LP + ir];
+        acc_r += r * r;
+      }
+    }
+  }
+  // ---- partials [residual^2, residual skipped, 0, delta] of this level
+  double v[4] = {acc_r, 0.0, 0.0, acc_d};
+  block_sum4(v, red);
+  if (tid == 0 && MODE == 1) {
+    double *pp = K.kpart + 4 * (size_t)t;
+    pp[0] = v[0];
+    pp[1] = (jfull >= 3 && !do_res) ? 1.0 : 0.0;
+    pp[2] = 0.0;
+    pp[3] = v[3];
+  }
+}
+
+template <int R, int PR, int MODE>
+__global__ __launch_bounds__(kKT) void k_kslice(KsP K, int jfull) {
+  ks_body<R, PR, MODE>(K, jfull, blockIdx.x);
+}
+
+// Batched launch: one block per time level of every instance in the table.
+template <int R, int PR, int MODE>
+__global__ __launch_bounds__(kKT) void k_kslice_multi(const KsP *__restrict__ table, int ninst, int jfull) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const KsP K = table[lo];
+  ks_body<R, PR, MODE>(K, jfull, b - K.blk0);
+}
+
+template <int R, int PR>
+size_t ks_shmem() { return (size_t)(32 * R - 1) * (32 * R + 1) * sizeof(double); }
+
+template <int R, int PR>
+hipError_t run_ks(hipStream_t st, const KsP *K, const KsP *table, int ninst, int blocks, int mode, int jfull) {
+  const size_t sh = ks_shmem<R, PR>();
+  if (sh > 65536) {
+    hipFuncSetAttribute((const void *)k_kslice<R, PR, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipFuncSetAttribute((const void *)k_kslice<R, PR, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipFuncSetAttribute((const void *)k_kslice_multi<R, PR, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipFuncSetAttribute((const void *)k_kslice_multi<R, PR, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  }
+  if (K) {
+    if (mode == 0) hipLaunchKernelGGL((k_kslice<R, PR, 0>), dim3(blocks), dim3(kKT), sh, st, *K, jfull);
+    else hipLaunchKernelGGL((k_kslice<R, PR, 1>), dim3(blocks), dim3(kKT), sh, st, *K, jfull);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_kslice_multi<R, PR, 0>), dim3(blocks), dim3(kKT), sh, st, table, ninst, jfull);
+    else hipLaunchKernelGGL((k_kslice_multi<R, PR, 1>), dim3(blocks), dim3(kKT), sh, st, table, ninst, jfull);
+  }
+  return hipGetLastError();
+}
+
+template <int PR>
+hipError_t run_ks_r(hipStream_t st, int L, const KsP *K, const KsP *table, int ninst, int blocks, int mode, int jfull) {
+  switch (L) {
+    case 32: return run_ks<1, PR>(st, K, table, ninst, blocks, mode, jfull);
+    case 64: return run_ks<2, PR>(st, K, table, ninst, blocks, mode, jfull);
+    case 128: return run_ks<4, PR>(st, K, table, ninst, blocks, mode, jfull);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128); }
+
+KsP kslice_desc(const Plan *p, double *x, const double *bh) {
+  KsP K{};
+  K.N = p->N; K.n = p->n; K.m = p->m; K.ld = p->ld; K.L = p->L; K.scheme = p->scheme;
+  K.blk0 = 0;
+  K.theta = p->theta; K.tau = p->tau; K.h2inv = p->h2inv; K.scale = 1.0 / sqrt(2.0 * p->L);
+  K.sqsigmin = p->sqsigmin;
+  K.ax = p->ax; K.ay = p->ay; K.tw = p->tw;
+  const bool f32 = p->pprec == SMR_FP32;
+  for (int i = 0; i < 3; ++i) K.Z[i] = f32 ? (const void *)p->ZF[i] : (const void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
+  K.x = x; K.bh = bh; K.q = p->QX; K.kpart = p->part + kKsPartOffset; K.sc = p->sc;
+  return K;
+}
+
+hipError_t launch_kslice(Ctx c, int mode, int j, double *x, const double *bh) {
+  const Plan *p = c.p;
+  const KsP K = kslice_desc(p, x, bh);
+  return p->pprec == SMR_FP32 ? run_ks_r<1>(c.st, p->L, &K, nullptr, 1, p->n, mode, j)
+                              : run_ks_r<0>(c.st, p->L, &K, nullptr, 1, p->n, mode, j);
+}
+
+hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int blocks, int L, int pprec, int mode,
+                               int j) {
+  return pprec == SMR_FP32 ? run_ks_r<1>(st, L, nullptr, table, ninst, blocks, mode, j)
+                           : run_ks_r<0>(st, L, nullptr, table, ninst, blocks, mode, j);
+}
+
+}  // namespace smr

@@ -115,7 +115,9 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double (*red)[kWaves]
 
 // MINRES scalar recurrence after launch j-1, whose mode was pmode, from the block sums of
 // that launch (run by thread 0 of every block of launch j).
-__device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double s2, double s3) {
+// have_res = false: the true residual of the newest iterate was not evaluated (its lower
+// bound excluded convergence), so only the iteration limit is tested.
+__device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double s2, double s3, bool have_res) {
   if (pmode == MODE_INIT) {
     // s0 = ||v_1||^2, s1 = ||b||^2, s2 = gamma_1^2, s3 = <T^ z_1, z_1>
     sc->bnorm = sqrt(s1);
@@ -139,8 +141,11 @@ __device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double 
   // s0 = ||r(x_{j-1})||^2 (STEADY), s2 = gamma_{j+1}^2, s3 = <T^ z_{j+1}, z_{j+1}>
   sc->iter += 1;                                  // launches since INIT = j
   if (pmode == MODE_STEADY) {
-    sc->relres = sqrt(s0) / sc->bnorm;            // of x_{j-1}
-    if (sc->relres <= sc->rtol || sc->exact) { sc->iter -= 1; sc->status = DONE_CONV; return; }
+    if (have_res) {
+      sc->relres = sqrt(s0) / sc->bnorm;          // of x_{j-1}
+      if (sc->relres <= sc->rtol) { sc->iter -= 1; sc->status = DONE_CONV; return; }
+    }
+    if (sc->exact) { sc->iter -= 1; sc->status = DONE_CONV; return; }
     if (sc->iter - 1 >= sc->maxit) { sc->iter -= 1; sc->status = DONE_MAXIT; return; }
   }
   if (s2 < 0.0 || !isfinite(s2)) { sc->iter -= 1; sc->status = DONE_NOTSPD; return; }
@@ -281,10 +286,21 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
 #pragma unroll
       for (int q = 0; q < 4; ++q) t[q] += pp[4 * (size_t)b + q];
     }
+    double skip = 0.0;
+    if (P.qext) {           // the per-level matvec's residual and delta partials
+      for (int b = tid; b < P.nks; b += kThreads) {
+        const double *kp = P.kpart + 4 * (size_t)b;
+        t[0] += kp[0];
+        skip += kp[1];
+        t[3] += kp[3];
+      }
+    }
+    double u[4] = {skip, 0.0, 0.0, 0.0};
     block_sum4(t, red);
+    block_sum4(u, red);
     if (tid == 0) {
       S = *sprev;
-      scalar_update(&S, pmode, t[0], t[1], t[2], t[3]);
+      scalar_update(&S, pmode, t[0], t[1], t[2], t[3], u[0] == 0.0);
       if (tile == 0) *snew = S;
     }
     __syncthreads();
@@ -325,16 +341,18 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
   auto bstream = [&](int ta, int tb) {
     const Coef k = coef_of(P, P.tmu[bcc]);
-#pragma unroll 2
+#pragma unroll 4
     for (int t = ta; t < tb; ++t) {
       const size_t i = vat(ld, t, bcc);
       const double w = wnew(i);
       const double x0 = xv[i] + ceta * w;
-      const double r = bh[i] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
       if (bok) {
         wb[i] = w;
         xv[i] = x0;
-        acc_r += r * r;
+        if (!P.qext) {    // variable a: the per-level matvec takes the true residual
+          const double r = bh[i] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
+          acc_r += r * r;
+        }
       }
       bx2 = bx1;
       bx1 = x0;
@@ -352,15 +370,16 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const Coef k = coef_of(P, P.tmu[cc]);
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
+    const bool ext = P.qext != nullptr;               // (T z)^ given by the per-level matvec
     auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? xv[i] : (double)zcur[i]; };
-    double y1 = t0 >= 1 ? src(vat(ld, t0 - 1, cc)) : 0.0;
-    double y2 = t0 >= 2 ? src(vat(ld, t0 - 2, cc)) : 0.0;
-#pragma unroll 2
+    double y1 = (!ext && t0 >= 1) ? src(vat(ld, t0 - 1, cc)) : 0.0;
+    double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
+#pragma unroll 4
     for (int t = t0; t < t1; ++t) {
       const int o = n - 1 - t;
       const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
-      const double y0 = src(it);
-      const double ty = k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
+      const double y0 = ext ? 0.0 : src(it);
+      const double ty = ext ? P.qext[it] : k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
       double v;
       if (MODE == MODE_INIT) {
         const double bt = bh[it];
@@ -463,7 +482,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
       const double y0 = zrow(t);
       if (ok) {
         znext[vat(ld, t, col)] = (T)y0;
-        acc_d += (k.l0 * y0 + k.l1 * y1 + k.l2 * y2) * zrow(n - 1 - t);
+        if (!P.qext) acc_d += (k.l0 * y0 + k.l1 * y1 + k.l2 * y2) * zrow(n - 1 - t);
       }
       y2 = y1;
       y1 = y0;
@@ -592,6 +611,11 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh) {
   for (int i = 0; i < 3; ++i) P.Z[i] = f32 ? (void *)p->ZF[i] : (void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
   P.V[0] = p->V[0]; P.V[1] = p->V[1]; P.W[0] = p->W[0]; P.W[1] = p->W[1];
   P.x = x; P.bh = bh; P.part = p->part; P.sc = p->sc;
+  if (!p->const_coef) {
+    P.qext = p->QX;
+    P.kpart = p->part + kKsPartOffset;
+    P.nks = p->n;
+  }
   return P;
 }
 

@@ -43,7 +43,7 @@ smr_status fail(smr_status st, const char *fmt, ...) {
 
 // ---------------------------------------------------------------- event profiler
 enum ProfClass { PROF_TIME = 0, PROF_DST = 1, PROF_STENCIL = 2, PROF_VEC = 3, PROF_SCALAR = 4, PROF_SPEC = 5,
-                 PROF_NCLASS = 6 };
+                 PROF_KSLICE = 6, PROF_NCLASS = 7 };
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;                     // free events
@@ -163,6 +163,14 @@ smr_status validate(const smr_desc *d) {
   return SMR_OK;
 }
 
+// A 2D variable-coefficient P_H solve runs in the sine basis when the per-level matvec
+// supports its N (the level, N x (N + 2) float64, is held in LDS).
+bool var_sine_basis(const smr_desc *d) {
+  const int L = d->N + 1;
+  return d->dim == 2 && (L == 32 || L == 64 || L == 128) && d->precond == SMR_P_H &&
+         !(d->flags & SMR_FLAG_GENERAL_PATH) && (d->ax_host || d->a_nodal_host);
+}
+
 struct Layout {
   size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, vec0;
   int nvec;
@@ -202,8 +210,9 @@ Layout layout_of(const smr_desc *d) {
   l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
   l.part = take(sizeof(double) * 16 * (size_t)kRedSlots);
   l.sc = take(2 * sizeof(Scal));
-  // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve)
-  l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0);
+  // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve, + QX for the
+  // variable-coefficient sine-basis solve)
+  l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0) + (var_sine_basis(d) ? 1 : 0);
   l.vec0 = off;
   off += (size_t)l.nvec * align256(sizeof(double) * len);
   l.total = off;
@@ -343,9 +352,10 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.a_min = amin;
   p.a_max = amax;
   p.const_coef = (amin == amax);
-  if (p.pprec == SMR_FP32 && !p.const_coef) {
+  if (p.pprec == SMR_FP32 && !p.const_coef && !var_sine_basis(d)) {
     delete pl;
-    return fail(SMR_EUNSUPPORTED, "float32 preconditioning needs a constant coefficient (sine-basis solve)");
+    return fail(SMR_EUNSUPPORTED, "float32 preconditioning needs the sine-basis solve (constant a, or 2D with "
+                                  "N + 1 in {32, 64, 128})");
   }
   p.abar = 0.5 * (amin + amax);
   p.cheb_lo = std::min(1.0, amin / p.abar);
@@ -392,6 +402,18 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     }
     ez[t] = (double)(2.0L * sh);
     ez[n + t] = (double)sqrtl(th * th + (1.0L - th) * (1.0L - th) + 2.0L * th * (1.0L - th) * cp);
+  }
+  // smallest eigenvalue of P: a lower bound ||r||_2 >= sqrt(min sigma) ||r||_{P^-1}
+  {
+    double smin = INFINITY;
+    for (int t = 0; t < n; ++t) {
+      const double A = tcoef[4 * t], B = tcoef[4 * t + 1], Cc = tcoef[4 * t + 2], Dd = tcoef[4 * t + 3];
+      for (int q = 0; q < m; ++q) {
+        const double re = A + tmu[q] * B, im = Cc + tmu[q] * Dd;
+        smin = std::min(smin, re * re + im * im);
+      }
+    }
+    p.sqsigmin = std::sqrt(std::sqrt(smin));
   }
   // ---- folded time sine blocks in MFMA fragment order
   const int hp = p.hp, KS = hp / 4;
@@ -453,8 +475,10 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.Z[0] = vec[2]; p.Z[1] = vec[3];
   p.W[0] = vec[4]; p.W[1] = vec[5];
   p.Q = vec[6]; p.T1 = vec[7]; p.T2 = vec[8]; p.G = vec[9];
-  p.T3 = lay.nvec > 10 ? vec[10] : nullptr;
-  p.T4 = lay.nvec > 11 ? vec[11] : nullptr;
+  const bool cheb = p.precond == SMR_P_THETA_CHEB;
+  p.T3 = cheb ? vec[10] : nullptr;
+  p.T4 = cheb ? vec[11] : nullptr;
+  p.QX = var_sine_basis(d) ? vec[lay.nvec - 1] : nullptr;
 
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s); };
   hipError_t e = hipSuccess;
@@ -495,7 +519,7 @@ namespace smr {
 namespace {
 
 bool use_spectral(const Plan &p) {
-  return p.const_coef && p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH);
+  return p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH) && (p.const_coef || p.QX != nullptr);
 }
 
 smr_status check_plan(const smr_plan *pl) {
@@ -606,6 +630,8 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
   LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
   LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
+  const bool ext = !p.const_coef;   // variable a: (T z)^ from the per-level matvec
+  if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 0, 0, Xh, Bh));
   LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
   const Profiler::Mark m0 = g_prof.mark();
   int issued = 0;            // launches j = 1..issued enqueued; sc[issued & 1] is the latest state
@@ -618,6 +644,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
     const int todo = std::min(chunk, last - issued);
     for (int it = 0; it < todo; ++it) {
       const int j = issued + it + 1;
+      if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 1, j, Xh, Bh));
       LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, j, Xh, Bh));
     }
     issued += todo;
@@ -626,6 +653,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   if (g_prof.on) {   // keep the records of the launches that did work (j = 1 .. iter + 1)
     Profiler::Mark k = m0;
     k.n[PROF_SPEC] += (size_t)std::min(issued, h.iter + 1);
+    if (ext) k.n[PROF_KSLICE] += (size_t)std::min(issued, h.iter + 1);
     g_prof.truncate(k);
   }
   if (h.status == DONE_CONV && h.bnorm == 0.0) {
@@ -752,7 +780,8 @@ smr_status smr_minres_solve(const smr_plan *pl, const double *b, double *x, doub
 
 smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans, size_t *bytes) {
   if (count < 0 || (count > 0 && !plans) || !bytes) return fail(SMR_EINVAL, "bad batch arguments");
-  *bytes = align256(sizeof(SpecP) * (size_t)std::max(count, 1)) + align256(sizeof(Scal) * (size_t)std::max(count, 1));
+  const size_t c1 = (size_t)std::max(count, 1);
+  *bytes = align256(sizeof(SpecP) * c1) + align256(sizeof(Scal) * c1) + align256(sizeof(KsP) * c1);
   return SMR_OK;
 }
 
@@ -770,7 +799,9 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
   }
   hipStream_t s = (hipStream_t)stream;
   SpecP *d_table = (SpecP *)d_ws;
-  Scal *d_scal = (Scal *)((char *)d_ws + align256(sizeof(SpecP) * (size_t)std::max(count, 1)));
+  const size_t c1 = (size_t)std::max(count, 1);
+  Scal *d_scal = (Scal *)((char *)d_ws + align256(sizeof(SpecP) * c1));
+  KsP *d_ks = (KsP *)((char *)d_ws + align256(sizeof(SpecP) * c1) + align256(sizeof(Scal) * c1));
   // sine-basis instances, grouped by (time-size class, transform precision)
   std::vector<int> spec_ids, general_ids;
   for (int i = 0; i < count; ++i) (use_spectral(plans[i]->p) ? spec_ids : general_ids).push_back(i);
@@ -792,6 +823,27 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     cl.count += 1;
   }
   const int ns = (int)spec_ids.size();
+  // variable-coefficient sine-basis instances: per-level matvec, grouped by (N + 1, precision)
+  std::vector<int> var_ids;
+  for (int i : spec_ids)
+    if (!plans[i]->p.const_coef) var_ids.push_back(i);
+  std::stable_sort(var_ids.begin(), var_ids.end(), [&](int a, int c) {
+    const Plan &pa = plans[a]->p, &pc = plans[c]->p;
+    return pa.L != pc.L ? pa.L < pc.L : pa.pprec < pc.pprec;
+  });
+  struct KClass { int first, count, blocks, L, pprec; };
+  std::vector<KClass> kclasses;
+  std::vector<KsP> ktable(var_ids.size());
+  for (size_t k = 0; k < var_ids.size(); ++k) {
+    const Plan &p = plans[var_ids[k]]->p;
+    if (kclasses.empty() || kclasses.back().L != p.L || kclasses.back().pprec != p.pprec)
+      kclasses.push_back(KClass{(int)k, 0, 0, p.L, p.pprec});
+    KClass &cl = kclasses.back();
+    ktable[k] = kslice_desc(&p, p.T2, p.T1);
+    ktable[k].blk0 = cl.blocks;
+    cl.blocks += p.n;
+    cl.count += 1;
+  }
   smr_status first_bad = SMR_OK;
   if (ns > 0) {
     for (int k = 0; k < ns; ++k) {
@@ -812,8 +864,12 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
     }
     HIP_TRY(hipMemcpyAsync(d_table, table.data(), sizeof(SpecP) * ns, hipMemcpyHostToDevice, s));
+    if (!ktable.empty())
+      HIP_TRY(hipMemcpyAsync(d_ks, ktable.data(), sizeof(KsP) * ktable.size(), hipMemcpyHostToDevice, s));
     Ctx c0{&plans[spec_ids[0]]->p, s};
     Ctx &c = c0;
+    for (const KClass &cl : kclasses)
+      LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
     for (const Class &cl : classes)
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, 0, 0));
     std::vector<Scal> hs(ns);
@@ -829,6 +885,8 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       const int todo = std::min(chunk, last - issued);
       for (int it = 0; it < todo; ++it) {
         const int j = issued + it + 1;
+        for (const KClass &cl : kclasses)
+          LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
         for (const Class &cl : classes)
           LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec,
                                               j == 1 ? 1 : 2, j));

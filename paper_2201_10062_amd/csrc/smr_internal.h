@@ -14,6 +14,7 @@ namespace smr {
 constexpr int kMaxN = 511;       // N + 1 <= 512
 constexpr int kMaxn = 1024;
 constexpr int kRedSlots = 8192;  // partial sums per reduction (grid-stride kernels use <= this many blocks)
+constexpr size_t kKsPartOffset = 8 * (size_t)kRedSlots;   // per-level partials of the sine-basis matvec
 
 // MINRES status codes kept on the device.
 enum DevStatus : int { RUNNING = 0, DONE_CONV = 1, DONE_MAXIT = 2, DONE_NOTSPD = 3, DONE_BREAKDOWN = 4 };
@@ -44,6 +45,7 @@ struct Plan {
   bool const_coef;            // every face value equal
   double a_min, a_max, abar, cheb_lo, cheb_hi;
   double kbar_d, kbar_cx, kbar_cy;
+  double sqsigmin;            // sqrt of the smallest eigenvalue of P (P_H / Phat)
   int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
   int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
   // tables (device)
@@ -57,6 +59,7 @@ struct Plan {
   double *tw;                 // complex twiddles exp(-2 pi i t / (2L)), t < L (interleaved)
   // vectors (device), each vlen doubles (physical-basis use: stride m; sine basis: stride ld)
   double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
+  double *QX;                 // (T z)^ of the variable-coefficient sine-basis solve (or null)
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
   double *part;               // 16 * kRedSlots partial sums
@@ -126,7 +129,31 @@ struct SpecP {
   const double *bh;      // transformed right-hand side b^ (unpermuted)
   double *part;          // 2 slots (launch parity) of 4 partial sums per column tile
   Scal *sc;              // 2 scalar states: sc[j & 1] is the state after launch j
+  // variable coefficient: (T z)^ comes from the per-level kernel, with its partial sums
+  // [residual^2, residual skipped, 0, delta] per time level (null / 0 for constant a)
+  const double *qext;
+  const double *kpart;
+  int nks, pad2;
 };
+
+// One instance of the per-level sine-basis matvec (also the element of its batched table).
+struct KsP {
+  int N, n, m, ld, L, scheme, blk0, pad;
+  double theta, tau, h2inv, scale, sqsigmin;
+  const double *ax, *ay, *tw;
+  const void *Z[3];      // z rotation of the fused kernel (the transform's precision)
+  const double *x, *bh;  // iterate and right-hand side (sine basis)
+  double *q;             // out: (T s)^
+  double *kpart;         // out: 4 partial sums per time level
+  const Scal *sc;
+};
+bool kslice_supported(const Plan *p);
+KsP kslice_desc(const Plan *p, double *x, const double *bh);
+// mode 0: q = (T x)^ before the initialising launch; mode 1: q = (T z_j)^ with its partials
+// before fused launch j
+hipError_t launch_kslice(Ctx c, int mode, int j, double *x, const double *bh);
+hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int blocks, int L, int pprec, int mode,
+                               int j);
 
 hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh);
 SpecP spec_desc(const Plan *p, double *x, const double *bh);

@@ -248,11 +248,15 @@ def test_mixed_fp32_solve(dim, N, n, scheme, theta):
     assert rel(x, _n(x64)) > 1e-13
 
 
-def test_mixed_fp32_rejects_variable_coefficients():
+def test_mixed_fp32_rejects_physical_basis_plans():
+    """Float32 preconditioning exists only where the solve runs in the sine basis: a variable
+    coefficient with N + 1 outside {32, 64, 128}, or the forced physical-basis path, is refused."""
     from paper_2201_10062_amd import Plan, SmrError
     ax, ay = _faces("var", 7, 2)
     with pytest.raises(SmrError):
         Plan(2, 7, 8, pprec="fp32", ax=ax, ay=ay)
+    with pytest.raises(SmrError):
+        Plan(2, 31, 8, pprec="fp32", general_path=True)
 
 
 # ---------------------------------------------------------------- batched solves
