@@ -13,7 +13,11 @@ beside it.  The dominant kernel (the fused sine-basis MINRES iteration) is timed
 HIP events on its launch stream and priced against the HBM roofline (and, beside it, its
 two folded time GEMMs against the FP64 matrix peak).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Beside it: the 64-instance BDF2 batch of uneven sizes, plain float64 (instances one after
+another) against mixed precision + batched (float32 time transform, one launch per size
+class per iteration), time-to-1e-8 for the whole batch.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
 """
 from __future__ import annotations
 
@@ -66,6 +70,53 @@ def cpu_baseline(p, iters: int = 10):
                       f"(P_H, true residual each iteration), {dt:.1f} s on one host core"}
 
 
+def batched_bdf2_leg(dev, warmup: int, steps: int, rtol: float):
+    """The 64-instance BDF2 batch (uneven N in {31, 63, 127}, n in {64, 128, 256}, a = 1 or
+    1 + 0.5 cos(pi x), b ~ N(0, 1), seed 2): plain float64 (the same method, instances solved
+    back to back on one stream) against mixed + batched (float32 time transform, every
+    iteration one launch per size class over all instances).  Inputs resident in HBM."""
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Batch, Plan
+    probs = W.bdf2_batch()
+    bs = [torch.from_numpy(p.b.reshape(-1)).to(dev) for p in probs]
+    plain = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, device=dev) for p in probs]
+    mixed = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, pprec="fp32", device=dev) for p in probs]
+    batch = Batch(mixed)
+
+    def run_plain():
+        return [pl.solve(b, rtol=rtol, maxit=1000)[1] for pl, b in zip(plain, bs)]
+
+    def run_mixed():
+        return batch.solve(bs, rtol=rtol, maxit=1000)[1]
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, infos
+
+    t_plain, ip = timed(run_plain)
+    t_mixed, im = timed(run_mixed)
+    ok = all(i["status"] == "ok" and i["relres_true"] <= rtol for i in ip + im)
+    it_p = [i["iters"] for i in ip]
+    it_m = [i["iters"] for i in im]
+    ratio = max(b / a for a, b in zip(it_p, it_m) if a > 0)
+    nvar = sum(p.ax is not None for p in probs)
+    dof = sum(p.n * p.N * p.N for p in probs)
+    return {"workload": "bdf2_batch64_uneven", "instances": len(probs), "variable_coefficient": nvar,
+            "dof_total": dof, "rtol": rtol,
+            "plain_fp64_sequential_ms": t_plain * 1e3, "mixed_fp32_batched_ms": t_mixed * 1e3,
+            "speedup": t_plain / t_mixed,
+            "iters_total_plain": sum(it_p), "iters_total_mixed": sum(it_m),
+            "iters_max_ratio_mixed_over_plain": ratio, "all_converged": ok,
+            "mixed_iters_per_s": sum(it_m) / t_mixed, "plain_iters_per_s": sum(it_p) / t_plain}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +124,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance BDF2 batch comparison")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -181,6 +233,8 @@ def main() -> int:
                          "iters_per_s": minfo["iters"] * args.steps / (tm1 - tm0),
                          "relres_true": minfo["relres_true"],
                          "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
+    if not args.no_batch:
+        out["batched_bdf2"] = batched_bdf2_leg(dev, warmup=1, steps=2, rtol=args.rtol)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -37,18 +37,75 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ int brev6(int l) { return (int)(__brev((unsigned)l) >> 26); }
 
+// Value of lane (lane ^ d).  Spans 1, 2, 4 and 8 stay inside a 16-lane row and use DPP moves
+// (quad_perm [1,0,3,2] and [2,3,0,1]; row_half_mirror then quad_perm [3,2,1,0], i.e. xor 7
+// then xor 3; row_ror:8); spans 16 and 32 go through the cross-lane permute.
+template <int D>
+__device__ __forceinline__ int xor_lane_i(int v) {
+  if (D == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if (D == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  if (D == 4) return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+  if (D == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+  return __shfl_xor(v, D, 64);
+}
+template <int D>
+__device__ __forceinline__ double xor_lane(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = xor_lane_i<D>((int)(u & 0xffffffff)), hi = xor_lane_i<D>((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // W_M^t for 0 <= t < M from the half table tw[t] = exp(-2 pi i t / M), t < M/2
 __device__ __forceinline__ double2 twid(const double2 *__restrict__ tw, int t, int M) {
-  if (t < M / 2) return tw[t];
-  const double2 w = tw[t - M / 2];
-  return make_double2(-w.x, -w.y);
+  const double2 w = tw[t < M / 2 ? t : t - M / 2];
+  return t < M / 2 ? w : make_double2(-w.x, -w.y);
+}
+
+// Per-lane constants of the wave DFT, loaded once: in-lane twiddles W_M^{lane k1}
+// (k1 = 1..R-1) and, per cross-lane stage s of span d = 32 >> s, the sign sg = +1 (lane in
+// the top half of its pair) or -1 and the multiplier wm = 1 (top) or W_{2d}^{lane mod d}.
+template <int R>
+struct Twiddles {
+  double2 in[R > 1 ? R - 1 : 1];
+  double2 wm[6];
+  double sg[6];
+  __device__ __forceinline__ void load(const double2 *__restrict__ tw, int lane) {
+    constexpr int M = 64 * R;
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) in[k1 - 1] = twid(tw, lane * k1, M);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int d = 32 >> s;
+      const bool top = (lane & d) == 0;
+      sg[s] = top ? 1.0 : -1.0;
+      wm[s] = top ? make_double2(1.0, 0.0) : tw[(lane & (d - 1)) * (M / (2 * d))];
+    }
+  }
+};
+
+// One cross-lane stage of span D: all partner reads first, then (sg v + p) wm per value.
+template <int R, int D>
+__device__ __forceinline__ void dif_stage(double2 (&v)[R], double sg, double2 wm) {
+  double2 p[R];
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) {
+    p[k1].x = xor_lane<D>(v[k1].x);
+    p[k1].y = xor_lane<D>(v[k1].y);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) {
+    const double tx = fma(sg, v[k1].x, p[k1].x), ty = fma(sg, v[k1].y, p[k1].y);
+    v[k1] = cmul(make_double2(tx, ty), wm);
+  }
 }
 
 // In-register M-point DFT (M = 64 R) of the values v[j1] = z[64 j1 + lane]; on return
-// v[k1] = Z[k1 + R brev6(lane)].
+// v[k1] = Z[k1 + R brev6(lane)].  A decimation-in-frequency butterfly of the pair
+// (a, b) = (top, bottom) gives a + b on the top lane and (a - b) w on the bottom one; with
+// p the partner's value both are (sg v + p) wm, so every lane runs the same arithmetic.
+// Each stage issues all of its cross-lane reads before using them.
 template <int R>
-__device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const double2 *__restrict__ tw) {
-  constexpr int M = 64 * R;
+__device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const Twiddles<R> &W) {
   if (R == 2) {
     const double2 a = v[0];
     v[0] = cadd(a, v[1]);
@@ -62,55 +119,50 @@ __device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const double
     v[3] = make_double2(a1.x - a3.y, a1.y + a3.x);   // a1 + i a3
   }
 #pragma unroll
-  for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], twid(tw, lane * k1, M));
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const bool top = (lane & d) == 0;
-    const double2 w = tw[(lane & (d - 1)) * (M / (2 * d))];
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) {
-      double2 p;
-      p.x = __shfl_xor(v[k1].x, d, 64);
-      p.y = __shfl_xor(v[k1].y, d, 64);
-      v[k1] = top ? cadd(v[k1], p) : cmul(csub(p, v[k1]), w);
-    }
-  }
+  for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], W.in[k1 - 1]);
+  dif_stage<R, 32>(v, W.sg[0], W.wm[0]);
+  dif_stage<R, 16>(v, W.sg[1], W.wm[1]);
+  dif_stage<R, 8>(v, W.sg[2], W.wm[2]);
+  dif_stage<R, 4>(v, W.sg[3], W.wm[3]);
+  dif_stage<R, 2>(v, W.sg[4], W.wm[4]);
+  dif_stage<R, 1>(v, W.sg[5], W.wm[5]);
 }
 
 // Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS
 // (row pitch LP), in place; each wave takes pairs of lines.
 template <int R, int DIR>
-__device__ __forceinline__ void dst_level(double *X, int N, int LP, const double2 *__restrict__ tw, double scale,
-                                          int wave, int lane) {
+__device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddles<R> &W, double scale, int wave,
+                                          int lane) {
   constexpr int M = 64 * R, L = M / 2;
   auto at = [&](int line, int pos) { return DIR == 0 ? line * LP + pos : pos * LP + line; };
   const int npairs = (N + 1) / 2;
+  // odd-extension source position and sign of this lane's R values (independent of the pair)
+  int srcp[R];
+  double sgn[R];
+#pragma unroll
+  for (int j1 = 0; j1 < R; ++j1) {
+    const int jn = 64 * j1 + lane;
+    const bool lo = jn >= 1 && jn <= N, hi = jn > L;
+    srcp[j1] = lo ? jn - 1 : hi ? M - jn - 1 : 0;
+    sgn[j1] = lo ? 1.0 : hi ? -1.0 : 0.0;
+  }
   for (int pr = wave; pr < npairs; pr += kKW) {
-    const int la = 2 * pr, lb = 2 * pr + 1;
-    const bool hb = lb < N;
+    const int la = 2 * pr, lb = min(2 * pr + 1, N - 1);
+    const double bmask = 2 * pr + 1 < N ? 1.0 : 0.0;
     double2 v[R];
 #pragma unroll
     for (int j1 = 0; j1 < R; ++j1) {
-      const int jn = 64 * j1 + lane;             // index into the odd extension
-      int src = -1;
-      double sg = 1.0;
-      if (jn >= 1 && jn <= N) src = jn - 1;
-      else if (jn > L) { src = M - jn - 1; sg = -1.0; }
-      double a = 0.0, b = 0.0;
-      if (src >= 0) {
-        a = sg * X[at(la, src)];
-        if (hb) b = sg * X[at(lb, src)];
-      }
-      v[j1] = make_double2(a, b);
+      const double a = X[at(la, srcp[j1])], b = X[at(lb, srcp[j1])];
+      v[j1] = make_double2(sgn[j1] * a, sgn[j1] * bmask * b);
     }
-    wave_dft<R>(v, lane, tw);
+    wave_dft<R>(v, lane, W);
     const int k2 = brev6(lane);
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       const int K = k1 + R * k2;
       if (K >= 1 && K <= N) {
         X[at(la, K - 1)] = -v[k1].y * scale;
-        if (hb) X[at(lb, K - 1)] = v[k1].x * scale;
+        if (2 * pr + 1 < N) X[at(lb, K - 1)] = v[k1].x * scale;
       }
     }
   }
@@ -120,10 +172,11 @@ __device__ __forceinline__ void dst_level(double *X, int N, int LP, const double
 template <int R, int KMAX>
 __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int wave, int lane) {
   const int N = K.N, LP = N + 2;
-  const double2 *tw = reinterpret_cast<const double2 *>(K.tw);
-  dst_level<R, 0>(X, N, LP, tw, K.scale, wave, lane);
+  Twiddles<R> W;
+  W.load(reinterpret_cast<const double2 *>(K.tw), lane);
+  dst_level<R, 0>(X, N, LP, W, K.scale, wave, lane);
   __syncthreads();
-  dst_level<R, 1>(X, N, LP, tw, K.scale, wave, lane);
+  dst_level<R, 1>(X, N, LP, W, K.scale, wave, lane);
   __syncthreads();
   double kv[KMAX];
 #pragma unroll
@@ -152,9 +205,9 @@ __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int 
     }
   }
   __syncthreads();
-  dst_level<R, 0>(X, N, LP, tw, K.scale, wave, lane);
+  dst_level<R, 0>(X, N, LP, W, K.scale, wave, lane);
   __syncthreads();
-  dst_level<R, 1>(X, N, LP, tw, K.scale, wave, lane);
+  dst_level<R, 1>(X, N, LP, W, K.scale, wave, lane);
   __syncthreads();
 }
 
@@ -211,34 +264,24 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const T *st = s + (size_t)t * ld;
     const T *s1 = t >= 1 ? st - ld : nullptr;
     const T *s2 = t >= 2 ? st - 2 * ld : nullptr;
-    double id[KMAX], zf[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int e = tid + k * kKT;
-      id[k] = 0.0;
-      zf[k] = 0.0;
-      if (e < m) {
-        const double v0 = (double)st[e];
-        const double v1 = s1 ? (double)s1[e] : 0.0;
-        const double v2 = s2 ? (double)s2[e] : 0.0;
-        id[k] = c0 * v0 + c1 * v1 + c2 * v2;
-        const int jr = e / N, ir = e - jr * N;
-        X[jr * LP + ir] = b0 * v0 + b1 * v1;
-        if (MODE == 1) zf[k] = (double)s[(size_t)(n - 1 - t) * ld + e];
-      }
+    for (int e = tid; e < m; e += kKT) {
+      const double v0 = (double)st[e];
+      const double v1 = s1 ? (double)s1[e] : 0.0;
+      const int jr = e / N, ir = e - jr * N;
+      X[jr * LP + ir] = b0 * v0 + b1 * v1;
     }
     __syncthreads();
     uku_level<R, KMAX>(X, K, tid, wave, lane);
     double *q = K.q + (size_t)t * ld;
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int e = tid + k * kKT;
-      if (e < m) {
-        const int jr = e / N, ir = e - jr * N;
-        const double v = id[k] + K.tau * X[jr * LP + ir];
-        q[e] = v;
-        if (MODE == 1) acc_d += v * zf[k];
-      }
+    const T *sf = s + (size_t)(n - 1 - t) * ld;
+    for (int e = tid; e < m; e += kKT) {
+      const double v0 = (double)st[e];
+      const double v1 = s1 ? (double)s1[e] : 0.0;
+      const double v2 = s2 ? (double)s2[e] : 0.0;
+      const int jr = e / N, ir = e - jr * N;
+      const double v = c0 * v0 + c1 * v1 + c2 * v2 + K.tau * X[jr * LP + ir];
+      q[e] = v;
+      if (MODE == 1) acc_d += v * (double)sf[e];
     }
   }
   // ---- true residual ||b^ - (T x)^||^2 on level t
@@ -248,30 +291,21 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const double *x1 = t >= 1 ? xt - ld : nullptr;
     const double *x2 = t >= 2 ? xt - 2 * ld : nullptr;
     const double *bt = K.bh + (size_t)t * ld;
-    double rb[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int e = tid + k * kKT;
-      rb[k] = 0.0;
-      if (e < m) {
-        const double v0 = xt[e];
-        const double v1 = x1 ? x1[e] : 0.0;
-        const double v2 = x2 ? x2[e] : 0.0;
-        rb[k] = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2);
-        const int jr = e / N, ir = e - jr * N;
-        X[jr * LP + ir] = b0 * v0 + b1 * v1;
-      }
+    for (int e = tid; e < m; e += kKT) {
+      const double v0 = xt[e];
+      const double v1 = x1 ? x1[e] : 0.0;
+      const int jr = e / N, ir = e - jr * N;
+      X[jr * LP + ir] = b0 * v0 + b1 * v1;
     }
     __syncthreads();
     uku_level<R, KMAX>(X, K, tid, wave, lane);
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int e = tid + k * kKT;
-      if (e < m) {
-        const int jr = e / N, ir = e - jr * N;
-        const double r = rb[k] - K.tau * X[jr * LP + ir];
-        acc_r += r * r;
-      }
+    for (int e = tid; e < m; e += kKT) {
+      const double v0 = xt[e];
+      const double v1 = x1 ? x1[e] : 0.0;
+      const double v2 = x2 ? x2[e] : 0.0;
+      const int jr = e / N, ir = e - jr * N;
+      const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2) - K.tau * X[jr * LP + ir];
+      acc_r += r * r;
     }
   }
   // ---- partials [residual^2, residual skipped, 0, delta] of this level
