@@ -109,6 +109,10 @@ typedef struct {
   int32_t status;          /* smr_status of the solve                                     */
   double relres_true;      /* ||f_H - T x||_2 / ||f_H||_2 at exit (float64 matvec)        */
   double relres_prec;      /* |eta| / gamma_1: relative P^{-1}-norm residual estimate     */
+  int32_t res_evals;       /* true residuals evaluated (the initial one included); the
+                              sine-basis path skips those that sqrt(min sigma) |eta| proves
+                              to exceed the tolerance                                     */
+  int32_t reserved;
 } smr_info;
 
 /* Bytes of device workspace needed by a plan for `desc` (Sec. 3.1.1: O(nm) storage). */

@@ -122,6 +122,7 @@ __device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double 
     // s0 = ||v_1||^2, s1 = ||b||^2, s2 = gamma_1^2, s3 = <T^ z_1, z_1>
     sc->bnorm = sqrt(s1);
     sc->iter = 0;
+    sc->nres = 1;
     sc->exact = 0;
     sc->status = RUNNING;
     if (s1 == 0.0) { sc->relres = 0.0; sc->status = DONE_CONV; return; }
@@ -142,6 +143,7 @@ __device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double 
   sc->iter += 1;                                  // launches since INIT = j
   if (pmode == MODE_STEADY) {
     if (have_res) {
+      sc->nres += 1;
       sc->relres = sqrt(s0) / sc->bnorm;          // of x_{j-1}
       if (sc->relres <= sc->rtol) { sc->iter -= 1; sc->status = DONE_CONV; return; }
     }
@@ -300,7 +302,8 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     block_sum4(u, red);
     if (tid == 0) {
       S = *sprev;
-      scalar_update(&S, pmode, t[0], t[1], t[2], t[3], u[0] == 0.0);
+      // slot 1 of a steady launch flags a skipped residual (it holds ||b||^2 after INIT)
+      scalar_update(&S, pmode, t[0], t[1], t[2], t[3], u[0] == 0.0 && (pmode != MODE_STEADY || t[1] == 0.0));
       if (tile == 0) *snew = S;
     }
     __syncthreads();
@@ -319,6 +322,11 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   double *__restrict__ xv = P.x;
 
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
+  // the true residual of x_{j-1} is needed only once sqrt(min sigma) |eta| (a lower bound of
+  // ||r||_2, |eta| being ||r||_{P^-1}) no longer excludes convergence, or at the iteration limit
+  const bool bres = MODE == MODE_STEADY && !P.qext &&
+                    (P.sqsigmin * fabs(S.eta) <= 2.0 * S.rtol * S.bnorm || S.iter >= S.maxit);
+  if (MODE == MODE_STEADY && !P.qext && !bres && tid == 0) acc_b = 1.0;
 
   // ---- B (steady launches, streaming waves 4..7): lagged w_{j-1}, x_{j-1} and the true
   //      residual of x_{j-1}, streamed over time levels with x carried for the stencil.  Each
@@ -349,7 +357,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
       if (bok) {
         wb[i] = w;
         xv[i] = x0;
-        if (!P.qext) {    // variable a: the per-level matvec takes the true residual
+        if (bres) {       // (variable a: the per-level matvec takes the true residual)
           const double r = bh[i] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
           acc_r += r * r;
         }
@@ -599,6 +607,7 @@ int spec_blocks(const Plan *p) {
 
 SpecP spec_desc(const Plan *p, double *x, const double *bh) {
   SpecP P{};
+  P.sqsigmin = p->sqsigmin;
   P.n = p->n; P.m = p->m; P.ld = p->ld; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
   P.tiles = spec_blocks(p);
   P.tile0 = 0;

@@ -607,6 +607,8 @@ smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
     info->status = res;
     info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
     info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
+    info->res_evals = h.nres;
+    info->reserved = 0;
   }
   return res;
 }
@@ -733,6 +735,8 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, doub
     info->status = res;
     info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
     info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
+    info->res_evals = h.iter + 1;      // the physical-basis iteration evaluates every one
+    info->reserved = 0;
   }
   return res;
 }

@@ -32,6 +32,7 @@ struct Scal {
   double va, vb;                        // v_{j+1} = q - va v_j - vb v_{j-1}
   double rtol;
   int iter, status, maxit, exact;
+  int nres, pad;                        // true residuals evaluated so far
 };
 
 // Host-side plan: parameters plus device pointers into the caller's workspace.
@@ -118,6 +119,7 @@ hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, cons
 struct SpecP {
   int n, m, ld, h1, h2, scheme, tiles, tile0;   // ld: row stride of the vectors below
   double theta;
+  double sqsigmin;       // sqrt of the smallest eigenvalue of P (residual lower bound)
   const void *So, *SoT, *Se, *SeT;   // folded sine tables in the transform's precision
   const double *tcoef, *tmu;
   // vectors (spatial-sine basis, (n, ld) row-major); z in the transform's precision.  Launch j uses

@@ -135,6 +135,12 @@ def test_minres_iterate_parity(dim, N, n, scheme, theta, precond, kind, general)
     assert info["relres_true"] <= 1e-8
     assert abs(info["relres_true"] - ref.relres_true) <= 1e-6 * ref.relres_true + 1e-14
     assert abs(info["relres_prec"] - ref.relres_prec) <= 1e-6 * ref.relres_prec + 1e-14
+    # the physical basis evaluates every true residual; the sine basis at least the initial
+    # and the deciding one (the skipped ones were excluded by sqrt(min sigma) |eta|)
+    if general or precond != "PH":
+        assert info["res_evals"] == info["iters"] + 1
+    else:
+        assert 1 + (info["iters"] > 0) <= info["res_evals"] <= info["iters"] + 1
 
 
 def test_minres_unpreconditioned_iterates():
