@@ -117,6 +117,40 @@ def batched_bdf2_leg(dev, warmup: int, steps: int, rtol: float):
             "mixed_iters_per_s": sum(it_m) / t_mixed, "plain_iters_per_s": sum(it_p) / t_plain}
 
 
+def paper_tables_leg(dev, reps: int = 3):
+    """The largest row of each of the paper's Tables 1-4 (n = 256, m + 1 = 256, 16.6 M
+    unknowns, tolerance 1e-6, P_H) solved here, beside the iteration counts and MATLAB CPU
+    seconds the paper prints for them (dual 16-core Xeon Gold 6246R, 3.4 GHz, Sec. 5)."""
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Plan
+    rows = []
+    path = os.path.join(ROOT, "tests", "golden", "paper_tables_full.txt")
+    with open(path) as fh:
+        for line in fh:
+            r = line.split()
+            if r and not line.startswith("#") and r[3] == "256" and r[4] == "256":
+                rows.append(r)
+    out = []
+    for r in rows:
+        tab, ex, theta, n, mp1 = r[0], r[1], float(r[2]), int(r[3]), int(r[4])
+        N = mp1 - 1
+        p = W.example1(N, n, theta) if ex == "1" else W.example2(N, n, theta)
+        g = Plan(2, N, n, theta=theta, ax=p.ax, ay=p.ay, device=dev)
+        b = g.build_rhs(torch.from_numpy(p.f.reshape(-1)).to(dev), torch.from_numpy(p.u0).to(dev))
+        g.solve(b, rtol=1e-6, maxit=200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x, info = g.solve(b, rtol=1e-6, maxit=200)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        out.append({"table": tab, "n": n, "m_plus_1": mp1, "dof": n * N * N, "iters": info["iters"],
+                    "paper_iters": int(r[6]), "gpu_ms": ms, "paper_cpu_s": float(r[7])})
+        del g, b, x
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +273,7 @@ def main() -> int:
                          "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
     if not args.no_batch:
         out["batched_bdf2"] = batched_bdf2_leg(dev, warmup=1, steps=2, rtol=args.rtol)
+        out["paper_tables_largest"] = paper_tables_leg(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
