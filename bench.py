@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -151,6 +153,63 @@ def paper_tables_leg(dev, reps: int = 3):
     return out
 
 
+def variable_coef_leg(dev, rtol: float):
+    """The variable-coefficient workload (N = 255, n = 512, backward Euler,
+    a = 1 + 0.5 sin(2 pi x) sin(2 pi y) at faces, f ~ U(-1, 1), seed 1): P_theta with the
+    3-step Chebyshev per-mode solve, and P_H(Kbar) beside it (float64, physical-basis path)."""
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Plan
+    p = W.variable_coef_2d()
+    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    out = {"workload": f"varcoef2d_N{p.N}_n{p.n}", "dof": p.n * p.m, "rtol": rtol}
+    for name, kw in (("P_theta_cheb3", {"precond": "PTHETA_CHEB", "cheb_k": 3}), ("P_H_kbar", {})):
+        g = Plan(2, p.N, p.n, theta=p.theta, ax=p.ax, ay=p.ay, device=dev, **kw)
+        b = g.build_rhs(f, u0)
+        g.solve(b, rtol=rtol, maxit=400)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = g.solve(b, rtol=rtol, maxit=400)
+        torch.cuda.synchronize()
+        out[name] = {"time_to_tol_ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
+                     "relres_true": info["relres_true"], "status": info["status"]}
+        del g, b, x
+    return out
+
+
+def differentiable_leg(dev, rtol: float):
+    """The differentiable-solve workload (N = 127, n = 256, backward Euler, 16 Gaussian-bump
+    sources, u0 = 0): loss = ||u(f, a) - u_obs||^2 at nodal a = 1 with u_obs solved at
+    a = 1 + 0.3 x y; one forward (batched MINRES) + backward (batched adjoint MINRES, adjoint
+    right-hand side, coefficient gradient) through torch.autograd."""
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd.autograd import heat_solve
+    probs, a_truth = W.inverse_problem_2d()
+    f = torch.from_numpy(np.stack([q.f for q in probs])).to(dev)
+    with torch.no_grad():
+        uobs = heat_solve(f, torch.from_numpy(a_truth).to(dev), None, rtol=rtol)
+
+    def step():
+        ft = f.clone().requires_grad_(True)
+        at = torch.ones_like(torch.from_numpy(a_truth)).to(dev).requires_grad_(True)
+        u = heat_solve(ft, at, None, rtol=rtol)
+        loss = ((u - uobs) ** 2).sum()
+        loss.backward()
+        return at.grad
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ga = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"workload": "inverse_problem_N127_n256_batch16", "dof_per_source": probs[0].n * probs[0].m,
+            "sources": len(probs), "forward_backward_ms": ms, "rtol": rtol,
+            "grad_a_norm": float(ga.norm())}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +217,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance BDF2 batch comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="only the headline workload (skip the batch, paper-table, variable-coefficient "
+                         "and differentiable legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -274,6 +335,8 @@ def main() -> int:
     if not args.no_batch:
         out["batched_bdf2"] = batched_bdf2_leg(dev, warmup=1, steps=2, rtol=args.rtol)
         out["paper_tables_largest"] = paper_tables_leg(dev)
+        out["variable_coefficient"] = variable_coef_leg(dev, args.rtol)
+        out["differentiable"] = differentiable_leg(dev, args.rtol)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
