@@ -47,7 +47,11 @@ enum ProfClass { PROF_TIME = 0, PROF_DST = 1, PROF_STENCIL = 2, PROF_VEC = 3, PR
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;                     // free events
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[PROF_NCLASS];
+  struct Rec {
+    hipEvent_t a, b;
+    int count;                                      // launches between the two events
+  };
+  std::vector<Rec> rec[PROF_NCLASS];
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -66,21 +70,32 @@ struct Profiler {
     for (int i = 0; i < PROF_NCLASS; ++i) k.n[i] = rec[i].size();
     return k;
   }
+  void drop_back(int i) {
+    pool.push_back(rec[i].back().a);
+    pool.push_back(rec[i].back().b);
+    rec[i].pop_back();
+  }
   // drop the records made after mark k (launches that exited without work)
   void truncate(const Mark &k) {
-    for (int i = 0; i < PROF_NCLASS; ++i) {
-      while (rec[i].size() > k.n[i]) {
-        pool.push_back(rec[i].back().first);
-        pool.push_back(rec[i].back().second);
-        rec[i].pop_back();
-      }
+    for (int i = 0; i < PROF_NCLASS; ++i)
+      while (rec[i].size() > k.n[i]) drop_back(i);
+  }
+  // of class i's records after mark k keep those covering the first `keep` launches (a
+  // record that straddles the limit keeps its time and counts only the launches inside)
+  void keep_launches(const Mark &k, int i, long keep) {
+    size_t r = k.n[i];
+    long seen = 0;
+    for (; r < rec[i].size() && seen < keep; ++r) {
+      if (seen + rec[i][r].count > keep) rec[i][r].count = (int)(keep - seen);
+      seen += rec[i][r].count;
     }
+    while (rec[i].size() > r) drop_back(i);
   }
   void clear() {
     for (auto &r : rec) {
       for (auto &pr : r) {
-        pool.push_back(pr.first);
-        pool.push_back(pr.second);
+        pool.push_back(pr.a);
+        pool.push_back(pr.b);
       }
       r.clear();
     }
@@ -91,8 +106,9 @@ Profiler g_prof;
 struct ProfScope {
   int cls;
   hipStream_t st;
+  int count;
   hipEvent_t a = nullptr;
-  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+  ProfScope(int c, hipStream_t s, int n = 1) : cls(c), st(s), count(n) {
     if (g_prof.on) {
       a = g_prof.get();
       if (a) hipEventRecord(a, st);
@@ -103,7 +119,7 @@ struct ProfScope {
       hipEvent_t b = g_prof.get();
       if (b) {
         hipEventRecord(b, st);
-        g_prof.rec[cls].push_back({a, b});
+        g_prof.rec[cls].push_back({a, b, count});
       } else {
         g_prof.pool.push_back(a);
       }
@@ -509,6 +525,13 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
 }
 
 smr_status smr_destroy(smr_plan *plan) {
+  if (plan) {
+    const Plan &p = plan->p;
+    if (p.steady6) hipGraphExecDestroy(p.steady6);
+    if (p.snap) hipHostFree(p.snap);
+    for (hipEvent_t e : p.snap_ev)
+      if (e) hipEventDestroy(e);
+  }
   delete plan;
   return SMR_OK;
 }
@@ -613,6 +636,52 @@ smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
   return res;
 }
 
+// Pinned host status snapshots of a plan (two, used alternately) and their events.
+smr_status ensure_snapshots(const Plan &p) {
+  if (!p.snap) HIP_TRY(hipHostMalloc((void **)&p.snap, 2 * sizeof(Scal), hipHostMallocDefault));
+  for (hipEvent_t &e : p.snap_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return SMR_OK;
+}
+
+// Stream that graphs are captured on (the caller's stream may be the legacy default stream,
+// which cannot be captured); default priority, never used to run work.
+hipStream_t capture_stream() {
+  static hipStream_t cs = nullptr;
+  if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+  return cs;
+}
+
+// Six consecutive steady launches j = 6..11 of the sine-basis solve (with the per-level
+// matvec for a variable coefficient), captured once per plan.  Their arguments depend on j
+// only through j mod 6 (buffer rotation, launch parity) and j >= 3, so the same graph runs
+// launches 6k..6k+5 for every k >= 1.  The vectors are the plan's own (b^ in T1, x^ in T2).
+smr_status ensure_steady_graph(const Plan &p, double *Xh, const double *Bh) {
+  if (p.steady6) return SMR_OK;
+  hipStream_t cs = capture_stream();
+  if (!cs) return fail(SMR_EDEVICE, "no capture stream");
+  Ctx cc{&p, cs};
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int j = 6; j < 12 && e == hipSuccess; ++j) {
+    if (!p.const_coef) e = launch_kslice(cc, 1, j, Xh, Bh);
+    if (e == hipSuccess) e = launch_spec(cc, 2, j, Xh, Bh);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(SMR_EDEVICE, "capturing the steady iterations failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(SMR_EDEVICE, "instantiating the steady iterations failed: %s", hipGetErrorString(e3));
+  p.steady6 = ex;
+  return SMR_OK;
+}
+
 // Constant coefficients: the whole MINRES runs in the spatial sine basis with one fused
 // kernel per iteration; b and x0 are transformed on entry, the iterate on exit.
 smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
@@ -636,27 +705,57 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
   if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 0, 0, Xh, Bh));
   LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
   const Profiler::Mark m0 = g_prof.mark();
-  int issued = 0;            // launches j = 1..issued enqueued; sc[issued & 1] is the latest state
-  int chunk = 4;
-  const int last = maxit + 2;   // launch maxit + 2 takes the stop decision on iteration maxit
-  for (;;) {
-    HIP_TRY(hipMemcpyAsync(&h, p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (h.status != RUNNING || issued >= last) break;
-    const int todo = std::min(chunk, last - issued);
-    for (int it = 0; it < todo; ++it) {
-      const int j = issued + it + 1;
-      if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 1, j, Xh, Bh));
-      LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, j, Xh, Bh));
+  st = ensure_snapshots(p);
+  if (st != SMR_OK) return st;
+  // launches j >= 6 replay six captured iterations, except while profiling a variable-
+  // coefficient solve (a replay's events could not separate its two kernels)
+  const bool graph = !(g_prof.on && ext) && ensure_steady_graph(p, Xh, Bh) == SMR_OK;
+  int issued = 0;                   // launches j = 1..issued enqueued
+  const int last = maxit + 2;       // launch maxit + 2 takes the stop decision on iteration maxit
+  int pend[2], npend = 0, slot_next = 0;
+  // enqueue the next chunk and a snapshot of the state after it (pinned host copy + event)
+  auto enqueue_next = [&]() -> smr_status {
+    if (issued < 5 || !graph) {
+      const int todo = std::min(issued < 5 ? 5 - issued : 6, last - issued);
+      for (int it = 0; it < todo; ++it) {
+        const int j = issued + it + 1;
+        if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 1, j, Xh, Bh));
+        LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, j, Xh, Bh));
+      }
+      issued += todo;
+    } else {                        // issued + 1 is a multiple of 6 here
+      ProfScope ps(PROF_SPEC, s, 6);
+      HIP_TRY(hipGraphLaunch(p.steady6, s));
+      issued += 6;
     }
-    issued += todo;
-    chunk = std::min(chunk * 2, 16);
+    HIP_TRY(hipMemcpyAsync(&p.snap[slot_next], p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(p.snap_ev[slot_next], s));
+    pend[npend++] = slot_next;
+    slot_next ^= 1;
+    return SMR_OK;
+  };
+  // keep one chunk in flight ahead of the status being checked, so the device never waits
+  st = enqueue_next();
+  if (st != SMR_OK) return st;
+  for (;;) {
+    if (issued < last && npend < 2) {
+      st = enqueue_next();
+      if (st != SMR_OK) return st;
+    }
+    const int slot = pend[0];
+    pend[0] = pend[1];
+    --npend;
+    HIP_TRY(hipEventSynchronize(p.snap_ev[slot]));
+    h = p.snap[slot];
+    if (h.status != RUNNING) break;
+    if (npend == 0 && issued >= last) break;
   }
+  // launches after the decision pass the state on: the latest slot holds the final state
+  HIP_TRY(hipMemcpyAsync(&h, p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   if (g_prof.on) {   // keep the records of the launches that did work (j = 1 .. iter + 1)
-    Profiler::Mark k = m0;
-    k.n[PROF_SPEC] += (size_t)std::min(issued, h.iter + 1);
-    if (ext) k.n[PROF_KSLICE] += (size_t)std::min(issued, h.iter + 1);
-    g_prof.truncate(k);
+    g_prof.keep_launches(m0, PROF_SPEC, std::min(issued, h.iter + 1));
+    if (ext) g_prof.keep_launches(m0, PROF_KSLICE, std::min(issued, h.iter + 1));
   }
   if (h.status == DONE_CONV && h.bnorm == 0.0) {
     LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
@@ -1007,13 +1106,15 @@ smr_status smr_profile_enable(int32_t on) {
 smr_status smr_profile_read(int32_t cls, int32_t *launches, double *total_ms) {
   if (cls < 0 || cls >= PROF_NCLASS || !launches || !total_ms) return fail(SMR_EINVAL, "bad profile query");
   double tot = 0.0;
+  long n = 0;
   for (auto &pr : g_prof.rec[cls]) {
-    HIP_TRY(hipEventSynchronize(pr.second));
+    HIP_TRY(hipEventSynchronize(pr.b));
     float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    HIP_TRY(hipEventElapsedTime(&ms, pr.a, pr.b));
     tot += ms;
+    n += pr.count;
   }
-  *launches = (int32_t)g_prof.rec[cls].size();
+  *launches = (int32_t)n;
   *total_ms = tot;
   return SMR_OK;
 }

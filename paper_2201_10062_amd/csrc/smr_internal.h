@@ -65,6 +65,10 @@ struct Plan {
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
   double *part;               // 16 * kRedSlots partial sums
   Scal *sc;                   // device scalars (2 slots; the physical-basis path uses slot 0)
+  // host-side resources of the sine-basis solve, made on first use, released by smr_destroy
+  mutable hipGraphExec_t steady6 = nullptr;          // six captured steady iterations
+  mutable Scal *snap = nullptr;                      // two pinned host status snapshots
+  mutable hipEvent_t snap_ev[2] = {nullptr, nullptr};
   Scal *sc_host;              // pinned host mirror
   size_t ws_bytes;
 };

@@ -313,3 +313,21 @@ def test_batched_single_and_empty():
     assert infos[0]["iters"] == info1["iters"] and rel(_n(xs[0]), _n(x1)) < 1e-13
     xs, infos = Batch([]).solve([], rtol=1e-8)
     assert xs == [] and infos == []
+
+
+@pytest.mark.parametrize("kind", ["const", "var"])
+def test_repeated_solves_replay_captured_iterations(kind):
+    """Steady iterations from the sixth on replay a graph captured at the plan's first solve.
+    Several solves on one plan, with other eager work and synchronisations between them, each
+    run several replays; every one must equal the oracle."""
+    N, n = 31, 24
+    g, o = _pair(2, N, n, "theta", 0.5, kind="var" if kind == "var" else "const")
+    rng = np.random.default_rng(21)
+    for rep in range(4):
+        b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m))
+        ref = o.solve(b, rtol=1e-11, maxit=400)
+        x, info = g.solve(_t(b), rtol=1e-11, maxit=400)
+        assert info["iters"] == ref.iters and info["iters"] >= 18, (rep, info, ref.iters)
+        assert rel(_n(x), ref.x) < 1e-9
+        y = g.apply_A(_t(b))                     # eager work between the solves
+        assert rel(_n(y), o.apply_YT(b)) < 1e-12
