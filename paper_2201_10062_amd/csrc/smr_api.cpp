@@ -682,6 +682,54 @@ smr_status ensure_steady_graph(const Plan &p, double *Xh, const double *Bh) {
   return SMR_OK;
 }
 
+// Captured steady iterations of batched solves, keyed by the batch workspace address and the
+// class layout of the launches (a few recent layouts are kept).
+template <typename F>
+hipGraphExec_t batch_graph(const std::vector<long> &key, F &&enqueue) {
+  struct Entry {
+    std::vector<long> key;
+    hipGraphExec_t ex;
+  };
+  static std::vector<Entry> cache;
+  for (const Entry &en : cache)
+    if (en.key == key) return en.ex;
+  hipStream_t cs = capture_stream();
+  if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  const hipError_t e = enqueue(cs);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &g);
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess && e2 == hipSuccess && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+  if (g) hipGraphDestroy(g);
+  if (!ex) return nullptr;
+  if (cache.size() >= 8) {
+    hipGraphExecDestroy(cache.front().ex);
+    cache.erase(cache.begin());
+  }
+  cache.push_back(Entry{key, ex});
+  return ex;
+}
+
+// Pinned host status snapshots for batched solves (two slots of `cap` instances).
+struct BatchSnap {
+  Scal *h = nullptr;
+  int cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+BatchSnap &batch_snapshots(int count) {
+  static BatchSnap bs;
+  if (count > bs.cap) {
+    if (bs.h) hipHostFree(bs.h);
+    bs.h = nullptr;
+    bs.cap = 0;
+    if (hipHostMalloc((void **)&bs.h, 2 * sizeof(Scal) * (size_t)count, hipHostMallocDefault) == hipSuccess)
+      bs.cap = count;
+  }
+  for (hipEvent_t &e : bs.ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  return bs;
+}
+
 // Constant coefficients: the whole MINRES runs in the spatial sine basis with one fused
 // kernel per iteration; b and x0 are transformed on entry, the iterate on exit.
 smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
@@ -975,28 +1023,79 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
     for (const Class &cl : classes)
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, 0, 0));
-    std::vector<Scal> hs(ns);
-    int issued = 0, chunk = 4;
-    const int last = maxit + 2;
-    for (;;) {
-      HIP_TRY(launch_gather_scal(s, d_table, ns, issued & 1, d_scal));
-      HIP_TRY(hipMemcpyAsync(hs.data(), d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      bool running = false;
-      for (const Scal &h : hs) running |= (h.status == RUNNING);
-      if (!running || issued >= last) break;
-      const int todo = std::min(chunk, last - issued);
-      for (int it = 0; it < todo; ++it) {
-        const int j = issued + it + 1;
-        for (const KClass &cl : kclasses)
-          LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
-        for (const Class &cl : classes)
-          LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec,
-                                              j == 1 ? 1 : 2, j));
-      }
-      issued += todo;
-      chunk = std::min(chunk * 2, 16);
+    // one iteration j: the per-level matvec of every N class, then the fused launch of every
+    // time-size class
+    auto iteration = [&](hipStream_t st, int j) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (const KClass &cl : kclasses)
+        if (e == hipSuccess) e = launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j);
+      for (const Class &cl : classes)
+        if (e == hipSuccess)
+          e = launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, j == 1 ? 1 : 2, j);
+      return e;
+    };
+    // steady iterations j >= 6 replay a captured graph of six (cached by workspace and class
+    // layout; the tables it reads are re-uploaded above on every call), except while profiling
+    hipGraphExec_t g6 = nullptr;
+    if (!g_prof.on) {
+      std::vector<long> key{(long)(uintptr_t)d_ws};
+      for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
+      for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.pprec});
+      g6 = batch_graph(key, [&](hipStream_t cs) {
+        hipError_t e = hipSuccess;
+        for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration(cs, j);
+        return e;
+      });
     }
+    BatchSnap &bs = batch_snapshots(ns);
+    if (!bs.h) return fail(SMR_EDEVICE, "pinned status buffer");
+    std::vector<Scal> hs(ns);
+    int issued = 0;
+    const int last = maxit + 2;
+    int pend[2], npend = 0, slot_next = 0;
+    auto enqueue_next = [&]() -> smr_status {
+      if (issued < 5 || !g6) {
+        const int todo = std::min(issued < 5 ? 5 - issued : 6, last - issued);
+        for (int it = 0; it < todo; ++it) {
+          const int j = issued + it + 1;
+          for (const KClass &cl : kclasses)
+            LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
+          for (const Class &cl : classes)
+            LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec,
+                                                j == 1 ? 1 : 2, j));
+        }
+        issued += todo;
+      } else {
+        HIP_TRY(hipGraphLaunch(g6, s));
+        issued += 6;
+      }
+      HIP_TRY(launch_gather_scal(s, d_table, ns, issued & 1, d_scal));
+      HIP_TRY(hipMemcpyAsync(bs.h + (size_t)slot_next * bs.cap, d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(bs.ev[slot_next], s));
+      pend[npend++] = slot_next;
+      slot_next ^= 1;
+      return SMR_OK;
+    };
+    smr_status st0 = enqueue_next();
+    if (st0 != SMR_OK) return st0;
+    for (;;) {
+      if (issued < last && npend < 2) {
+        st0 = enqueue_next();
+        if (st0 != SMR_OK) return st0;
+      }
+      const int slot = pend[0];
+      pend[0] = pend[1];
+      --npend;
+      HIP_TRY(hipEventSynchronize(bs.ev[slot]));
+      bool running = false;
+      for (int k = 0; k < ns; ++k) running |= (bs.h[(size_t)slot * bs.cap + k].status == RUNNING);
+      if (!running) break;
+      if (npend == 0 && issued >= last) break;
+    }
+    // launches after each instance's decision pass its state on: the latest slots are final
+    HIP_TRY(launch_gather_scal(s, d_table, ns, issued & 1, d_scal));
+    HIP_TRY(hipMemcpyAsync(hs.data(), d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < ns; ++k) {
       const int i = spec_ids[k];
       const Plan &p = plans[i]->p;

@@ -198,3 +198,23 @@ def test_var_sine_basis_full_size_variable_workload_slice():
     assert r <= 1e-8 and abs(r - info["relres_true"]) <= 1e-3 * r
     u = o.solve_direct(b)
     assert rel(x, u) < 1e-6
+
+
+def test_batched_repeated_calls_replay_captured_iterations():
+    """Batched steady iterations replay a graph cached by workspace and class layout: three
+    calls on one batch, with eager single solves between them, each equal to the oracle."""
+    from paper_2201_10062_amd import Batch, Plan
+    probs = W.bdf2_batch(count=9, Ns=(15, 31, 63), ns=(16, 24, 32))
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    batch = Batch(plans)
+    systems = [System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    rng = np.random.default_rng(22)
+    extra = Plan(2, 31, 8, theta=0.5)
+    for rep in range(3):
+        bs = [rng.standard_normal(p.n * p.N * p.N) for p in probs]
+        xs, infos = batch.solve([_t(b) for b in bs], rtol=1e-10, maxit=600)
+        for p, o, b, x, info in zip(probs, systems, bs, xs, infos):
+            ref = o.solve(b, rtol=1e-10, maxit=600)
+            assert info["status"] == "ok" and info["iters"] == ref.iters, (rep, p.name, info, ref.iters)
+            assert rel(_n(x), ref.x) < 1e-9, (rep, p.name)
+        extra.solve(_t(rng.standard_normal(8 * 31 * 31)), rtol=1e-8)   # eager work between calls
