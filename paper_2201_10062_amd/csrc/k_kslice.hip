@@ -320,6 +320,33 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
   }
 }
 
+// Orthonormal 2D DST-I of every time level in one pass: the level (input slice stride sin)
+// goes into LDS, through the row and column transforms, and out with slice stride sout.
+template <int R>
+__global__ __launch_bounds__(kKT) void k_dst2d(const double *__restrict__ in, double *__restrict__ out, long sin,
+                                               long sout, const double *__restrict__ tw, double scale) {
+  extern __shared__ double X[];
+  constexpr int N = 32 * R - 1, LP = N + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double *src = in + (size_t)blockIdx.x * sin;
+  for (int e = tid; e < N * N; e += kKT) {
+    const int j = e / N, i = e - j * N;
+    X[j * LP + i] = src[e];
+  }
+  Twiddles<R> W;
+  W.load(reinterpret_cast<const double2 *>(tw), lane);
+  __syncthreads();
+  dst_level<R, 0>(X, N, LP, W, scale, wave, lane);
+  __syncthreads();
+  dst_level<R, 1>(X, N, LP, W, scale, wave, lane);
+  __syncthreads();
+  double *dst = out + (size_t)blockIdx.x * sout;
+  for (int e = tid; e < N * N; e += kKT) {
+    const int j = e / N, i = e - j * N;
+    dst[e] = X[j * LP + i];
+  }
+}
+
 template <int R, int PR, int MODE>
 __global__ __launch_bounds__(kKT) void k_kslice(KsP K, int jfull) {
   ks_body<R, PR, MODE>(K, jfull, blockIdx.x);
@@ -375,6 +402,26 @@ hipError_t run_ks_r(hipStream_t st, int L, const KsP *K, const KsP *table, int n
 }  // namespace
 
 bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128); }
+
+template <int R>
+static hipError_t run_dst2d(hipStream_t st, int n, const double *in, double *out, long sin, long sout,
+                            const double *tw) {
+  const size_t sh = (size_t)(32 * R - 1) * (32 * R + 1) * sizeof(double);
+  if (sh > 65536) hipFuncSetAttribute((const void *)k_dst2d<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL(k_dst2d<R>, dim3(n), dim3(kKT), sh, st, in, out, sin, sout, tw, 1.0 / sqrt(64.0 * R));
+  return hipGetLastError();
+}
+
+hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride) {
+  const Plan *p = c.p;
+  switch (p->L) {
+    case 32: return run_dst2d<1>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
+    case 64: return run_dst2d<2>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
+    case 128: return run_dst2d<4>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
 
 KsP kslice_desc(const Plan *p, double *x, const double *bh) {
   KsP K{};

@@ -606,6 +606,10 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
 // slice strides of in and out (m for physical vectors, ld for sine-basis ones)
 smr_status spatial_dst(const Plan &p, hipStream_t s, const double *in, double *out, long in_ld, long out_ld) {
   Ctx c{&p, s};
+  if (kslice_supported(&p) && in != out) {   // the whole level in LDS: one pass
+    LAUNCH(PROF_DST, launch_dst2d(c, in, out, in_ld, out_ld));
+    return SMR_OK;
+  }
   LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, nullptr, in_ld, out_ld));
   if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, nullptr, out_ld, out_ld));
   return SMR_OK;

@@ -154,6 +154,9 @@ struct KsP {
   const Scal *sc;
 };
 bool kslice_supported(const Plan *p);
+// 2D spatial sine transform of every time level in one pass (dim 2, N + 1 in {32, 64, 128});
+// out may equal in only when the strides agree
+hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride);
 KsP kslice_desc(const Plan *p, double *x, const double *bh);
 // mode 0: q = (T x)^ before the initialising launch; mode 1: q = (T z_j)^ with its partials
 // before fused launch j
