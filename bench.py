@@ -119,6 +119,35 @@ def batched_bdf2_leg(dev, warmup: int, steps: int, rtol: float):
             "mixed_iters_per_s": sum(it_m) / t_mixed, "plain_iters_per_s": sum(it_p) / t_plain}
 
 
+def manufactured_1d_leg(dev, rtol: float, reps: int = 20):
+    """The 1D manufactured-solution workload (N = 63, n = 64, backward Euler, a = 1,
+    u = sin(pi x) e^t, 4032 unknowns): latency-bound, so time-to-tolerance per solve, the
+    launches it takes, and the max error against the exact solution."""
+    import math
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Plan
+    p = W.manufactured_1d()
+    g = Plan(1, p.N, p.n, theta=p.theta, device=dev)
+    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    b = g.build_rhs(f, u0)
+    g.solve(b, rtol=rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.build_rhs(f, u0, out=b)
+        x, info = g.solve(b, rtol=rtol)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    xs = (np.arange(1, p.N + 1) / (p.N + 1))
+    t = np.arange(1, p.n + 1) / p.n
+    exact = np.sin(math.pi * xs)[None, :] * np.exp(t)[:, None]
+    err = float(np.abs(x.cpu().numpy().reshape(p.n, p.N) - exact).max())
+    return {"workload": "manufactured1d_N63_n64", "dof": p.n * p.N, "time_to_tol_ms": ms,
+            "iters": info["iters"], "rtol": rtol, "max_err_vs_exact": err}
+
+
 def paper_tables_leg(dev, reps: int = 3):
     """The largest row of each of the paper's Tables 1-4 (n = 256, m + 1 = 256, 16.6 M
     unknowns, tolerance 1e-6, P_H) solved here, beside the iteration counts and MATLAB CPU
@@ -334,6 +363,7 @@ def main() -> int:
                          "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
     if not args.no_batch:
         out["batched_bdf2"] = batched_bdf2_leg(dev, warmup=1, steps=2, rtol=args.rtol)
+        out["manufactured_1d"] = manufactured_1d_leg(dev, args.rtol)
         out["paper_tables_largest"] = paper_tables_leg(dev)
         out["variable_coefficient"] = variable_coef_leg(dev, args.rtol)
         out["differentiable"] = differentiable_leg(dev, args.rtol)

@@ -79,6 +79,15 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
  * variable-coefficient cases, P_theta and P = I run the general physical-basis iteration
  * (stencil matvec and 3D transforms), which this flag forces for every plan. */
 #define SMR_FLAG_GENERAL_PATH 1
+/* Column-tile width of the fused sine-basis kernel: each workgroup owns that many spatial
+ * modes of all n time levels (the folded time blocks of Sec. 3.1.1 are contracted per tile
+ * on the matrix cores).  With neither bit set, smr_setup times one steady iteration at each
+ * width on the plan's own workspace and keeps 32 unless 16 is at least 5% faster (narrow
+ * tiles pay off when the spatial grid is small); 32 needs ceil(n/2) <= 128 (SMR_EUNSUPPORTED
+ * otherwise) and ceil(n/2) > 128 always takes 16.  The width changes only the summation
+ * order of the reductions.  Setting both bits is SMR_EINVAL. */
+#define SMR_FLAG_TILE16 2
+#define SMR_FLAG_TILE32 4
 
 typedef struct {
   int32_t dim;             /* spatial dimension, 1 or 2                                   */
@@ -89,7 +98,8 @@ typedef struct {
   int32_t pprec;           /* smr_pprec                                                   */
   int32_t cheb_k;          /* Chebyshev steps per mode (SMR_P_THETA_CHEB), 1..16          */
   int32_t flags;           /* bit 0 (SMR_FLAG_GENERAL_PATH): iterate in the physical basis
-                            * even when a is constant; other bits must be 0              */
+                            * even when a is constant; bits 1, 2 (SMR_FLAG_TILE16/32):
+                            * fix the column-tile width; other bits must be 0           */
   double T;                /* final time (> 0)                                            */
   double theta;            /* theta-method parameter (SMR_THETA)                          */
   /* Coefficient a (host pointers, copied during smr_setup).  Give at most one form:
@@ -124,6 +134,10 @@ smr_status smr_workspace_size(const smr_desc *desc, size_t *bytes);
  * owned by the caller and kept alive until smr_destroy).  Synchronises `stream`. */
 smr_status smr_setup(const smr_desc *desc, void *d_ws, size_t ws_bytes, void *stream,
                      smr_plan **out);
+
+/* Column-tile width the plan's sine-basis solves launch with (16 or 32; see
+ * SMR_FLAG_TILE16), 0 when its solves run in the physical basis.  Host only. */
+smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols);
 
 /* Free the host-side plan (the workspace stays with the caller).  NULL is accepted. */
 smr_status smr_destroy(smr_plan *plan);

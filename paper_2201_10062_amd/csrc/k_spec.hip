@@ -21,6 +21,7 @@
 // is the same (first iteration whose true residual is <= rtol), one launch later.
 #include "smr_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace smr {
@@ -541,9 +542,9 @@ template <int HP, int C, int PR>
 hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
   else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
@@ -555,9 +556,9 @@ template <int HP, int C, int PR>
 hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
-    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0)
     hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
@@ -568,48 +569,75 @@ hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mod
   return hipGetLastError();
 }
 
-template <int PR>
+template <int PR, int C>
 hipError_t run_spec_hp(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
-    case 16: return run_spec<16, 32, PR>(st, P, mode, blocks, jph, pmode);
-    case 32: return run_spec<32, 32, PR>(st, P, mode, blocks, jph, pmode);
-    case 64: return run_spec<64, 32, PR>(st, P, mode, blocks, jph, pmode);
-    case 128: return run_spec<128, 32, PR>(st, P, mode, blocks, jph, pmode);
-    case 256: return run_spec<256, 16, PR>(st, P, mode, blocks, jph, pmode);
-    case 512: return run_spec<512, 16, PR>(st, P, mode, blocks, jph, pmode);
+    case 16: return run_spec<16, C, PR>(st, P, mode, blocks, jph, pmode);
+    case 32: return run_spec<32, C, PR>(st, P, mode, blocks, jph, pmode);
+    case 64: return run_spec<64, C, PR>(st, P, mode, blocks, jph, pmode);
+    case 128: return run_spec<128, C, PR>(st, P, mode, blocks, jph, pmode);
     default: break;
+  }
+  if constexpr (C == 16) {   // two 32-column LDS blocks of 256 or more rows do not fit
+    if (hp == 256) return run_spec<256, 16, PR>(st, P, mode, blocks, jph, pmode);
+    if (hp == 512) return run_spec<512, 16, PR>(st, P, mode, blocks, jph, pmode);
   }
   return hipErrorInvalidValue;
 }
 
-template <int PR>
-hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph, int pmode) {
+template <int PR, int C>
+hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph,
+                        int pmode) {
   switch (hp) {
-    case 16: return run_spec_multi<16, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
-    case 32: return run_spec_multi<32, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
-    case 64: return run_spec_multi<64, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
-    case 128: return run_spec_multi<128, 32, PR>(st, table, ninst, mode, blocks, jph, pmode);
-    case 256: return run_spec_multi<256, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
-    case 512: return run_spec_multi<512, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 16: return run_spec_multi<16, C, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 32: return run_spec_multi<32, C, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 64: return run_spec_multi<64, C, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    case 128: return run_spec_multi<128, C, PR>(st, table, ninst, mode, blocks, jph, pmode);
     default: break;
   }
+  if constexpr (C == 16) {
+    if (hp == 256) return run_spec_multi<256, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
+    if (hp == 512) return run_spec_multi<512, 16, PR>(st, table, ninst, mode, blocks, jph, pmode);
+  }
   return hipErrorInvalidValue;
+}
+
+hipError_t run_one(hipStream_t st, const SpecP &P, int pprec, int cols, int mode, int blocks, int hp, int jph,
+                   int pmode) {
+  if (cols == 16)
+    return pprec == SMR_FP32 ? run_spec_hp<1, 16>(st, P, mode, blocks, hp, jph, pmode)
+                             : run_spec_hp<0, 16>(st, P, mode, blocks, hp, jph, pmode);
+  if (cols == 32)
+    return pprec == SMR_FP32 ? run_spec_hp<1, 32>(st, P, mode, blocks, hp, jph, pmode)
+                             : run_spec_hp<0, 32>(st, P, mode, blocks, hp, jph, pmode);
+  return hipErrorInvalidValue;
+}
+
+// The benign state a timing launch starts from: a running recurrence whose previous launch
+// (slot 0) summed to ||r||^2 = 1, gamma^2 = 1, delta = 1/2 with no residual skipped.
+__global__ void k_tune_state(Scal *__restrict__ sc, double *__restrict__ part, int npart,
+                             double *__restrict__ kpart, int nkpart, Scal s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  if (i == 0) sc[0] = s;
+  for (int k = i; k < npart; k += stride) part[k] = k == 0 || k == 2 ? 1.0 : k == 3 ? 0.5 : 0.0;
+  if (kpart)
+    for (int k = i; k < nkpart; k += stride) kpart[k] = 0.0;
 }
 
 }  // namespace
 
-int spec_cols(const Plan *p) { return p->hp >= 256 ? 16 : 32; }
+int spec_cols(const Plan *p) { return p->spec_c; }
 
-int spec_blocks(const Plan *p) {
-  const int C = spec_cols(p);
-  return (p->m + C - 1) / C;
-}
+int spec_cols_default(int hp) { return hp >= 256 ? 16 : 32; }
 
-SpecP spec_desc(const Plan *p, double *x, const double *bh) {
+bool spec_cols_ok(int hp, int cols) { return cols == 16 || (cols == 32 && hp <= 128); }
+
+SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   SpecP P{};
   P.sqsigmin = p->sqsigmin;
   P.n = p->n; P.m = p->m; P.ld = p->ld; P.h1 = p->h1; P.h2 = p->h2; P.scheme = p->scheme; P.theta = p->theta;
-  P.tiles = spec_blocks(p);
+  const int C = cols ? cols : p->spec_c;
+  P.tiles = (p->m + C - 1) / C;
   P.tile0 = 0;
   const bool f32 = p->pprec == SMR_FP32;
   P.So = f32 ? (const void *)p->Sof : (const void *)p->So;
@@ -635,15 +663,70 @@ hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh) {
   const Plan *p = c.p;
   const SpecP P = spec_desc(p, x, bh);
   const int jph = j % 6, pmode = prev_mode(mode, j);
-  return p->pprec == SMR_FP32 ? run_spec_hp<1>(c.st, P, mode, P.tiles, p->hp, jph, pmode)
-                              : run_spec_hp<0>(c.st, P, mode, P.tiles, p->hp, jph, pmode);
+  return run_one(c.st, P, p->pprec, p->spec_c, mode, P.tiles, p->hp, jph, pmode);
 }
 
-hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
-                             int j) {
+hipError_t spec_tune(Plan *p, hipStream_t st) {
+  if (!spec_cols_ok(p->hp, 32)) {
+    p->spec_c = 16;
+    return hipSuccess;
+  }
+  hipError_t e = hipSuccess;
+  const size_t vbytes = sizeof(double) * p->vlen;
+  double *vecs[] = {p->V[0], p->V[1], p->Z[0], p->Z[1], p->W[0], p->W[1], p->Q, p->T1, p->T2, p->QX};
+  for (double *v : vecs)
+    if (v && e == hipSuccess) e = hipMemsetAsync(v, 0, vbytes, st);
+  if (p->pprec == SMR_FP32)
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMemsetAsync(p->ZF[i], 0, sizeof(float) * p->vlen, st);
+  if (e != hipSuccess) return e;
+  Scal s{};
+  s.status = RUNNING; s.iter = 5; s.maxit = 1 << 30;
+  s.gamma = s.gamma1 = s.gamma_new = s.zs = 1.0; s.delta = 0.5;
+  s.c = s.c_old = 1.0; s.eta = 1.0; s.bnorm = 1.0; s.rtol = 0.0;   // never converges
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  const int cand[2] = {32, 16};
+  float best[2] = {1e30f, 1e30f};
+  constexpr int kReps = 6;
+  // launch 7 of a solve: reads scalar slot 0 and partial slot 0, writes slot 1
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      p->spec_c = cand[k];
+      const SpecP P = spec_desc(p, p->T1, p->T2);
+      const int npart = 4 * P.tiles, nk = P.kpart ? 4 * P.nks : 0;
+      auto one = [&]() {
+        hipLaunchKernelGGL(k_tune_state, dim3((npart + 255) / 256), dim3(256), 0, st, p->sc, p->part, npart,
+                           P.kpart ? p->part + kKsPartOffset : nullptr, nk, s);
+        hipError_t r = hipGetLastError();
+        return r == hipSuccess ? run_one(st, P, p->pprec, cand[k], MODE_STEADY, P.tiles, p->hp, 1, MODE_STEADY) : r;
+      };
+      e = one();
+      if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+      for (int r = 0; r < kReps && e == hipSuccess; ++r) e = one();
+      if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e == hipSuccess) best[k] = std::min(best[k], ms);
+    }
+  for (hipEvent_t v : ev)
+    if (v) hipEventDestroy(v);
+  // the wider tile stays unless the narrow one is clearly faster
+  p->spec_c = best[1] < 0.95f * best[0] ? 16 : 32;
+  return e;
+}
+
+hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
+                             int mode, int j) {
   const int jph = j % 6, pmode = prev_mode(mode, j);
-  return pprec == SMR_FP32 ? run_multi_hp<1>(st, table, ninst, mode, blocks, hp, jph, pmode)
-                           : run_multi_hp<0>(st, table, ninst, mode, blocks, hp, jph, pmode);
+  if (cols == 16)
+    return pprec == SMR_FP32 ? run_multi_hp<1, 16>(st, table, ninst, mode, blocks, hp, jph, pmode)
+                             : run_multi_hp<0, 16>(st, table, ninst, mode, blocks, hp, jph, pmode);
+  if (cols == 32)
+    return pprec == SMR_FP32 ? run_multi_hp<1, 32>(st, table, ninst, mode, blocks, hp, jph, pmode)
+                             : run_multi_hp<0, 32>(st, table, ninst, mode, blocks, hp, jph, pmode);
+  return hipErrorInvalidValue;
 }
 
 __global__ void k_gather_scal(const SpecP *__restrict__ table, int ninst, int slot, Scal *__restrict__ out) {

@@ -171,7 +171,12 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
   if (d->pprec == SMR_FP32 && (d->precond != SMR_P_H || (d->flags & SMR_FLAG_GENERAL_PATH)))
     return fail(SMR_EUNSUPPORTED, "float32 preconditioning is available for the sine-basis P_H solve only");
-  if ((d->flags & ~SMR_FLAG_GENERAL_PATH) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
+  const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32;
+  if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
+  if ((d->flags & SMR_FLAG_TILE16) && (d->flags & SMR_FLAG_TILE32))
+    return fail(SMR_EINVAL, "SMR_FLAG_TILE16 and SMR_FLAG_TILE32 exclude each other");
+  if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
+    return fail(SMR_EUNSUPPORTED, "32-column tiles need ceil(n/2) <= 128 (got n = %d)", d->n);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
   if (d->ax_host && d->dim == 2 && !d->ay_host) return fail(SMR_EINVAL, "dim 2 face values need ay");
@@ -271,6 +276,18 @@ void mean_faces(const Plan &p, const std::vector<double> &ax, const std::vector<
   cy = N > 1 ? (double)(sy / ((long double)N * (N - 1))) : 0.0;
 }
 
+// compute units of the current device (256 on MI355X)
+int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+bool use_spectral(const Plan &p) {
+  return p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH) && (p.const_coef || p.QX != nullptr);
+}
+
 }  // namespace
 }  // namespace smr
 
@@ -326,6 +343,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.h1 = (d->n + 1) / 2;
   p.h2 = d->n / 2;
   p.hp = hp_of(p.h1);
+  p.spec_c = (d->flags & SMR_FLAG_TILE16) ? 16 : (d->flags & SMR_FLAG_TILE32) ? 32 : spec_cols_default(p.hp);
   p.ws_bytes = ws_bytes;
 
   const int N = p.N, n = p.n, m = p.m, dim = p.dim;
@@ -520,6 +538,13 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     delete pl;
     return fail(SMR_EDEVICE, "setup upload failed: %s", hipGetErrorString(e));
   }
+  if (use_spectral(p) && !(p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32))) {
+    e = spec_tune(&p, s);
+    if (e != hipSuccess) {
+      delete pl;
+      return fail(SMR_EDEVICE, "tile-width timing failed: %s", hipGetErrorString(e));
+    }
+  }
   *out = pl;
   return SMR_OK;
 }
@@ -540,10 +565,6 @@ smr_status smr_destroy(smr_plan *plan) {
 
 namespace smr {
 namespace {
-
-bool use_spectral(const Plan &p) {
-  return p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH) && (p.const_coef || p.QX != nullptr);
-}
 
 smr_status check_plan(const smr_plan *pl) {
   if (!pl) return fail(SMR_EINVAL, "plan is NULL");
@@ -897,6 +918,14 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, doub
 
 extern "C" {
 
+smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols) {
+  if (check_plan(plan) != SMR_OK) return SMR_EINVAL;
+  if (!cols) return fail(SMR_EINVAL, "cols is NULL");
+  *cols = use_spectral(plan->p) ? spec_cols(&plan->p) : 0;
+  return SMR_OK;
+}
+
+
 smr_status smr_build_rhs(const smr_plan *pl, const double *f, const double *u0, double *b, void *stream) {
   smr_status st = check_plan(pl);
   if (st != SMR_OK) return st;
@@ -960,19 +989,44 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
   // sine-basis instances, grouped by (time-size class, transform precision)
   std::vector<int> spec_ids, general_ids;
   for (int i = 0; i < count; ++i) (use_spectral(plans[i]->p) ? spec_ids : general_ids).push_back(i);
+  // Column-tile width per instance: a width forced on the plan stays; otherwise every
+  // instance of a (time-size class, precision) group takes 32 once the group's 32-column
+  // workgroups cover the compute units (narrow tiles only pay off on an underfilled chip,
+  // which is what the per-plan timing at setup measures).
+  std::vector<int> cols(count, 0);
+  {
+    std::vector<std::pair<long, long>> wide;   // (hp * 2 + pprec, 32-column workgroups)
+    auto forced = [](const Plan &p) { return (p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32)) != 0; };
+    auto group = [&](const Plan &p) -> long & {
+      const long key = (long)p.hp * 2 + p.pprec;
+      for (auto &w : wide)
+        if (w.first == key) return w.second;
+      wide.push_back({key, 0});
+      return wide.back().second;
+    };
+    const long cus = cu_count();
+    for (int i : spec_ids)
+      if (!forced(plans[i]->p)) group(plans[i]->p) += (plans[i]->p.m + 31) / 32;
+    for (int i : spec_ids) {
+      const Plan &p = plans[i]->p;
+      cols[i] = forced(p) ? p.spec_c : !spec_cols_ok(p.hp, 32) ? 16 : group(p) >= cus ? 32 : 16;
+    }
+  }
   std::stable_sort(spec_ids.begin(), spec_ids.end(), [&](int a, int c) {
     const Plan &pa = plans[a]->p, &pc = plans[c]->p;
-    return pa.hp != pc.hp ? pa.hp < pc.hp : pa.pprec < pc.pprec;
+    if (pa.hp != pc.hp) return pa.hp < pc.hp;
+    return cols[a] != cols[c] ? cols[a] < cols[c] : pa.pprec < pc.pprec;
   });
-  struct Class { int first, count, blocks, hp, pprec; };
+  struct Class { int first, count, blocks, hp, cols, pprec; };
   std::vector<Class> classes;
   std::vector<SpecP> table(spec_ids.size());
   for (size_t k = 0; k < spec_ids.size(); ++k) {
     const Plan &p = plans[spec_ids[k]]->p;
-    if (classes.empty() || classes.back().hp != p.hp || classes.back().pprec != p.pprec)
-      classes.push_back(Class{(int)k, 0, 0, p.hp, p.pprec});
+    const int c = cols[spec_ids[k]];
+    if (classes.empty() || classes.back().hp != p.hp || classes.back().cols != c || classes.back().pprec != p.pprec)
+      classes.push_back(Class{(int)k, 0, 0, p.hp, c, p.pprec});
     Class &cl = classes.back();
-    table[k] = spec_desc(&p, p.T2, p.T1);
+    table[k] = spec_desc(&p, p.T2, p.T1, c);
     table[k].tile0 = cl.blocks;
     cl.blocks += table[k].tiles;
     cl.count += 1;
@@ -1026,7 +1080,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     for (const KClass &cl : kclasses)
       LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
     for (const Class &cl : classes)
-      LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, 0, 0));
+      LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, 0, 0));
     // one iteration j: the per-level matvec of every N class, then the fused launch of every
     // time-size class
     auto iteration = [&](hipStream_t st, int j) -> hipError_t {
@@ -1035,7 +1089,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
         if (e == hipSuccess) e = launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j);
       for (const Class &cl : classes)
         if (e == hipSuccess)
-          e = launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec, j == 1 ? 1 : 2, j);
+          e = launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, j == 1 ? 1 : 2, j);
       return e;
     };
     // steady iterations j >= 6 replay a captured graph of six (cached by workspace and class
@@ -1044,7 +1098,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     if (!g_prof.on) {
       std::vector<long> key{(long)(uintptr_t)d_ws};
       for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
-      for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.pprec});
+      for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec});
       g6 = batch_graph(key, [&](hipStream_t cs) {
         hipError_t e = hipSuccess;
         for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration(cs, j);
@@ -1065,7 +1119,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
           for (const KClass &cl : kclasses)
             LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
           for (const Class &cl : classes)
-            LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.pprec,
+            LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec,
                                                 j == 1 ? 1 : 2, j));
         }
         issued += todo;

@@ -49,6 +49,7 @@ struct Plan {
   double sqsigmin;            // sqrt of the smallest eigenvalue of P (P_H / Phat)
   int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
   int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
+  int spec_c;                 // column-tile width of the fused sine-basis kernel (16 or 32)
   // tables (device)
   double *ax, *ay;            // face values (filled with 1 for a = 1)
   double *tmu;                // m: tau * eigenvalue of K (a const) or Kbar, sine-basis order
@@ -165,11 +166,19 @@ hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int 
                                int j);
 
 hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh);
-SpecP spec_desc(const Plan *p, double *x, const double *bh);
-hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int pprec, int mode,
-                             int j);
+// cols: column-tile width of the launch (0: the plan's own)
+SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols = 0);
+hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
+                             int mode, int j);
 hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int slot, Scal *out);
-int spec_blocks(const Plan *p);
+// Column-tile width (spatial modes per workgroup) of the fused kernel: 16 or 32, the latter
+// for hp <= 128 only (two 32-column LDS blocks of 256 rows do not fit).
+int spec_cols(const Plan *p);
+int spec_cols_default(int hp);
+bool spec_cols_ok(int hp, int cols);
+// Times one steady launch per width on the plan's (still empty) work vectors and stores the
+// faster width in p->spec_c; synchronises st.
+hipError_t spec_tune(Plan *p, hipStream_t st);
 hipError_t launch_zero_int(Ctx c, int *x, int count);
 
 // Chebyshev per-mode solve pieces (P_theta).

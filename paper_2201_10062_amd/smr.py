@@ -27,7 +27,7 @@ PPRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
 EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
     "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_solve_adjoint_batched", "smr_rhs_adjoint", "smr_grad_a",
-    "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error",
+    "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error", "smr_tile_cols",
 )
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5, "kslice": 6}
 
@@ -73,6 +73,7 @@ def load() -> ctypes.CDLL:
     lib.smr_workspace_size.argtypes = [ctypes.POINTER(SmrDesc), ctypes.POINTER(ctypes.c_size_t)]
     lib.smr_setup.argtypes = [ctypes.POINTER(SmrDesc), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     lib.smr_destroy.argtypes = [P]
+    lib.smr_tile_cols.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.smr_build_rhs.argtypes = [P, P, P, P, P]
     lib.smr_apply_A.argtypes = [P, P, P, P]
     lib.smr_apply_P_inv.argtypes = [P, P, P, P]
@@ -104,11 +105,16 @@ def _check(st: int):
 
 
 FLAG_GENERAL_PATH = 1
+FLAG_TILE16 = 2
+FLAG_TILE32 = 4
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
-              ax=None, ay=None, a_nodal=None, general_path=False):
-    """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays."""
+              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None):
+    """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
+    tile_cols: None (timed at setup), 16 or 32."""
+    if tile_cols not in (None, 16, 32):
+        raise ValueError(f"tile_cols must be None, 16 or 32 (got {tile_cols})")
     keep = []
 
     def host(a):
@@ -119,7 +125,8 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
         return arr.ctypes.data
 
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
-                cheb_k=cheb_k, flags=FLAG_GENERAL_PATH if general_path else 0, T=T, theta=theta,
+                cheb_k=cheb_k, flags=(FLAG_GENERAL_PATH if general_path else 0)
+                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32}[tile_cols], T=T, theta=theta,
                 ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal))
     return d, keep
 
@@ -159,7 +166,7 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda", general_path: bool = False):
+                 device="cuda", general_path: bool = False, tile_cols=None):
         import torch
         self.lib = load()
         self.dim, self.N, self.n = dim, N, n
@@ -167,7 +174,8 @@ class Plan:
         self.scheme, self.theta, self.T = scheme, float(theta), float(T)
         self.precond, self.pprec = precond, pprec
         self.device = torch.device(device)
-        d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path)
+        d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path,
+                            tile_cols)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -180,6 +188,13 @@ class Plan:
                                   _stream(), ctypes.byref(h)))
         self.handle = h
         del keep
+
+    @property
+    def tile_cols(self) -> int:
+        """Column-tile width of the sine-basis solve (16 or 32), 0 on the physical-basis path."""
+        c = ctypes.c_int32(0)
+        _check(self.lib.smr_tile_cols(self.handle, ctypes.byref(c)))
+        return c.value
 
     def __del__(self):
         h = getattr(self, "handle", None)

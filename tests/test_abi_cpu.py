@@ -42,11 +42,29 @@ def test_library_exports_every_declared_symbol():
     (dict(dim=2, N=7, n=4, T=-1.0), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=4, precond="PTHETA_CHEB", cheb_k=0), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=4, precond="PTHETA_CHEB", scheme="bdf2"), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=257, tile_cols=32), smr.SMR_EUNSUPPORTED),   # ceil(n/2) > 128
 ])
 def test_invalid_descriptors_rejected_on_host(kw, status):
     with pytest.raises(smr.SmrError) as ei:
         smr.workspace_size(**kw)
     assert ei.value.status == status
+
+
+def test_tile_width_flags_checked_on_host():
+    assert smr.workspace_size(dim=2, N=7, n=256, tile_cols=32) == smr.workspace_size(dim=2, N=7, n=256)
+    assert smr.workspace_size(dim=2, N=7, n=512, tile_cols=16) > 0
+    lib = pkg.load()
+    d, keep = smr.make_desc(2, 7, 4)
+    d.flags = smr.FLAG_TILE16 | smr.FLAG_TILE32
+    out = ctypes.c_size_t(0)
+    assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
+    assert b"exclude" in lib.smr_last_error()
+    d.flags = 8
+    assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
+    with pytest.raises(ValueError):
+        smr.make_desc(2, 7, 4, tile_cols=24)
+    cols = ctypes.c_int32(-1)
+    assert lib.smr_tile_cols(None, ctypes.byref(cols)) == smr.SMR_EINVAL
 
 
 def test_setup_rejects_bad_workspace_before_device_work():
