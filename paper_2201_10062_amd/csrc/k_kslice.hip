@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kKT) void k_kslice_multi(const KsP *__restrict__ ta
     if (table[mid].blk0 <= b) lo = mid;
     else hi = mid - 1;
   }
-  const KsP K = table[lo];
+  const KsP &K = table[lo];   // read in place (a private copy would go to scratch)
   ks_body<R, PR, MODE>(K, jfull, b - K.blk0);
 }
 

@@ -534,7 +534,7 @@ void k_spec_multi(const SpecP *__restrict__ table, int ninst, int jph, int pmode
     if (table[mid].tile0 <= b) lo = mid;
     else hi = mid - 1;
   }
-  const SpecP P = table[lo];
+  const SpecP &P = table[lo];   // read in place (a private copy would go to scratch)
   spec_body<HP, C, MODE, PR>(P, jph, pmode, b - P.tile0);
 }
 
