@@ -155,13 +155,15 @@ smr_status smr_apply_A(const smr_plan *plan, const double *d_x, double *d_y, voi
  * (d_z == d_v) is allowed. */
 smr_status smr_apply_P_inv(const smr_plan *plan, const double *d_v, double *d_z, void *stream);
 
-/* Preconditioned MINRES on Y T x = Y b (b = the unpermuted f_H, n*m device).  d_x holds
- * the initial guess on entry (zero it for the paper's x0 = 0) and the iterate on exit.
- * Stops at the first iteration whose true relative residual ||b - T x||/||b|| <= rtol
- * (rtol > 0), or after maxit (>= 0) iterations.  info_host (host) receives the count
- * and residuals.  Returns the solve status (SMR_OK on convergence).  Synchronises. */
-smr_status smr_minres_solve(const smr_plan *plan, const double *d_b, double *d_x, double rtol,
-                            int32_t maxit, smr_info *info_host, void *stream);
+/* Preconditioned MINRES on Y T x = Y b (b = the unpermuted f_H, n*m device).  d_x0: the
+ * initial guess (n*m device, read only, may equal d_x) or NULL for x0 = 0, the choice of
+ * the paper's experiments (Sec. 5), which also skips transforming a guess.  d_x (n*m, not
+ * d_b) receives the iterate.  Stops at the first iteration whose true relative residual
+ * ||b - T x||/||b|| <= rtol (rtol > 0), or after maxit (>= 0) iterations.  info_host (host)
+ * receives the count and residuals.  Returns the solve status (SMR_OK on convergence).
+ * Synchronises. */
+smr_status smr_minres_solve(const smr_plan *plan, const double *d_b, const double *d_x0, double *d_x,
+                            double rtol, int32_t maxit, smr_info *info_host, void *stream);
 
 /* Device workspace (bytes, 256-byte aligned) that smr_minres_solve_batched needs for this
  * set of plans: the per-instance descriptor tables and status array of the batched launches. */
@@ -174,16 +176,17 @@ smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans,
  * covering all column tiles, each instance with its own device scalars; converged instances
  * are masked on the device.  The remaining instances are solved one after another on the
  * general path.  plans, d_b, d_x and infos_host are host
- * arrays of length count; d_b[i] / d_x[i] follow the conventions of smr_minres_solve.
+ * arrays of length count; d_x0 is a host array of length count or NULL (every x0 = 0);
+ * d_b[i] / d_x0[i] / d_x[i] follow the conventions of smr_minres_solve.
  * d_ws: caller-owned device workspace of smr_batch_workspace_size bytes.  Returns SMR_OK when
  * every instance converged, else the first failing status (each info holds its own). */
 smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
-                                    const double *const *d_b, double *const *d_x, double rtol,
-                                    int32_t maxit, void *d_ws, size_t ws_bytes,
-                                    smr_info *infos_host, void *stream);
+                                    const double *const *d_b, const double *const *d_x0,
+                                    double *const *d_x, double rtol, int32_t maxit, void *d_ws,
+                                    size_t ws_bytes, smr_info *infos_host, void *stream);
 
 /* Adjoint solve T^T lambda = g: since T^T = Y T Y, MINRES on (Y T) mu = g with the same
- * preconditioner, then lambda = Y mu.  d_g, d_lambda: n*m.  d_lambda is zeroed first. */
+ * preconditioner from mu0 = 0, then lambda = Y mu.  d_g, d_lambda: n*m, distinct. */
 smr_status smr_solve_adjoint(const smr_plan *plan, const double *d_g, double *d_lambda,
                              double rtol, int32_t maxit, smr_info *info_host, void *stream);
 

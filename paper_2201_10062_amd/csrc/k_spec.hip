@@ -9,6 +9,7 @@
 // transformed vectors and only b, x0 and the result cross the spatial transform.  One
 // kernel does a whole iteration for a tile of C spatial modes (all n time levels):
 //   A. q = (Y T)^ zt_j, v_{j+1} = q - va v_j - vb v_{j-1} (stored), butterflied into LDS;
+//      (v_0, w_0 and w_{-1} are zero by definition and never read, so nothing is cleared);
 //      lagged search direction w_{j-1} and x_{j-1} (its coefficients need gamma_j, which
 //      the previous launch produced);
 //   B. true residual of x_{j-1}: ||Y b - (Y T)^ x||^2 partial;
@@ -55,7 +56,8 @@ template <> struct Prec<1> {
 };
 constexpr int kWaves = kThreads / 64;
 
-enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2 };
+// MODE_EARLY: a steady iteration of launch 2 or 3, where w_{j-2} or w_{j-3} does not exist yet
+enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2, MODE_EARLY = 3 };
 
 // per-column stencil coefficients of (T y)_t = l0 y_t + l1 y_{t-1} + l2 y_{t-2}
 struct Coef {
@@ -310,6 +312,13 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     __syncthreads();
     if (S.status != RUNNING) return;
   }
+  if (MODE == MODE_INIT && tile == 0 && tid == 0) {   // the state the first launch starts from
+    Scal s0{};
+    s0.rtol = P.rtol;
+    s0.maxit = P.maxit;
+    s0.status = RUNNING;
+    P.sc[0] = s0;
+  }
   const double va = uni(S.va), vb = uni(S.vb), zs = uni(S.zs);
   const double a1 = uni(S.a1), a2 = uni(S.a2), a3 = uni(S.a3), ceta = uni(S.ceta), zsl = uni(S.gamma_new);
   const T *__restrict__ zcur = reinterpret_cast<const T *>(P.Z[(j + 2) % 3]);
@@ -325,15 +334,16 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
   // the true residual of x_{j-1} is needed only once sqrt(min sigma) |eta| (a lower bound of
   // ||r||_2, |eta| being ||r||_{P^-1}) no longer excludes convergence, or at the iteration limit
-  const bool bres = MODE == MODE_STEADY && !P.qext &&
+  constexpr bool STEADY = MODE == MODE_STEADY || MODE == MODE_EARLY;
+  const bool bres = STEADY && !P.qext &&
                     (P.sqsigmin * fabs(S.eta) <= 2.0 * S.rtol * S.bnorm || S.iter >= S.maxit);
-  if (MODE == MODE_STEADY && !P.qext && !bres && tid == 0) acc_b = 1.0;
+  if (STEADY && !P.qext && !bres && tid == 0) acc_b = 1.0;
 
   // ---- B (steady launches, streaming waves 4..7): lagged w_{j-1}, x_{j-1} and the true
   //      residual of x_{j-1}, streamed over time levels with x carried for the stencil.  Each
   //      group's levels are split between the four matrix-core passes.  The carries read the
   //      previous group's last levels, so they are taken here, before any wave writes w or x.
-  const bool bwave = MODE == MODE_STEADY && wave >= 4;
+  const bool bwave = STEADY && wave >= 4;
   const int bc = (tid - kThreads / 2) % C, bg = (tid - kThreads / 2) / C;
   const bool bok = col0 + bc < m;
   const int bcc = bok ? col0 + bc : m - 1;
@@ -342,7 +352,13 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   int bq[5];                                   // B's levels split in four, one per GEMM pass
 #pragma unroll
   for (int q = 0; q <= 4; ++q) bq[q] = bt0 + ((bt1 - bt0) * q + 3) / 4;
-  auto wnew = [&](size_t i) { return (zsl * (double)zprev[i] - a3 * wb[i] - a2 * wa[i]) / a1; };
+  // w_{j-2} exists from launch 3 on, w_{j-3} from launch 4 on (launch j has iter = j - 1);
+  // in launches 2 and 3 the missing ones are read from v_j (finite) with a zero coefficient
+  const bool w2 = MODE != MODE_EARLY || S.iter >= 2, w3 = MODE != MODE_EARLY || S.iter >= 3;
+  const double *__restrict__ war = w2 ? wa : vcur;
+  const double *__restrict__ wbr = w3 ? (const double *)wb : vcur;
+  const double a2e = w2 ? a2 : 0.0, a3e = w3 ? a3 : 0.0;
+  auto wnew = [&](size_t i) { return (zsl * (double)zprev[i] - a3e * wbr[i] - a2e * war[i]) / a1; };
   double bx1 = 0.0, bx2 = 0.0;
   if (bwave) {
     if (bt0 >= 1) { const size_t i = vat(ld, bt0 - 1, bcc); bx1 = xv[i] + ceta * wnew(i); }
@@ -380,7 +396,8 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const int R = (n + G - 1) / G;
     const int t0 = g * R, t1 = min(n, t0 + R);
     const bool ext = P.qext != nullptr;               // (T z)^ given by the per-level matvec
-    auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? xv[i] : (double)zcur[i]; };
+    const bool xz = MODE == MODE_INIT && P.x0zero;    // x0 = 0: no x read, (T x0)^ = 0
+    auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? (xz ? 0.0 : xv[i]) : (double)zcur[i]; };
     double y1 = (!ext && t0 >= 1) ? src(vat(ld, t0 - 1, cc)) : 0.0;
     double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
 #pragma unroll 4
@@ -388,12 +405,15 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
       const int o = n - 1 - t;
       const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
       const double y0 = ext ? 0.0 : src(it);
-      const double ty = ext ? P.qext[it] : k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
+      const double ty = ext ? (xz ? 0.0 : P.qext[it]) : k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
       double v;
       if (MODE == MODE_INIT) {
         const double bt = bh[it];
         v = bt - ty;                                 // (Y b)_o - ((Y T)^ x0)_o
         if (ok) { acc_r += v * v; acc_b += bt * bt; }
+        if (xz && ok) xv[it] = 0.0;
+      } else if (MODE == MODE_FIRST) {
+        v = zs * ty - va * vcur[io];                 // v_0 = 0
       } else {
         v = zs * ty - va * vcur[io] - vb * vold[io];
       }
@@ -425,12 +445,12 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   const T *So = reinterpret_cast<const T *>(P.So), *Se = reinterpret_cast<const T *>(P.Se);
   const T *SoT = reinterpret_cast<const T *>(P.SoT), *SeT = reinterpret_cast<const T *>(P.SeT);
   if (wave < 4) gemm_tiles<HP, C, PR>(So, U, wave, lane, acc);
-  else if (MODE == MODE_STEADY) bstream(bq[0], bq[1]);
+  else if (STEADY) bstream(bq[0], bq[1]);
   __syncthreads();
   if (wave < 4) {
     store_acc<HP, C, PR>(acc, U, wave, lane);     // S_o u -> U
     gemm_tiles<HP, C, PR>(Se, D, wave, lane, acc);
-  } else if (MODE == MODE_STEADY) {
+  } else if (STEADY) {
     bstream(bq[1], bq[2]);
   }
   __syncthreads();
@@ -458,12 +478,12 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
   __syncthreads();
   if (wave < 4) gemm_tiles<HP, C, PR>(SoT, U, wave, lane, acc);
-  else if (MODE == MODE_STEADY) bstream(bq[2], bq[3]);
+  else if (STEADY) bstream(bq[2], bq[3]);
   __syncthreads();
   if (wave < 4) {
     store_acc<HP, C, PR>(acc, U, wave, lane);     // u' -> U
     gemm_tiles<HP, C, PR>(SeT, D, wave, lane, acc);
-  } else if (MODE == MODE_STEADY) {
+  } else if (STEADY) {
     bstream(bq[3], bq[4]);
   }
   __syncthreads();
@@ -545,10 +565,12 @@ hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jp
     (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 3, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
   else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
-  else hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
+  else if (mode == 2) hipLaunchKernelGGL((k_spec<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
+  else hipLaunchKernelGGL((k_spec<HP, C, 3, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
   return hipGetLastError();
 }
 
@@ -559,13 +581,16 @@ hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mod
     (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 3, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0)
     hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
   else if (mode == 1)
     hipLaunchKernelGGL((k_spec_multi<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL((k_spec_multi<HP, C, 2, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
+  else
+    hipLaunchKernelGGL((k_spec_multi<HP, C, 3, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);
   return hipGetLastError();
 }
 
@@ -648,6 +673,7 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   for (int i = 0; i < 3; ++i) P.Z[i] = f32 ? (void *)p->ZF[i] : (void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
   P.V[0] = p->V[0]; P.V[1] = p->V[1]; P.W[0] = p->W[0]; P.W[1] = p->W[1];
   P.x = x; P.bh = bh; P.part = p->part; P.sc = p->sc;
+  P.x0zero = 0; P.rtol = 0.0; P.maxit = 0;
   if (!p->const_coef) {
     P.qext = p->QX;
     P.kpart = p->part + kKsPartOffset;
@@ -656,14 +682,21 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   return P;
 }
 
-// mode of launch j - 1, whose partial sums launch j reduces
+// mode of launch j - 1, whose partial sums launch j reduces (an early steady launch leaves
+// them in the steady layout)
 static int prev_mode(int mode, int j) { return mode == MODE_FIRST ? MODE_INIT : (j == 2 ? MODE_FIRST : MODE_STEADY); }
 
-hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh) {
+// launches 2 and 3 run the early variant of the steady iteration
+static int launch_mode(int mode, int j) { return mode == MODE_STEADY && j < 4 ? MODE_EARLY : mode; }
+
+hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool x0zero, double rtol, int maxit) {
   const Plan *p = c.p;
-  const SpecP P = spec_desc(p, x, bh);
+  SpecP P = spec_desc(p, x, bh);
+  P.x0zero = x0zero ? 1 : 0;
+  P.rtol = rtol;
+  P.maxit = maxit;
   const int jph = j % 6, pmode = prev_mode(mode, j);
-  return run_one(c.st, P, p->pprec, p->spec_c, mode, P.tiles, p->hp, jph, pmode);
+  return run_one(c.st, P, p->pprec, p->spec_c, launch_mode(mode, j), P.tiles, p->hp, jph, pmode);
 }
 
 hipError_t spec_tune(Plan *p, hipStream_t st) {
@@ -720,6 +753,7 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
                              int mode, int j) {
   const int jph = j % 6, pmode = prev_mode(mode, j);
+  mode = launch_mode(mode, j);
   if (cols == 16)
     return pprec == SMR_FP32 ? run_multi_hp<1, 16>(st, table, ninst, mode, blocks, hp, jph, pmode)
                              : run_multi_hp<0, 16>(st, table, ninst, mode, blocks, hp, jph, pmode);

@@ -757,26 +757,21 @@ BatchSnap &batch_snapshots(int count) {
 
 // Constant coefficients: the whole MINRES runs in the spatial sine basis with one fused
 // kernel per iteration; b and x0 are transformed on entry, the iterate on exit.
-smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
-                           smr_info *info) {
+// x0 == NULL: zero initial guess (the initialising launch writes x = 0 in the sine basis)
+smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const double *x0, double *x, double rtol,
+                           int maxit, smr_info *info) {
   Ctx c{&p, s};
   double *Bh = p.T1, *Xh = p.T2;
   smr_status st = to_sine_basis(p, s, b, Bh);
   if (st != SMR_OK) return st;
-  st = to_sine_basis(p, s, x, Xh);
-  if (st != SMR_OK) return st;
+  if (x0) {
+    st = to_sine_basis(p, s, x0, Xh);
+    if (st != SMR_OK) return st;
+  }
   Scal h{};
-  h.rtol = rtol;
-  h.maxit = maxit;
-  h.status = RUNNING;
-  const Scal h2[2] = {h, h};
-  HIP_TRY(hipMemcpyAsync(p.sc, h2, sizeof(h2), hipMemcpyHostToDevice, s));
-  LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
-  LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
   const bool ext = !p.const_coef;   // variable a: (T z)^ from the per-level matvec
-  if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 0, 0, Xh, Bh));
-  LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh));
+  if (ext && x0) LAUNCH(PROF_KSLICE, launch_kslice(c, 0, 0, Xh, Bh));
+  LAUNCH(PROF_SPEC, launch_spec(c, 0, 0, Xh, Bh, x0 == nullptr, rtol, maxit));
   const Profiler::Mark m0 = g_prof.mark();
   st = ensure_snapshots(p);
   if (st != SMR_OK) return st;
@@ -843,9 +838,11 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, double
 const double *scal_field(const Plan &p, size_t off) { return (const double *)((const char *)p.sc + off); }
 
 // MINRES on (Y T) x = Y b from the initial x; b unpermuted.
-smr_status minres(const Plan &p, hipStream_t s, const double *b, double *x, double rtol, int maxit,
+smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x0, double *x, double rtol, int maxit,
                   smr_info *info) {
   Ctx c{&p, s};
+  if (!x0) LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
+  else if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
   Scal h{};
   h.rtol = rtol;
   h.maxit = maxit;
@@ -952,14 +949,15 @@ smr_status smr_apply_P_inv(const smr_plan *pl, const double *v, double *z, void 
   return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr);
 }
 
-smr_status smr_minres_solve(const smr_plan *pl, const double *b, double *x, double rtol, int32_t maxit,
-                            smr_info *info, void *stream) {
+smr_status smr_minres_solve(const smr_plan *pl, const double *b, const double *x0, double *x, double rtol,
+                            int32_t maxit, smr_info *info, void *stream) {
   smr_status st = check_plan(pl);
   if (st != SMR_OK) return st;
   if (!b || !x) return fail(SMR_EINVAL, "b and x must be non-NULL");
+  if (b == x) return fail(SMR_EINVAL, "b and x must be distinct");
   if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
-  if (use_spectral(pl->p)) return minres_spectral(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
-  return minres(pl->p, (hipStream_t)stream, b, x, rtol, maxit, info);
+  if (use_spectral(pl->p)) return minres_spectral(pl->p, (hipStream_t)stream, b, x0, x, rtol, maxit, info);
+  return minres(pl->p, (hipStream_t)stream, b, x0, x, rtol, maxit, info);
 }
 
 smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans, size_t *bytes) {
@@ -970,8 +968,8 @@ smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans,
 }
 
 smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans, const double *const *b,
-                                    double *const *x, double rtol, int32_t maxit, void *d_ws, size_t ws_bytes,
-                                    smr_info *infos, void *stream) {
+                                    const double *const *x0, double *const *x, double rtol, int32_t maxit,
+                                    void *d_ws, size_t ws_bytes, smr_info *infos, void *stream) {
   if (count < 0 || (count > 0 && (!plans || !b || !x || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
   if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
   size_t need = 0;
@@ -980,6 +978,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     return fail(SMR_EWORKSPACE, "batch workspace missing, misaligned or smaller than %zu bytes", need);
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !b[i] || !x[i]) return fail(SMR_EINVAL, "instance %d: NULL plan or vector", i);
+    if (b[i] == x[i]) return fail(SMR_EINVAL, "instance %d: b and x must be distinct", i);
   }
   hipStream_t s = (hipStream_t)stream;
   SpecP *d_table = (SpecP *)d_ws;
@@ -1054,31 +1053,31 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     cl.count += 1;
   }
   smr_status first_bad = SMR_OK;
+  bool any_guess_ext = false;
   if (ns > 0) {
     for (int k = 0; k < ns; ++k) {
       const Plan &p = plans[spec_ids[k]]->p;
-      Ctx c{&p, s};
       smr_status st = to_sine_basis(p, s, b[spec_ids[k]], p.T1);
       if (st != SMR_OK) return st;
-      st = to_sine_basis(p, s, x[spec_ids[k]], p.T2);
-      if (st != SMR_OK) return st;
-      Scal h{};
-      h.rtol = rtol;
-      h.maxit = maxit;
-      h.status = RUNNING;
-      const Scal h2[2] = {h, h};
-      HIP_TRY(hipMemcpyAsync(p.sc, h2, sizeof(h2), hipMemcpyHostToDevice, s));
-      LAUNCH(PROF_VEC, launch_zero(c, p.V[0], p.vlen));
-      LAUNCH(PROF_VEC, launch_zero(c, p.W[0], p.vlen));
-      LAUNCH(PROF_VEC, launch_zero(c, p.W[1], p.vlen));
+      const double *g0 = x0 ? x0[spec_ids[k]] : nullptr;
+      if (g0) {
+        st = to_sine_basis(p, s, g0, p.T2);
+        if (st != SMR_OK) return st;
+        any_guess_ext |= !p.const_coef;
+      }
+      table[k].x0zero = g0 == nullptr;
+      table[k].rtol = rtol;
+      table[k].maxit = maxit;
     }
     HIP_TRY(hipMemcpyAsync(d_table, table.data(), sizeof(SpecP) * ns, hipMemcpyHostToDevice, s));
     if (!ktable.empty())
       HIP_TRY(hipMemcpyAsync(d_ks, ktable.data(), sizeof(KsP) * ktable.size(), hipMemcpyHostToDevice, s));
     Ctx c0{&plans[spec_ids[0]]->p, s};
     Ctx &c = c0;
-    for (const KClass &cl : kclasses)
-      LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
+    // (T x0)^ is needed only for a given guess (zero-guess instances ignore it)
+    if (any_guess_ext)
+      for (const KClass &cl : kclasses)
+        LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
     for (const Class &cl : classes)
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, 0, 0));
     // one iteration j: the per-level matvec of every N class, then the fused launch of every
@@ -1171,7 +1170,7 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     HIP_TRY(hipStreamSynchronize(s));
   }
   for (int i : general_ids) {
-    smr_status st = minres(plans[i]->p, s, b[i], x[i], rtol, maxit, &infos[i]);
+    smr_status st = minres(plans[i]->p, s, b[i], x0 ? x0[i] : nullptr, x[i], rtol, maxit, &infos[i]);
     if (st != SMR_OK && first_bad == SMR_OK) first_bad = st;
   }
   return first_bad;
@@ -1188,8 +1187,8 @@ smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, d
   Ctx c{&p, s};
   // (Y T) mu = g  <=>  (Y T) mu = Y (Y g): solve with b' = Y g, then lambda = Y mu
   LAUNCH(PROF_VEC, launch_scale_copy(c, g, p.G, 1.0, 1));
-  LAUNCH(PROF_VEC, launch_zero(c, lam, p.len));
-  st = use_spectral(p) ? minres_spectral(p, s, p.G, lam, rtol, maxit, info) : minres(p, s, p.G, lam, rtol, maxit, info);
+  st = use_spectral(p) ? minres_spectral(p, s, p.G, nullptr, lam, rtol, maxit, info)
+                       : minres(p, s, p.G, nullptr, lam, rtol, maxit, info);
   if (st != SMR_OK && st != SMR_ENOTCONV) return st;
   LAUNCH(PROF_VEC, launch_scale_copy(c, lam, p.G, 1.0, 1));
   HIP_TRY(hipMemcpyAsync(lam, p.G, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1208,10 +1207,10 @@ smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans
     const Plan &p = plans[i]->p;
     Ctx c{&p, s};
     LAUNCH(PROF_VEC, launch_scale_copy(c, g[i], p.G, 1.0, 1));   // (Y T) mu = g  <=>  solve with b' = Y g
-    LAUNCH(PROF_VEC, launch_zero(c, lam[i], p.len));
     bs[i] = p.G;
   }
-  smr_status st = smr_minres_solve_batched(count, plans, bs.data(), lam, rtol, maxit, d_ws, ws_bytes, infos, stream);
+  smr_status st =
+      smr_minres_solve_batched(count, plans, bs.data(), nullptr, lam, rtol, maxit, d_ws, ws_bytes, infos, stream);
   if (st != SMR_OK && st != SMR_ENOTCONV) return st;
   for (int i = 0; i < count; ++i) {                           // lambda = Y mu
     const Plan &p = plans[i]->p;

@@ -140,7 +140,10 @@ struct SpecP {
   // [residual^2, residual skipped, 0, delta] per time level (null / 0 for constant a)
   const double *qext;
   const double *kpart;
-  int nks, pad2;
+  int nks;
+  int x0zero;            // INIT: the solve starts from x0 = 0 (x is written, not read)
+  double rtol;           // INIT: the starting scalar state (sc[0]) it writes
+  int maxit, pad3;
 };
 
 // One instance of the per-level sine-basis matvec (also the element of its batched table).
@@ -165,7 +168,9 @@ hipError_t launch_kslice(Ctx c, int mode, int j, double *x, const double *bh);
 hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int blocks, int L, int pprec, int mode,
                                int j);
 
-hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh);
+// INIT (mode 0) also writes the starting scalar state (rtol, maxit) and, with x0zero, x = 0.
+hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool x0zero = false,
+                       double rtol = 0.0, int maxit = 0);
 // cols: column-tile width of the launch (0: the plan's own)
 SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols = 0);
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,

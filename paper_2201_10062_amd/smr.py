@@ -77,11 +77,11 @@ def load() -> ctypes.CDLL:
     lib.smr_build_rhs.argtypes = [P, P, P, P, P]
     lib.smr_apply_A.argtypes = [P, P, P, P]
     lib.smr_apply_P_inv.argtypes = [P, P, P, P]
-    lib.smr_minres_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
+    lib.smr_minres_solve.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
     lib.smr_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]
     lib.smr_minres_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
-                                             ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, P,
-                                             ctypes.c_size_t, ctypes.POINTER(SmrInfo), P]
+                                             ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_double,
+                                             ctypes.c_int32, P, ctypes.c_size_t, ctypes.POINTER(SmrInfo), P]
     lib.smr_solve_adjoint.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
     lib.smr_solve_adjoint_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
                                               ctypes.POINTER(P), ctypes.c_double, ctypes.c_int32, P,
@@ -234,11 +234,13 @@ class Plan:
         return z
 
     def solve(self, b, x0=None, rtol=1e-8, maxit=500, raise_on_fail=True):
-        """MINRES on Y T x = Y b; returns (x, info dict)."""
+        """MINRES on Y T x = Y b from x0 (None: x0 = 0); returns (x, info dict)."""
         self._vec(b)
-        x = self.empty().zero_() if x0 is None else self._vec(x0.clone())
+        if x0 is not None:
+            self._vec(x0)
+        x = self.empty()
         info = SmrInfo()
-        st = self.lib.smr_minres_solve(self.handle, _ptr(b), _ptr(x), float(rtol), int(maxit),
+        st = self.lib.smr_minres_solve(self.handle, _ptr(b), _ptr(x0), _ptr(x), float(rtol), int(maxit),
                                        ctypes.byref(info), _stream())
         if st != SMR_OK and raise_on_fail and st != SMR_ENOTCONV:
             _check(st)
@@ -293,17 +295,22 @@ class Batch:
         self.ws = raw[off:off + nbytes.value]
 
     def solve(self, bs, x0s=None, rtol=1e-8, maxit=500):
-        """Solve every (plan, b) pair; returns (xs, infos)."""
+        """Solve every (plan, b) pair from x0s (None: every x0 = 0); returns (xs, infos)."""
         n = len(self.plans)
-        xs = [p.empty().zero_() if x0s is None else x0.clone() for p, x0 in zip(self.plans, x0s or [None] * n)]
-        for p, b, x in zip(self.plans, bs, xs):
+        xs = [p.empty() for p in self.plans]
+        for p, b in zip(self.plans, bs):
             p._vec(b)
-            p._vec(x)
         P = ctypes.c_void_p
+        x0p = None
+        if x0s is not None:
+            for p, x0 in zip(self.plans, x0s):
+                if x0 is not None:
+                    p._vec(x0)
+            x0p = (P * n)(*[_ptr(x0) for x0 in x0s])
         bp = (P * n)(*[b.data_ptr() for b in bs])
         xp = (P * n)(*[x.data_ptr() for x in xs])
         infos = (SmrInfo * n)()
-        st = load().smr_minres_solve_batched(n, self._hp, bp, xp, float(rtol), int(maxit),
+        st = load().smr_minres_solve_batched(n, self._hp, bp, x0p, xp, float(rtol), int(maxit),
                                              ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), infos, _stream())
         if st not in (SMR_OK, SMR_ENOTCONV):
             _check(st)

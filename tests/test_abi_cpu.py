@@ -82,7 +82,7 @@ def test_setup_rejects_bad_workspace_before_device_work():
 def test_null_plan_rejected():
     lib = pkg.load()
     assert lib.smr_apply_A(None, None, None, None) == smr.SMR_EINVAL
-    assert lib.smr_minres_solve(None, None, None, 1e-8, 10, None, None) == smr.SMR_EINVAL
+    assert lib.smr_minres_solve(None, None, None, None, 1e-8, 10, None, None) == smr.SMR_EINVAL
 
 
 def test_workspace_size_grows_with_problem():

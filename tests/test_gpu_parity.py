@@ -185,6 +185,53 @@ def test_minres_warm_start_and_zero_rhs_and_maxit(general):
     assert info["iters"] == ref.iters and rel(_n(x), ref.x) < 1e-10
 
 
+@pytest.mark.parametrize("kind,general", [("const", False), ("var", False), ("const", True)],
+                         ids=["fused", "fused-var", "general"])
+def test_zero_guess_equals_explicit_zero_and_in_place_guess(kind, general):
+    """x0 = NULL (the initialising launch writes x = 0) gives bit for bit the iterate of an
+    explicit zero guess; a guess passed in place (d_x0 == d_x) equals one passed separately."""
+    import ctypes
+    from paper_2201_10062_amd import smr
+    g, o = _pair(2, 31, 24, "theta", 0.5, kind=kind, general=general)
+    rng = np.random.default_rng(13)
+    b = o.rhs(rng.standard_normal((25, g.m)), rng.standard_normal(g.m))
+    bt = _t(b)
+    x1, i1 = g.solve(bt, rtol=1e-9)
+    x2, i2 = g.solve(bt, x0=_t(np.zeros_like(b)), rtol=1e-9)
+    assert i1["iters"] == i2["iters"] and np.array_equal(_n(x1), _n(x2))
+    ref = o.solve(b, rtol=1e-9)
+    assert i1["iters"] == ref.iters and rel(_n(x1), ref.x) < 1e-10
+    u0 = 0.3 * ref.x
+    xs, is_ = g.solve(bt, x0=_t(u0), rtol=1e-9)
+    xin = _t(u0)
+    info = smr.SmrInfo()
+    st = g.lib.smr_minres_solve(g.handle, ctypes.c_void_p(bt.data_ptr()), ctypes.c_void_p(xin.data_ptr()),
+                                ctypes.c_void_p(xin.data_ptr()), 1e-9, 500, ctypes.byref(info), smr._stream())
+    assert st == smr.SMR_OK and info.iters == is_["iters"]
+    assert np.array_equal(_n(xin), _n(xs))
+    ref0 = o.solve(b, rtol=1e-9, x0=u0)
+    assert is_["iters"] == ref0.iters and rel(_n(xs), ref0.x) < 1e-10
+
+
+def test_batched_initial_guesses():
+    """A batch where some instances start from a guess and the others from x0 = 0 (constant
+    and variable coefficients, sine-basis and physical-basis instances)."""
+    from paper_2201_10062_amd import Batch, Plan
+    probs = _bdf2_batch_small(12)
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    refs0 = [System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    x0s, want = [], []
+    for i, (p, o) in enumerate(zip(probs, refs0)):
+        g0 = None if i % 2 == 0 else 0.5 * o.solve_direct(p.b.reshape(-1))
+        x0s.append(g0)
+        want.append(o.solve(p.b.reshape(-1), rtol=1e-8, maxit=500, **({} if g0 is None else {"x0": g0})))
+    xs, infos = Batch(plans).solve([_t(p.b) for p in probs], x0s=[None if g0 is None else _t(g0) for g0 in x0s],
+                                   rtol=1e-8)
+    for p, x, info, ref in zip(probs, xs, infos, want):
+        assert info["status"] == "ok" and info["iters"] == ref.iters, (p.name, info, ref.iters)
+        assert rel(_n(x), ref.x) < 1e-10, p.name
+
+
 def test_adjoint_and_gradients_parity():
     N, n, theta = 15, 12, 0.5
     from paper_2201_10062_amd import Plan
