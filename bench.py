@@ -304,13 +304,15 @@ def main() -> int:
     dof = p.n * p.m
     # Dominant kernel: the fused sine-basis MINRES iteration (one launch per iteration,
     # plus one initialising launch per solve).  Algorithmic HBM bytes per degree of freedom:
-    #   init 32 (read b^, x0; write v_1, z_1), first 40 (read z_1, v_1, v_0; write v_2, z_2),
-    #   steady 88 (read z_j, z_{j-1}, v_j, v_{j-1}, w_{j-2}, w_{j-3}, x; write v, z, w, x),
-    #   plus 8 (read b^) in the launches that evaluate the true residual.
+    #   init 32 (zero guess: read b^; write v_1, z_1, x = 0), first 32 (read z_1, v_1; write
+    #   v_2, z_2), steady 88 (read z_j, z_{j-1}, v_j, v_{j-1}, w_{j-2}, w_{j-3}, x; write v, z,
+    #   w, x), less the w's that do not exist yet in launches 2 (w_0, w_-1) and 3 (w_0),
+    #   plus 8 (read b^) in the launches that evaluate the true residual (the library reports
+    #   how many it evaluated, the initial one included).
     # Each launch also does the two folded time GEMMs: 2 n^2 m flops.
-    # a steady launch that evaluates the true residual also reads b^ (8 B/DoF more); the
-    # library reports how many residuals it evaluated (the initial one included)
-    bytes_total = sum((32 + 40 + 88 * i["iters"] + 8 * (i["res_evals"] - 1)) * dof for i in infos)
+    def steady_bytes(k):
+        return sum(88 - (16 if j == 2 else 8 if j == 3 else 0) for j in range(2, k + 2))
+    bytes_total = sum((32 + 32 + steady_bytes(i["iters"]) + 8 * (i["res_evals"] - 1)) * dof for i in infos)
     launches_expected = sum(k + 2 for k in iters)
     flops_per_launch = 2.0 * p.n * p.n * p.m
     avg_launch_s = (ms_spec / n_spec) * 1e-3 if n_spec else float("nan")
