@@ -185,7 +185,9 @@ def paper_tables_leg(dev, reps: int = 3):
 def variable_coef_leg(dev, rtol: float):
     """The variable-coefficient workload (N = 255, n = 512, backward Euler,
     a = 1 + 0.5 sin(2 pi x) sin(2 pi y) at faces, f ~ U(-1, 1), seed 1): P_theta with the
-    3-step Chebyshev per-mode solve, and P_H(Kbar) beside it (float64, physical-basis path)."""
+    3-step Chebyshev per-mode solve, and P_H(Kbar) beside it, each in float64 and with the
+    time transforms on the float32 matrix cores (physical-basis path); the mixed-precision
+    results carry their error against the float64 GPU solution."""
     import torch
     import workloads as W
     from paper_2201_10062_amd import Plan
@@ -194,16 +196,25 @@ def variable_coef_leg(dev, rtol: float):
     u0 = torch.from_numpy(p.u0).to(dev)
     out = {"workload": f"varcoef2d_N{p.N}_n{p.n}", "dof": p.n * p.m, "rtol": rtol}
     for name, kw in (("P_theta_cheb3", {"precond": "PTHETA_CHEB", "cheb_k": 3}), ("P_H_kbar", {})):
-        g = Plan(2, p.N, p.n, theta=p.theta, ax=p.ax, ay=p.ay, device=dev, **kw)
-        b = g.build_rhs(f, u0)
-        g.solve(b, rtol=rtol, maxit=400)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, info = g.solve(b, rtol=rtol, maxit=400)
-        torch.cuda.synchronize()
-        out[name] = {"time_to_tol_ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
-                     "relres_true": info["relres_true"], "status": info["status"]}
-        del g, b, x
+        x64 = None
+        for pprec in ("fp64", "fp32"):
+            g = Plan(2, p.N, p.n, theta=p.theta, ax=p.ax, ay=p.ay, device=dev, pprec=pprec, **kw)
+            b = g.build_rhs(f, u0)
+            g.solve(b, rtol=rtol, maxit=400)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = g.solve(b, rtol=rtol, maxit=400)
+            torch.cuda.synchronize()
+            rec = {"time_to_tol_ms": (time.perf_counter() - t0) * 1e3, "iters": info["iters"],
+                   "relres_true": info["relres_true"], "status": info["status"]}
+            if pprec == "fp64":
+                x64 = x
+                out[name] = rec
+            else:
+                rec["rel_err_vs_fp64"] = float((x - x64).abs().max() / x64.abs().max())
+                out[name]["mixed_fp32"] = rec
+            del g, b
+        del x, x64
     return out
 
 

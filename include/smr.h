@@ -67,9 +67,12 @@ typedef enum {
 typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;
 typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
 /* Arithmetic inside P^{-1} during the solves.  The matvec, the Lanczos recurrences, the
- * MINRES scalars and the true residual are always float64.  SMR_FP32 (time transform on the
- * float32 matrix cores, z stored in float32) is available wherever the solve runs in the
- * sine basis (see SMR_FLAG_GENERAL_PATH); smr_apply_P_inv always applies P^{-1} in float64. */
+ * MINRES scalars and the true residual are always float64.  SMR_FP32 runs the time-axis sine
+ * transforms of P^{-1} on the float32 matrix cores with float32 accumulation: in the sine
+ * basis (see SMR_FLAG_GENERAL_PATH) z is also stored in float32; on the physical-basis path
+ * (P_H, Phat, P_theta) the vectors, spatial transforms, 1/sigma scaling and Chebyshev steps
+ * stay float64.  SMR_EINVAL with SMR_P_NONE.  smr_apply_P_inv always applies P^{-1} in
+ * float64. */
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 /* P_H / Phat solves run in the spatial sine basis (b and x0 transformed on entry, x on exit;
  * the same iterates in exact arithmetic): for constant a, Y T and P^{-1} act per spatial mode

@@ -1,4 +1,4 @@
-// Time-axis sine transform (gfx950, FP64 matrix cores).
+// Time-axis sine transform (gfx950, FP64 or FP32 matrix cores).
 //
 // P_H^{-1} factorises as (S_n (x) U) diag(1/sigma) (S_n (x) U) (Sec. 3.1.1); along time the
 // sine matrix S_n has no fast radix-2 form for the sizes used here (n + 1 = 65, 129, 257,
@@ -13,6 +13,9 @@
 // LDS, the folded sine blocks stream from L2 in MFMA-fragment order, each of the 4
 // waves owns a set of 16x16 output tiles of both parities, and the final butterfly is
 // done in registers because a wave holds u' and d' of the same rows.
+// PR 1 (mixed precision): the butterflied columns and the sine blocks are float32 and the
+// GEMMs run on the float32 matrix cores with float32 accumulation; the vectors in memory, the
+// 1/sigma scaling and the Parseval sum stay float64.
 #include "smr_internal.h"
 
 namespace smr {
@@ -20,10 +23,32 @@ namespace smr {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core arithmetic: A[i][k] and B[k][j] sit in lane i + 16k and j + 16k for both
+// precisions; accumulator register r of lane l holds D[4r + l/16][l%16] for float64 and
+// D[4(l/16) + r][l%16] for float32 (checked on gfx950).
+template <int PR> struct TPrec;
+template <> struct TPrec<0> {
+  typedef double T;
+  typedef d4 Acc;
+  static __device__ __forceinline__ Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int bk) { return 4 * r + bk; }
+};
+template <> struct TPrec<1> {
+  typedef float T;
+  typedef f4 Acc;
+  static __device__ __forceinline__ Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int bk) { return 4 * bk + r; }
+};
 
 struct TimeP {
   int n, m, h1, h2;
-  const double *So, *SoT, *Se, *SeT;   // fragment order: [((r * HP/8 + kk/2) * 64 + lane) * 2 + kk%2]
+  const void *So, *SoT, *Se, *SeT;     // fragment order: [((r * HP/8 + kk/2) * 64 + lane) * 2 + kk%2]
   const double *tcoef;                 // 4 per time mode: sigma = |(A + t B) + i (C + t D)|
   const double *tmu;                   // per column: t = tau * mu
 };
@@ -50,17 +75,23 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
   return s;
 }
 
-template <int HP, int C, int MODE>
+template <int HP, int C, int MODE, int PR>
 __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
                                               double *__restrict__ part, const Scal *__restrict__ gate) {
+  typedef typename TPrec<PR>::T T;
+  typedef typename TPrec<PR>::Acc Acc;
   if (gate && gate->status != RUNNING) return;
   constexpr int LD = C + 1;                   // LDS row stride (doubles)
   constexpr int RT = HP / 16, CT = C / 16, NT = RT * CT;
   constexpr int TPW = (NT + 3) / 4;           // tiles per wave (per parity)
   constexpr int KS = HP / 4;                  // k-steps
-  extern __shared__ double lds[];
-  double *U = lds;                            // [HP][LD] even-symmetric half (u)
-  double *D = lds + HP * LD;                  // [HP][LD] odd-symmetric half (d)
+  extern __shared__ double lds_raw[];
+  T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
+  T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
+  const T *__restrict__ So = reinterpret_cast<const T *>(tp.So);
+  const T *__restrict__ Se = reinterpret_cast<const T *>(tp.Se);
+  const T *__restrict__ SoT = reinterpret_cast<const T *>(tp.SoT);
+  const T *__restrict__ SeT = reinterpret_cast<const T *>(tp.SeT);
   __shared__ double red[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -81,17 +112,15 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
         u = in[(size_t)p * m + col];
       }
     }
-    U[p * LD + c] = u;
-    D[p * LD + c] = d;
+    U[p * LD + c] = (T)u;
+    D[p * LD + c] = (T)d;
   }
   __syncthreads();
 
-  d4 ao[TPW], ae[TPW];
+  const Acc zacc = {0, 0, 0, 0};
+  Acc ao[TPW], ae[TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) { ao[t] = d4{0, 0, 0, 0}; ae[t] = d4{0, 0, 0, 0}; }
-
-  // Fragment layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A[i][k] and B[k][j] sit in
-  // lane i + 16k and j + 16k; accumulator register r of lane l holds D[4r + l/16][l%16].
+  for (int t = 0; t < TPW; ++t) { ao[t] = zacc; ae[t] = zacc; }
   const int bk = lane >> 4, bj = lane & 15;
 
   // 2. first GEMM: [S_o u | S_e d] for this wave's tiles
@@ -101,12 +130,12 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
       const int tile = wave + 4 * t;
       if (tile < NT) {
         const int r = tile / CT, ct = tile - r * CT;
-        const double bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double au = tp.So[frag_at(r, KS, kk, lane)];
-        const double ad = tp.Se[frag_at(r, KS, kk, lane)];
-        ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu, ao[t], 0, 0, 0);
-        ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd, ae[t], 0, 0, 0);
+        const T bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
+        const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
+        const T au = So[frag_at(r, KS, kk, lane)];
+        const T ad = Se[frag_at(r, KS, kk, lane)];
+        ao[t] = TPrec<PR>::mfma(au, bu, ao[t]);
+        ae[t] = TPrec<PR>::mfma(ad, bd, ae[t]);
       }
     }
   }
@@ -122,9 +151,9 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
       if (col >= m) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int p = 16 * r + 4 * i + bk;
-        if (p < h1) out[(size_t)(2 * p) * m + col] = ao[t][i];
-        if (p < h2) out[(size_t)(2 * p + 1) * m + col] = ae[t][i];
+        const int p = 16 * r + TPrec<PR>::row(i, bk);
+        if (p < h1) out[(size_t)(2 * p) * m + col] = (double)ao[t][i];
+        if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (double)ae[t][i];
       }
     }
     return;
@@ -142,39 +171,39 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
     const double tm = col < m ? tp.tmu[col] : 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int p = 16 * r + 4 * i + bk;
+      const int p = 16 * r + TPrec<PR>::row(i, bk);
       double so = 0.0, se = 0.0;
       if (col < m && p < h1) {
-        const double w = inv_sigma(tp, 2 * p, tm);
-        so = ao[t][i] * w;
-        g2 += ao[t][i] * so;
+        const double a = (double)ao[t][i];
+        so = a * inv_sigma(tp, 2 * p, tm);
+        g2 += a * so;
       }
       if (col < m && p < h2) {
-        const double w = inv_sigma(tp, 2 * p + 1, tm);
-        se = ae[t][i] * w;
-        g2 += ae[t][i] * se;
+        const double a = (double)ae[t][i];
+        se = a * inv_sigma(tp, 2 * p + 1, tm);
+        g2 += a * se;
       }
-      U[p * LD + cl] = so;
-      D[p * LD + cl] = se;
+      U[p * LD + cl] = (T)so;
+      D[p * LD + cl] = (T)se;
     }
   }
   __syncthreads();
 
   // 4. second GEMM with the transposed blocks
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) { ao[t] = d4{0, 0, 0, 0}; ae[t] = d4{0, 0, 0, 0}; }
+  for (int t = 0; t < TPW; ++t) { ao[t] = zacc; ae[t] = zacc; }
   for (int kk = 0; kk < KS; ++kk) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = wave + 4 * t;
       if (tile < NT) {
         const int r = tile / CT, ct = tile - r * CT;
-        const double bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const double au = tp.SoT[frag_at(r, KS, kk, lane)];
-        const double ad = tp.SeT[frag_at(r, KS, kk, lane)];
-        ao[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu, ao[t], 0, 0, 0);
-        ae[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad, bd, ae[t], 0, 0, 0);
+        const T bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
+        const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
+        const T au = SoT[frag_at(r, KS, kk, lane)];
+        const T ad = SeT[frag_at(r, KS, kk, lane)];
+        ao[t] = TPrec<PR>::mfma(au, bu, ao[t]);
+        ae[t] = TPrec<PR>::mfma(ad, bd, ae[t]);
       }
     }
   }
@@ -190,12 +219,13 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
     if (col >= m) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int p = 16 * r + 4 * i + bk;
+      const int p = 16 * r + TPrec<PR>::row(i, bk);
+      const double a = (double)ao[t][i], b = (double)ae[t][i];
       if (p < h2) {
-        out[(size_t)p * m + col] = ao[t][i] + ae[t][i];
-        out[(size_t)(n - 1 - p) * m + col] = ao[t][i] - ae[t][i];
+        out[(size_t)p * m + col] = a + b;
+        out[(size_t)(n - 1 - p) * m + col] = a - b;
       } else if (p < h1) {
-        out[(size_t)p * m + col] = ao[t][i];
+        out[(size_t)p * m + col] = a;
       }
     }
   }
@@ -205,21 +235,36 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
   }
 }
 
-template <int HP, int C>
+template <int HP, int C, int PR>
 hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int mode, double *part, int *nb,
                     const Scal *gate) {
   const int blocks = (tp.m + C - 1) / C;
   if (nb) *nb = blocks;
-  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(double);
+  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename TPrec<PR>::T);
   if (shmem > 65536) {
-    hipFuncSetAttribute((const void *)k_time<HP, C, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipFuncSetAttribute((const void *)k_time<HP, C, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   }
   if (mode == 0)
-    hipLaunchKernelGGL((k_time<HP, C, 0>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+    hipLaunchKernelGGL((k_time<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
   else
-    hipLaunchKernelGGL((k_time<HP, C, 1>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+    hipLaunchKernelGGL((k_time<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
   return hipGetLastError();
+}
+
+template <int PR>
+hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double *out, int mode, double *part,
+                       int *nb, const Scal *gate) {
+  switch (hp) {
+    case 16: return run_time<16, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 32: return run_time<32, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 64: return run_time<64, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 128: return run_time<128, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 256: return run_time<256, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 512: return run_time<512, 16, PR>(c, tp, in, out, mode, part, nb, gate);
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -229,19 +274,16 @@ int time_blocks(const Plan *p) {
   return (p->m + C - 1) / C;
 }
 
-hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nb, const Scal *gate) {
+hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nb, const Scal *gate,
+                       bool f32) {
   const Plan *p = c.p;
+  if (f32 && p->pprec != SMR_FP32) return hipErrorInvalidValue;   // no float32 tables
   TimeP tp{p->n, p->m, p->h1, p->h2, p->So, p->SoT, p->Se, p->SeT, p->tcoef, p->tmu};
-  switch (p->hp) {
-    case 16: return run_time<16, 32>(c, tp, in, out, mode, part, nb, gate);
-    case 32: return run_time<32, 32>(c, tp, in, out, mode, part, nb, gate);
-    case 64: return run_time<64, 32>(c, tp, in, out, mode, part, nb, gate);
-    case 128: return run_time<128, 32>(c, tp, in, out, mode, part, nb, gate);
-    case 256: return run_time<256, 32>(c, tp, in, out, mode, part, nb, gate);
-    case 512: return run_time<512, 16>(c, tp, in, out, mode, part, nb, gate);
-    default: break;
+  if (f32) {
+    tp.So = p->Sof; tp.SoT = p->SoTf; tp.Se = p->Sef; tp.SeT = p->SeTf;
+    return run_time_hp<1>(c, tp, p->hp, in, out, mode, part, nb, gate);
   }
-  return hipErrorInvalidValue;
+  return run_time_hp<0>(c, tp, p->hp, in, out, mode, part, nb, gate);
 }
 
 }  // namespace smr

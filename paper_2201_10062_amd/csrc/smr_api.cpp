@@ -169,8 +169,8 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EINVAL, "cheb_k must be in [1, 16] (got %d)", d->cheb_k);
   if (d->pprec != SMR_FP64 && d->pprec != SMR_FP32)
     return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
-  if (d->pprec == SMR_FP32 && (d->precond != SMR_P_H || (d->flags & SMR_FLAG_GENERAL_PATH)))
-    return fail(SMR_EUNSUPPORTED, "float32 preconditioning is available for the sine-basis P_H solve only");
+  if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
+    return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
   const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32;
   if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
   if ((d->flags & SMR_FLAG_TILE16) && (d->flags & SMR_FLAG_TILE32))
@@ -386,11 +386,6 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.a_min = amin;
   p.a_max = amax;
   p.const_coef = (amin == amax);
-  if (p.pprec == SMR_FP32 && !p.const_coef && !var_sine_basis(d)) {
-    delete pl;
-    return fail(SMR_EUNSUPPORTED, "float32 preconditioning needs the sine-basis solve (constant a, or 2D with "
-                                  "N + 1 in {32, 64, 128})");
-  }
   p.abar = 0.5 * (amin + amax);
   p.cheb_lo = std::min(1.0, amin / p.abar);
   p.cheb_hi = std::max(1.0, amax / p.abar);
@@ -572,8 +567,9 @@ smr_status check_plan(const smr_plan *pl) {
 }
 
 // z = P^{-1} v; gamma^2 partials (Parseval or an explicit dot) into part2, count in *nb2.
+// f32: the time transforms on the float32 matrix cores (the solve of an SMR_FP32 plan)
 smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, double *part2, int *nb2,
-                      const Scal *gate) {
+                      const Scal *gate, bool f32) {
   Ctx c{&p, s};
   if (p.precond == SMR_P_NONE) {
     HIP_TRY(hipMemcpyAsync(z, v, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -583,13 +579,13 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   if (p.precond == SMR_P_H) {
     LAUNCH(PROF_DST, launch_dst(c, 0, v, p.T1, p.n, 0, gate));
     if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T1, p.T1, p.n, 0, gate));
-    LAUNCH(PROF_TIME, launch_time(c, p.T1, p.T2, 1, part2, nb2, gate));
+    LAUNCH(PROF_TIME, launch_time(c, p.T1, p.T2, 1, part2, nb2, gate, f32));
     if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T2, p.T2, p.n, 0, gate));
     LAUNCH(PROF_DST, launch_dst(c, 0, p.T2, z, p.n, 0, gate));
     return SMR_OK;
   }
   // P_theta with k-step Chebyshev per time mode: res = T1, x = T2, dvec = T3, tmp = T4
-  LAUNCH(PROF_TIME, launch_time(c, v, p.T1, 0, nullptr, nullptr, gate));
+  LAUNCH(PROF_TIME, launch_time(c, v, p.T1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
   auto binv = [&](const double *in, double *out) -> smr_status {
     if (p.dim == 1) {
@@ -618,7 +614,7 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
       rho = rn;
     }
   }
-  LAUNCH(PROF_TIME, launch_time(c, p.T2, z, 0, nullptr, nullptr, gate));
+  LAUNCH(PROF_TIME, launch_time(c, p.T2, z, 0, nullptr, nullptr, gate, f32));
   if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
   return SMR_OK;
 }
@@ -855,7 +851,8 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
   int nb = 0, nb2 = 0;
   // v_1 = Y b - Y T x0, ||v_1||^2, ||b||^2
   LAUNCH(PROF_STENCIL, launch_apply_YT(c, x, nullptr, p.V[1], b, part, &nb, nullptr));
-  smr_status st = apply_pinv(p, s, p.V[1], p.Z[0], part2, &nb2, nullptr);
+  const bool f32 = p.pprec == SMR_FP32;
+  smr_status st = apply_pinv(p, s, p.V[1], p.Z[0], part2, &nb2, nullptr, f32);
   if (st != SMR_OK) return st;
   LAUNCH(PROF_SCALAR, launch_scalar_step(c, 0, part, nb, part2, nb2));
   int cv = 1, cz = 0, cw = 1;   // v_j = V[cv], v_{j-1} = V[1-cv]; z_j = Z[cz]; w_{j-1} = W[cw], w_{j-2} = W[1-cw]
@@ -876,7 +873,7 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
       LAUNCH(PROF_STENCIL, launch_apply_YT(c, zj, zs, p.Q, nullptr, part, &nb, gate));
       LAUNCH(PROF_SCALAR, launch_scalar_step(c, 1, part, nb, nullptr, 0));
       LAUNCH(PROF_VEC, launch_vupdate(c, p.Q, vj, vo, gate));
-      st = apply_pinv(p, s, vo, zn, part2, &nb2, gate);
+      st = apply_pinv(p, s, vo, zn, part2, &nb2, gate, f32);
       if (st != SMR_OK) return st;
       LAUNCH(PROF_SCALAR, launch_scalar_step(c, 2, part2, nb2, part2, nb2));
       LAUNCH(PROF_VEC, launch_wxupdate(c, zj, w2, w1, x, gate));
@@ -946,7 +943,7 @@ smr_status smr_apply_P_inv(const smr_plan *pl, const double *v, double *z, void 
   smr_status st = check_plan(pl);
   if (st != SMR_OK) return st;
   if (!v || !z) return fail(SMR_EINVAL, "v and z must be non-NULL");
-  return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr);
+  return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr, false);
 }
 
 smr_status smr_minres_solve(const smr_plan *pl, const double *b, const double *x0, double *x, double rtol,

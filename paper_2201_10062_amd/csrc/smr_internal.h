@@ -98,9 +98,10 @@ hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const dou
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
                       const Scal *gate, long in_stride = 0, long out_stride = 0);
 // Time transform: mode 0: out = (S_n (x) I) in; mode 1: out = (S_n (x) I) diag(1/sigma) (S_n (x) I) in
-// with partial sums of <D vhat, vhat> into part when part != null.
+// with partial sums of <D vhat, vhat> into part when part != null.  f32: the GEMMs on the
+// float32 matrix cores with the plan's float32 sine tables (pprec SMR_FP32 plans only).
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nblocks_out,
-                       const Scal *gate);
+                       const Scal *gate, bool f32 = false);
 int time_blocks(const Plan *p);
 
 // Elementwise / reductions / scalar steps.
