@@ -81,8 +81,9 @@ __device__ __forceinline__ double rsqrt64(double q) {
   return r;
 }
 
-__device__ __forceinline__ double inv_sigma(const SpecP &P, int tmode, double t) {
-  const double *c = P.tcoef + 4 * tmode;
+// tc: the 4 coefficients per time mode (from LDS where the block holds a copy)
+__device__ __forceinline__ double inv_sigma(const double *tc, int tmode, double t) {
+  const double *c = tc + 4 * tmode;
   const double re = c[0] + t * c[1];
   const double im = c[2] + t * c[3];
   return rsqrt64(re * re + im * im);
@@ -268,6 +269,13 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   T *D = U + HP * LD;                      // [HP][LD]
   __shared__ double red[4][kWaves];
   __shared__ Scal S;
+  // the sigma coefficients of all time modes in LDS (8 KB at hp = 128; read by the 1/sigma
+  // pass); larger hp keeps reading them from L2 so that two blocks still fit per CU
+  constexpr bool TCL = HP <= 128;
+  __shared__ double tcs[TCL ? 8 * HP : 1];
+  if (TCL)
+    for (int e = threadIdx.x; e < 4 * P.n; e += kThreads) tcs[e] = P.tcoef[e];
+  const double *tcl = TCL ? tcs : P.tcoef;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = P.n, m = P.m, ld = P.ld, h1 = P.h1, h2 = P.h2;
@@ -465,12 +473,12 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     double so = 0.0, se = 0.0;
     if (okc && pp < h1) {
       const double a = (double)U[pp * LD + cl];
-      so = a * inv_sigma(P, 2 * pp, tm);
+      so = a * inv_sigma(tcl, 2 * pp, tm);
       acc_g += a * so;
     }
     if (okc && pp < h2) {
       const double a = (double)D[pp * LD + cl];
-      se = a * inv_sigma(P, 2 * pp + 1, tm);
+      se = a * inv_sigma(tcl, 2 * pp + 1, tm);
       acc_g += a * se;
     }
     U[pp * LD + cl] = (T)so;
