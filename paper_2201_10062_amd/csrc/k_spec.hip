@@ -99,18 +99,21 @@ __device__ __forceinline__ double uni(double x) {
 }
 
 // Sums of four values over the block, in a fixed order; the result is valid in thread 0.
-__device__ __forceinline__ void block_sum4(double (&v)[4], double (*red)[kWaves]) {
+// LEAD: wait first for every thread to be done reading red (not needed when barriers have
+// passed since its last use).
+template <int NV, bool LEAD>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kWaves]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < NV; ++q)
     for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-  __syncthreads();
+  if (LEAD) __syncthreads();
   if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[q][threadIdx.x >> 6] = v[q];
+    for (int q = 0; q < NV; ++q) red[q][threadIdx.x >> 6] = v[q];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NV; ++q) {
       double s = 0.0;
       for (int w = 0; w < kWaves; ++w) s += red[q][w];
       v[q] = s;
@@ -184,7 +187,7 @@ __device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double 
 // GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
 // CT column tiles, acc[i][ct] += A[r] * B[:, ct] over the k dimension, with B the LDS block.
 // One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps 2q and 2q+1 side
-// by side per lane, so one load fetches two k-steps; loads run one such pair ahead.
+// by side per lane, so one load fetches two k-steps; loads run two such pairs ahead.
 template <int HP, int C, int PR>
 __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ A,
                                            const typename Prec<PR>::T *Bs, int wave, int lane,
@@ -202,18 +205,20 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
   for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[i][ct] = zacc;
-  T2 q0[RPW];
+  T2 q0[RPW], qn[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int r = wave + 4 * i;
     q0[i] = r < RT ? A2[(size_t)r * KP * 64 + lane] : zero2;
+    qn[i] = (r < RT && 1 < KP) ? A2[((size_t)r * KP + 1) * 64 + lane] : zero2;
   }
   for (int kp = 0; kp < KP; ++kp) {
     T2 q1[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int r = wave + 4 * i;
-      q1[i] = (r < RT && kp + 1 < KP) ? A2[((size_t)r * KP + kp + 1) * 64 + lane] : zero2;
+      q1[i] = qn[i];
+      qn[i] = (r < RT && kp + 2 < KP) ? A2[((size_t)r * KP + kp + 2) * 64 + lane] : zero2;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -267,7 +272,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   extern __shared__ double lds_raw[];
   T *U = reinterpret_cast<T *>(lds_raw);   // [HP][LD]
   T *D = U + HP * LD;                      // [HP][LD]
-  __shared__ double red[4][kWaves];
+  __shared__ double red[5][kWaves];
   __shared__ Scal S;
   // the sigma coefficients of all time modes in LDS (8 KB at hp = 128; read by the 1/sigma
   // pass); larger hp keeps reading them from L2 so that two blocks still fit per CU
@@ -293,28 +298,25 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
       if (tile == 0 && tid == 0) *snew = *sprev;
       return;
     }
+    if (tid == 0) S = *sprev;      // in flight with the partial sums below
     const double *pp = P.part + (size_t)((j + 1) & 1) * 4 * P.tiles;
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // t[4]: residuals skipped by the per-level matvec
     for (int b = tid; b < P.tiles; b += kThreads) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) t[q] += pp[4 * (size_t)b + q];
     }
-    double skip = 0.0;
     if (P.qext) {           // the per-level matvec's residual and delta partials
       for (int b = tid; b < P.nks; b += kThreads) {
         const double *kp = P.kpart + 4 * (size_t)b;
         t[0] += kp[0];
-        skip += kp[1];
+        t[4] += kp[1];
         t[3] += kp[3];
       }
     }
-    double u[4] = {skip, 0.0, 0.0, 0.0};
-    block_sum4(t, red);
-    block_sum4(u, red);
+    block_sum<5, false>(t, red);
     if (tid == 0) {
-      S = *sprev;
       // slot 1 of a steady launch flags a skipped residual (it holds ||b||^2 after INIT)
-      scalar_update(&S, pmode, t[0], t[1], t[2], t[3], u[0] == 0.0 && (pmode != MODE_STEADY || t[1] == 0.0));
+      scalar_update(&S, pmode, t[0], t[1], t[2], t[3], t[4] == 0.0 && (pmode != MODE_STEADY || t[1] == 0.0));
       if (tile == 0) *snew = S;
     }
     __syncthreads();
@@ -528,7 +530,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
 
   // ---- E. block partials of this launch (reduced at the start of the next one)
   double t[4] = {acc_r, acc_b, acc_g, acc_d};
-  block_sum4(t, red);
+  block_sum<4, false>(t, red);
   if (tid == 0) {
     double *pp = P.part + (size_t)(j & 1) * 4 * P.tiles + 4 * (size_t)tile;
     pp[0] = t[0]; pp[1] = t[1]; pp[2] = t[2]; pp[3] = t[3];
