@@ -172,6 +172,7 @@ __device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddl
 template <int R, int KMAX>
 __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int wave, int lane) {
   const int N = K.N, LP = N + 2;
+  constexpr int NC = 32 * R - 1;   // = N (the launcher picks R = (N + 1) / 32): divisions by a constant
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(K.tw), lane);
   dst_level<R, 0>(X, N, LP, W, K.scale, wave, lane);
@@ -184,7 +185,7 @@ __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int 
     const int e = tid + k * kKT;
     kv[k] = 0.0;
     if (e < N * N) {
-      const int j = e / N, i = e - j * N;
+      const int j = e / NC, i = e - j * NC;
       const double uc = X[j * LP + i];
       const double uw = i > 0 ? X[j * LP + i - 1] : 0.0;
       const double ue = i < N - 1 ? X[j * LP + i + 1] : 0.0;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int 
   for (int k = 0; k < KMAX; ++k) {
     const int e = tid + k * kKT;
     if (e < N * N) {
-      const int j = e / N, i = e - j * N;
+      const int j = e / NC, i = e - j * NC;
       X[j * LP + i] = kv[k];
     }
   }
@@ -240,6 +241,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
   __shared__ double red[4][kKW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = K.N, n = K.n, m = K.m, LP = N + 2;
+  constexpr int NC = 32 * R - 1;   // = N (the launcher picks R = (N + 1) / 32): divisions by a constant
   const size_t ld = (size_t)K.ld;
   const int j = jfull % 6;   // rotation phase of the z buffers
   bool do_res = false;
@@ -267,7 +269,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     for (int e = tid; e < m; e += kKT) {
       const double v0 = (double)st[e];
       const double v1 = s1 ? (double)s1[e] : 0.0;
-      const int jr = e / N, ir = e - jr * N;
+      const int jr = e / NC, ir = e - jr * NC;
       X[jr * LP + ir] = b0 * v0 + b1 * v1;
     }
     __syncthreads();
@@ -278,7 +280,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
       const double v0 = (double)st[e];
       const double v1 = s1 ? (double)s1[e] : 0.0;
       const double v2 = s2 ? (double)s2[e] : 0.0;
-      const int jr = e / N, ir = e - jr * N;
+      const int jr = e / NC, ir = e - jr * NC;
       const double v = c0 * v0 + c1 * v1 + c2 * v2 + K.tau * X[jr * LP + ir];
       q[e] = v;
       if (MODE == 1) acc_d += v * (double)sf[e];
@@ -294,7 +296,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     for (int e = tid; e < m; e += kKT) {
       const double v0 = xt[e];
       const double v1 = x1 ? x1[e] : 0.0;
-      const int jr = e / N, ir = e - jr * N;
+      const int jr = e / NC, ir = e - jr * NC;
       X[jr * LP + ir] = b0 * v0 + b1 * v1;
     }
     __syncthreads();
@@ -303,7 +305,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
       const double v0 = xt[e];
       const double v1 = x1 ? x1[e] : 0.0;
       const double v2 = x2 ? x2[e] : 0.0;
-      const int jr = e / N, ir = e - jr * N;
+      const int jr = e / NC, ir = e - jr * NC;
       const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2) - K.tau * X[jr * LP + ir];
       acc_r += r * r;
     }
