@@ -260,7 +260,7 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
     case 32: return run_time<32, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 64: return run_time<64, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 128: return run_time<128, 32, PR>(c, tp, in, out, mode, part, nb, gate);
-    case 256: return run_time<256, 32, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 256: return run_time<256, 16, PR>(c, tp, in, out, mode, part, nb, gate);
     case 512: return run_time<512, 16, PR>(c, tp, in, out, mode, part, nb, gate);
     default: break;
   }
@@ -270,7 +270,7 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
 }  // namespace
 
 int time_blocks(const Plan *p) {
-  const int C = p->hp >= 512 ? 16 : 32;
+  const int C = p->hp >= 256 ? 16 : 32;   // two blocks per CU: 2 * hp * (C + 1) doubles of LDS each
   return (p->m + C - 1) / C;
 }
 
