@@ -1,4 +1,4 @@
-// Spatial sine transforms (gfx950).  The orthonormal DST-I S_N (Sec. 3.1.1, S_n of
+// Spatial sine transforms (gfx950), general form.  The orthonormal DST-I S_N (Sec. 3.1.1, S_n of
 // eqn:matrix_tri_p with n -> N) along x (contiguous lines) or y (stride-N lines) of
 // every time slice, for N + 1 = L a power of two.
 //
@@ -147,6 +147,8 @@ DstP make_dst(const Plan *p, int dir, int nslices) {
 
 static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
                           const Scal *gate, long in_stride, long out_stride) {
+  // 2D with N + 1 in {32, ..., 256}: line tiles through the register FFT
+  if (dst_tile_supported(c.p)) return launch_dst_tile(c, dir, in, out, nslices, scale_mode, gate, in_stride, out_stride);
   DstP d = make_dst(c.p, dir, nslices);
   d.scale_mode = scale_mode;
   if (in_stride) d.sin = in_stride;

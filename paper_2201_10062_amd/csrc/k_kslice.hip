@@ -99,6 +99,43 @@ __device__ __forceinline__ void dif_stage(double2 (&v)[R], double sg, double2 wm
   }
 }
 
+// In-lane 8-point DFT in natural order, v[k] <- sum_j v[j] exp(-2 pi i j k / 8): radix-2
+// decimation in frequency (spans 4, 2, 1), then the bit-reversal permutation.
+__device__ __forceinline__ double2 mul_w8(double2 a, int k) {   // a exp(-2 pi i k / 8)
+  constexpr double h = 0.70710678118654752440;                   // cos(pi / 4)
+  switch (k & 7) {
+    case 0: return a;
+    case 1: return make_double2(h * (a.x + a.y), h * (a.y - a.x));
+    case 2: return make_double2(a.y, -a.x);
+    default: return make_double2(h * (a.y - a.x), -h * (a.x + a.y));   // k = 3
+  }
+}
+__device__ __forceinline__ void lane_dft8(double2 (&v)[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 a = v[k], c = v[k + 4];
+    v[k] = cadd(a, c);
+    v[k + 4] = mul_w8(csub(a, c), k);
+  }
+#pragma unroll
+  for (int b = 0; b < 8; b += 4)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double2 a = v[b + k], c = v[b + k + 2];
+      v[b + k] = cadd(a, c);
+      v[b + k + 2] = mul_w8(csub(a, c), 2 * k);
+    }
+#pragma unroll
+  for (int b = 0; b < 8; b += 2) {
+    const double2 a = v[b], c = v[b + 1];
+    v[b] = cadd(a, c);
+    v[b + 1] = csub(a, c);
+  }
+  // position q holds frequency brev3(q): swap 1 <-> 4 and 3 <-> 6
+  double2 t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[3]; v[3] = v[6]; v[6] = t;
+}
+
 // In-register M-point DFT (M = 64 R) of the values v[j1] = z[64 j1 + lane]; on return
 // v[k1] = Z[k1 + R brev6(lane)].  A decimation-in-frequency butterfly of the pair
 // (a, b) = (top, bottom) gives a + b on the top lane and (a - b) w on the bottom one; with
@@ -118,6 +155,7 @@ __device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const Twiddl
     v[1] = make_double2(a1.x + a3.y, a1.y - a3.x);   // a1 - i a3
     v[3] = make_double2(a1.x - a3.y, a1.y + a3.x);   // a1 + i a3
   }
+  if constexpr (R == 8) lane_dft8(v);
 #pragma unroll
   for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], W.in[k1 - 1]);
   dif_stage<R, 32>(v, W.sg[0], W.wm[0]);
@@ -131,11 +169,11 @@ __device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const Twiddl
 // Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS
 // (row pitch LP), in place; each wave takes pairs of lines.
 template <int R, int DIR>
-__device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddles<R> &W, double scale, int wave,
-                                          int lane) {
+__device__ __forceinline__ void dst_lines(double *X, int N, int nl, int LP, const Twiddles<R> &W, double scale,
+                                          int wave, int lane) {
   constexpr int M = 64 * R, L = M / 2;
   auto at = [&](int line, int pos) { return DIR == 0 ? line * LP + pos : pos * LP + line; };
-  const int npairs = (N + 1) / 2;
+  const int npairs = (nl + 1) / 2;
   // odd-extension source position and sign of this lane's R values (independent of the pair)
   int srcp[R];
   double sgn[R];
@@ -147,8 +185,8 @@ __device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddl
     sgn[j1] = lo ? 1.0 : hi ? -1.0 : 0.0;
   }
   for (int pr = wave; pr < npairs; pr += kKW) {
-    const int la = 2 * pr, lb = min(2 * pr + 1, N - 1);
-    const double bmask = 2 * pr + 1 < N ? 1.0 : 0.0;
+    const int la = 2 * pr, lb = min(2 * pr + 1, nl - 1);
+    const double bmask = 2 * pr + 1 < nl ? 1.0 : 0.0;
     double2 v[R];
 #pragma unroll
     for (int j1 = 0; j1 < R; ++j1) {
@@ -162,10 +200,17 @@ __device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddl
       const int K = k1 + R * k2;
       if (K >= 1 && K <= N) {
         X[at(la, K - 1)] = -v[k1].y * scale;
-        if (2 * pr + 1 < N) X[at(lb, K - 1)] = v[k1].x * scale;
+        if (2 * pr + 1 < nl) X[at(lb, K - 1)] = v[k1].x * scale;
       }
     }
   }
+}
+
+// The same for all N lines of an N x N level.
+template <int R, int DIR>
+__device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddles<R> &W, double scale, int wave,
+                                          int lane) {
+  dst_lines<R, DIR>(X, N, N, LP, W, scale, wave, lane);
 }
 
 // X <- U K(a) U X for the level in LDS (U applied as DST along rows, then columns).
@@ -402,6 +447,119 @@ hipError_t run_ks_r(hipStream_t st, int L, const KsP *K, const KsP *table, int n
 }
 
 }  // namespace
+
+namespace {
+
+// One spatial DST-I pass over a 2D field (N + 1 = 32 R): along x (DIR 0, rows) or y (DIR 1,
+// columns) of every time slice.  A block owns up to kTL lines of one slice, loads them
+// coalesced into LDS (rows: contiguous; columns: kTL neighbours per row), every wave runs line
+// pairs through the register FFT, and the block stores them back (all loads finish before any
+// store, so in == out is allowed).  scale_mode 1 divides by the Chebyshev inner diagonal
+// ez[s] + ez[n + s] abar tmu_lap[q].
+constexpr int kTL = 32;
+struct TileP {
+  int N, n, tiles;            // tiles per slice
+  long sin, sout;
+  double scale, abar;
+  const double *tw, *ez, *tmu_lap;
+  int scale_mode;
+};
+
+template <int R, int DIR>
+__global__ __launch_bounds__(kKT) void k_dst_tile(TileP d, const double *__restrict__ in, double *__restrict__ out,
+                                                  const Scal *__restrict__ gate) {
+  if (gate && gate->status != RUNNING) return;
+  extern __shared__ double X[];
+  constexpr int N = 32 * R - 1;
+  constexpr int LP = DIR == 0 ? N + 2 : kTL + 1;   // LDS pitch of a line (DIR 0) or a position (DIR 1)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = blockIdx.x / d.tiles, i0 = (blockIdx.x - s * d.tiles) * kTL;
+  const int nl = min(kTL, N - i0);
+  const double *src = in + (size_t)s * d.sin;
+  double *dst = out + (size_t)s * d.sout;
+  Twiddles<R> W;
+  W.load(reinterpret_cast<const double2 *>(d.tw), lane);
+  if (DIR == 0) {
+    for (int e = tid; e < nl * N; e += kKT) {           // rows i0.. are contiguous
+      const int c = e / N, j = e - c * N;
+      X[c * LP + j] = src[(size_t)i0 * N + e];
+    }
+  } else {
+    for (int e = tid; e < kTL * N; e += kKT) {
+      const int j = e / kTL, c = e - j * kTL;
+      if (c < nl) X[j * LP + c] = src[(size_t)j * N + i0 + c];
+    }
+  }
+  __syncthreads();
+  dst_lines<R, DIR>(X, N, nl, LP, W, d.scale, wave, lane);
+  __syncthreads();
+  auto fin = [&](double v, size_t q) {
+    return d.scale_mode == 1 ? v / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : v;
+  };
+  if (DIR == 0) {
+    for (int e = tid; e < nl * N; e += kKT) {
+      const int c = e / N, j = e - c * N;
+      const size_t q = (size_t)i0 * N + e;
+      dst[q] = fin(X[c * LP + j], q);
+    }
+  } else {
+    for (int e = tid; e < kTL * N; e += kKT) {
+      const int j = e / kTL, c = e - j * kTL;
+      if (c < nl) {
+        const size_t q = (size_t)j * N + i0 + c;
+        dst[q] = fin(X[j * LP + c], q);
+      }
+    }
+  }
+}
+
+template <int R>
+hipError_t run_dst_tile(hipStream_t st, int dir, const TileP &d, int nslices, const double *in, double *out,
+                        const Scal *gate) {
+  constexpr int N = 32 * R - 1;
+  const size_t sh = (size_t)(dir == 0 ? kTL * (N + 2) : N * (kTL + 1)) * sizeof(double);
+  const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0> : (const void *)k_dst_tile<R, 1>;
+  if (sh > 65536) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+  }
+  const unsigned blocks = (unsigned)((long)nslices * d.tiles);
+  if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kKT), sh, st, d, in, out, gate);
+  else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kKT), sh, st, d, in, out, gate);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool dst_tile_supported(const Plan *p) {
+  return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128 || p->L == 256);
+}
+
+hipError_t launch_dst_tile(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
+                           const Scal *gate, long in_stride, long out_stride) {
+  const Plan *p = c.p;
+  if (!dst_tile_supported(p)) return hipErrorInvalidValue;
+  TileP d{};
+  d.N = p->N;
+  d.n = p->n;
+  d.tiles = (p->N + kTL - 1) / kTL;
+  d.sin = in_stride ? in_stride : p->m;
+  d.sout = out_stride ? out_stride : p->m;
+  d.scale = 1.0 / sqrt(2.0 * p->L);
+  d.abar = p->abar;
+  d.tw = p->tw;
+  d.ez = p->ez;
+  d.tmu_lap = p->tmu_lap;
+  d.scale_mode = scale_mode;
+  switch (p->L) {
+    case 32: return run_dst_tile<1>(c.st, dir, d, nslices, in, out, gate);
+    case 64: return run_dst_tile<2>(c.st, dir, d, nslices, in, out, gate);
+    case 128: return run_dst_tile<4>(c.st, dir, d, nslices, in, out, gate);
+    case 256: return run_dst_tile<8>(c.st, dir, d, nslices, in, out, gate);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
 
 bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128); }
 

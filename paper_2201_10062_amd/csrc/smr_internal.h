@@ -162,6 +162,11 @@ bool kslice_supported(const Plan *p);
 // 2D spatial sine transform of every time level in one pass (dim 2, N + 1 in {32, 64, 128});
 // out may equal in only when the strides agree
 hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride);
+// One DST-I pass (the arguments of launch_dst) as line tiles through the register FFT, for 2D
+// plans with N + 1 in {32, 64, 128, 256}; launch_dst takes it where it applies.
+bool dst_tile_supported(const Plan *p);
+hipError_t launch_dst_tile(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
+                           const Scal *gate, long in_stride, long out_stride);
 KsP kslice_desc(const Plan *p, double *x, const double *bh);
 // mode 0: q = (T x)^ before the initialising launch; mode 1: q = (T z_j)^ with its partials
 // before fused launch j

@@ -66,6 +66,8 @@ OPS = [
     (2, 31, 20, "bdf2", 1.0, "var"),
     (2, 3, 1, "theta", 1.0, "const"),
     (2, 1, 3, "theta", 0.5, "var"),
+    (2, 255, 4, "theta", 1.0, "var"),
+    (2, 255, 3, "bdf2", 1.0, "smooth"),
 ]
 
 
@@ -86,7 +88,7 @@ def test_apply_P_inv_parity(dim, N, n, scheme, theta, kind):
 
 
 @pytest.mark.parametrize("dim,N,n,theta,k", [(2, 15, 12, 1.0, 1), (2, 31, 9, 0.5, 3), (1, 31, 16, 1.0, 4),
-                                             (2, 7, 6, 1.0, 2)])
+                                             (2, 7, 6, 1.0, 2), (2, 127, 5, 1.0, 2), (2, 255, 3, 1.0, 2)])
 def test_apply_P_theta_cheb_parity(dim, N, n, theta, k):
     g, o = _pair(dim, N, n, "theta", theta, precond="PTHETA_CHEB", kind="var", cheb_k=k)
     v = np.random.default_rng(3).standard_normal(n * g.m)
