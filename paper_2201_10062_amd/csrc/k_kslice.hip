@@ -168,7 +168,7 @@ __device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const Twiddl
 
 // Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS
 // (row pitch LP), in place; each wave takes pairs of lines.
-template <int R, int DIR>
+template <int R, int DIR, int NW = kKW>   // NW: waves of the block
 __device__ __forceinline__ void dst_lines(double *X, int N, int nl, int LP, const Twiddles<R> &W, double scale,
                                           int wave, int lane) {
   constexpr int M = 64 * R, L = M / 2;
@@ -184,7 +184,7 @@ __device__ __forceinline__ void dst_lines(double *X, int N, int nl, int LP, cons
     srcp[j1] = lo ? jn - 1 : hi ? M - jn - 1 : 0;
     sgn[j1] = lo ? 1.0 : hi ? -1.0 : 0.0;
   }
-  for (int pr = wave; pr < npairs; pr += kKW) {
+  for (int pr = wave; pr < npairs; pr += NW) {
     const int la = 2 * pr, lb = min(2 * pr + 1, nl - 1);
     const double bmask = 2 * pr + 1 < nl ? 1.0 : 0.0;
     double2 v[R];
@@ -457,6 +457,8 @@ namespace {
 // store, so in == out is allowed).  scale_mode 1 divides by the Chebyshev inner diagonal
 // ez[s] + ez[n + s] abar tmu_lap[q].
 constexpr int kTL = 32;
+constexpr int kTT = 256;    // threads of a tile block: two blocks share a CU, one loads or stores
+                            // while the other transforms
 struct TileP {
   int N, n, tiles;            // tiles per slice
   long sin, sout;
@@ -466,7 +468,7 @@ struct TileP {
 };
 
 template <int R, int DIR>
-__global__ __launch_bounds__(kKT) void k_dst_tile(TileP d, const double *__restrict__ in, double *__restrict__ out,
+__global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restrict__ in, double *__restrict__ out,
                                                   const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   extern __shared__ double X[];
@@ -480,30 +482,30 @@ __global__ __launch_bounds__(kKT) void k_dst_tile(TileP d, const double *__restr
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(d.tw), lane);
   if (DIR == 0) {
-    for (int e = tid; e < nl * N; e += kKT) {           // rows i0.. are contiguous
+    for (int e = tid; e < nl * N; e += kTT) {           // rows i0.. are contiguous
       const int c = e / N, j = e - c * N;
       X[c * LP + j] = src[(size_t)i0 * N + e];
     }
   } else {
-    for (int e = tid; e < kTL * N; e += kKT) {
+    for (int e = tid; e < kTL * N; e += kTT) {
       const int j = e / kTL, c = e - j * kTL;
       if (c < nl) X[j * LP + c] = src[(size_t)j * N + i0 + c];
     }
   }
   __syncthreads();
-  dst_lines<R, DIR>(X, N, nl, LP, W, d.scale, wave, lane);
+  dst_lines<R, DIR, kTT / 64>(X, N, nl, LP, W, d.scale, wave, lane);
   __syncthreads();
   auto fin = [&](double v, size_t q) {
     return d.scale_mode == 1 ? v / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : v;
   };
   if (DIR == 0) {
-    for (int e = tid; e < nl * N; e += kKT) {
+    for (int e = tid; e < nl * N; e += kTT) {
       const int c = e / N, j = e - c * N;
       const size_t q = (size_t)i0 * N + e;
       dst[q] = fin(X[c * LP + j], q);
     }
   } else {
-    for (int e = tid; e < kTL * N; e += kKT) {
+    for (int e = tid; e < kTL * N; e += kTT) {
       const int j = e / kTL, c = e - j * kTL;
       if (c < nl) {
         const size_t q = (size_t)j * N + i0 + c;
@@ -524,8 +526,8 @@ hipError_t run_dst_tile(hipStream_t st, int dir, const TileP &d, int nslices, co
     if (e != hipSuccess) return e;
   }
   const unsigned blocks = (unsigned)((long)nslices * d.tiles);
-  if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kKT), sh, st, d, in, out, gate);
-  else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kKT), sh, st, d, in, out, gate);
+  if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
+  else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
   return hipGetLastError();
 }
 
