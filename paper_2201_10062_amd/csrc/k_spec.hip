@@ -21,6 +21,7 @@
 // The iterate x_{j-1} and its residual are final one launch after v_j, z_j: the stop test
 // is the same (first iteration whose true residual is <= rtol), one launch later.
 #include "smr_internal.h"
+#include "mfma_tiles.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -29,31 +30,8 @@ namespace smr {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 512;         // 8 waves
 
-// Arithmetic of the time transform: PR 0 = float64 (v_mfma_f64_16x16x4f64), PR 1 = float32
-// (v_mfma_f32_16x16x4f32).  Fragment layouts (checked on gfx950): A[i][k] in lane i + 16k and
-// B[k][j] in lane j + 16k for both; accumulator register r of lane l holds D[4r + l/16][l%16]
-// for float64 but D[4(l/16) + r][l%16] for float32.
-template <int PR> struct Prec;
-template <> struct Prec<0> {
-  typedef double T;
-  typedef d4 Acc;
-  static __device__ __forceinline__ Acc mfma(double a, double b, Acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int q, int bk) { return 4 * q + bk; }
-};
-template <> struct Prec<1> {
-  typedef float T;
-  typedef f4 Acc;
-  static __device__ __forceinline__ Acc mfma(float a, float b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int q, int bk) { return 4 * bk + q; }
-};
 constexpr int kWaves = kThreads / 64;
 
 // MODE_EARLY: a steady iteration of launch 2 or 3, where w_{j-2} or w_{j-3} does not exist yet
@@ -181,83 +159,6 @@ __device__ void scalar_update(Scal *sc, int pmode, double s0, double s1, double 
     sc->va = sc->delta / gn;
     sc->vb = gn / g;
     sc->zs = 1.0 / gn;
-  }
-}
-
-// GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
-// CT column tiles, acc[i][ct] += A[r] * B[:, ct] over the k dimension, with B the LDS block.
-// One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps 2q and 2q+1 side
-// by side per lane, so one load fetches two k-steps; loads run two such pairs ahead.
-template <int HP, int C, int PR>
-__device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ A,
-                                           const typename Prec<PR>::T *Bs, int wave, int lane,
-                                           typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16]) {
-  typedef typename Prec<PR>::T T;
-  typedef typename std::conditional<PR == 0, double2, float2>::type T2;
-  constexpr int LD = C + 1;
-  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
-  constexpr int KS = HP / 4, KP = KS / 2;         // k-steps, k-step pairs
-  const int bk = lane >> 4, bj = lane & 15;
-  const T2 *__restrict__ A2 = reinterpret_cast<const T2 *>(A);
-  const T2 zero2 = {T(0), T(0)};
-  const typename Prec<PR>::Acc zacc = {0, 0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < RPW; ++i)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[i][ct] = zacc;
-  T2 q0[RPW], qn[RPW];
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
-    q0[i] = r < RT ? A2[(size_t)r * KP * 64 + lane] : zero2;
-    qn[i] = (r < RT && 1 < KP) ? A2[((size_t)r * KP + 1) * 64 + lane] : zero2;
-  }
-  for (int kp = 0; kp < KP; ++kp) {
-    T2 q1[RPW];
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int r = wave + 4 * i;
-      q1[i] = qn[i];
-      qn[i] = (r < RT && kp + 2 < KP) ? A2[((size_t)r * KP + kp + 2) * 64 + lane] : zero2;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int kk = 2 * kp + h;
-      T b[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) b[ct] = Bs[(4 * kk + bk) * LD + 16 * ct + bj];
-#pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        if (wave + 4 * i < RT) {
-          const T a = h ? q0[i].y : q0[i].x;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) acc[i][ct] = Prec<PR>::mfma(a, b[ct], acc[i][ct]);
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) q0[i] = q1[i];
-  }
-}
-
-// Accumulator tiles of the four matrix-core waves -> LDS rows, in the accumulator layout of
-// the transform's precision.
-template <int HP, int C, int PR>
-__device__ __forceinline__ void store_acc(const typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16],
-                                          typename Prec<PR>::T *Dst, int wave, int lane) {
-  constexpr int LD = C + 1;
-  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
-  const int bk = lane >> 4, bj = lane & 15;
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
-    if (r >= RT) continue;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int cl = 16 * ct + bj;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Dst[(16 * r + Prec<PR>::row(q, bk)) * LD + cl] = acc[i][ct][q];
-    }
   }
 }
 

@@ -10,45 +10,22 @@
 // <S x, diag(1/sigma) S x> (= gamma^2 by Parseval) per block.
 //
 // A block owns C consecutive columns (spatial points); its butterflied columns sit in
-// LDS, the folded sine blocks stream from L2 in MFMA-fragment order, each of the 4
-// waves owns a set of 16x16 output tiles of both parities, and the final butterfly is
-// done in registers because a wave holds u' and d' of the same rows.
+// LDS and the four waves multiply them by one folded sine block per pass (the fragments
+// stream from L2 in MFMA-fragment order, two k-steps per load); the results go back to LDS,
+// where the 1/sigma scaling and the final butterfly read them.
 // PR 1 (mixed precision): the butterflied columns and the sine blocks are float32 and the
 // GEMMs run on the float32 matrix cores with float32 accumulation; the vectors in memory, the
 // 1/sigma scaling and the Parseval sum stay float64.
 #include "smr_internal.h"
+#include "mfma_tiles.h"
 
 namespace smr {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-// Matrix-core arithmetic: A[i][k] and B[k][j] sit in lane i + 16k and j + 16k for both
-// precisions; accumulator register r of lane l holds D[4r + l/16][l%16] for float64 and
-// D[4(l/16) + r][l%16] for float32 (checked on gfx950).
-template <int PR> struct TPrec;
-template <> struct TPrec<0> {
-  typedef double T;
-  typedef d4 Acc;
-  static __device__ __forceinline__ Acc mfma(double a, double b, Acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int r, int bk) { return 4 * r + bk; }
-};
-template <> struct TPrec<1> {
-  typedef float T;
-  typedef f4 Acc;
-  static __device__ __forceinline__ Acc mfma(float a, float b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int r, int bk) { return 4 * bk + r; }
-};
-
 struct TimeP {
   int n, m, h1, h2;
-  const void *So, *SoT, *Se, *SeT;     // fragment order: [((r * HP/8 + kk/2) * 64 + lane) * 2 + kk%2]
+  const void *So, *SoT, *Se, *SeT;     // folded sine blocks (fragment-pair order) in the GEMM precision
   const double *tcoef;                 // 4 per time mode: sigma = |(A + t B) + i (C + t D)|
   const double *tmu;                   // per column: t = tau * mu
 };
@@ -58,10 +35,6 @@ __device__ __forceinline__ double inv_sigma(const TimeP &tp, int tmode, double t
   const double re = c[0] + t * c[1];
   const double im = c[2] + t * c[3];
   return 1.0 / sqrt(re * re + im * im);
-}
-
-__device__ __forceinline__ size_t frag_at(int r, int ks, int kk, int lane) {
-  return (((size_t)r * (ks / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
 }
 
 __device__ __forceinline__ double block_sum256(double v, double *red) {
@@ -75,11 +48,17 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
   return s;
 }
 
+// hp <= 128: both parities per k-step (each wave owns output tiles of both halves and keeps
+// their accumulators; the final butterfly runs in registers).
+__device__ __forceinline__ size_t frag_at(int r, int ks, int kk, int lane) {
+  return (((size_t)r * (ks / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
+}
+
 template <int HP, int C, int MODE, int PR>
-__global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
+__global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
                                               double *__restrict__ part, const Scal *__restrict__ gate) {
-  typedef typename TPrec<PR>::T T;
-  typedef typename TPrec<PR>::Acc Acc;
+  typedef typename Prec<PR>::T T;
+  typedef typename Prec<PR>::Acc Acc;
   if (gate && gate->status != RUNNING) return;
   constexpr int LD = C + 1;                   // LDS row stride (doubles)
   constexpr int RT = HP / 16, CT = C / 16, NT = RT * CT;
@@ -134,8 +113,8 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
         const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
         const T au = So[frag_at(r, KS, kk, lane)];
         const T ad = Se[frag_at(r, KS, kk, lane)];
-        ao[t] = TPrec<PR>::mfma(au, bu, ao[t]);
-        ae[t] = TPrec<PR>::mfma(ad, bd, ae[t]);
+        ao[t] = Prec<PR>::mfma(au, bu, ao[t]);
+        ae[t] = Prec<PR>::mfma(ad, bd, ae[t]);
       }
     }
   }
@@ -151,7 +130,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
       if (col >= m) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int p = 16 * r + TPrec<PR>::row(i, bk);
+        const int p = 16 * r + Prec<PR>::row(i, bk);
         if (p < h1) out[(size_t)(2 * p) * m + col] = (double)ao[t][i];
         if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (double)ae[t][i];
       }
@@ -171,7 +150,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
     const double tm = col < m ? tp.tmu[col] : 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int p = 16 * r + TPrec<PR>::row(i, bk);
+      const int p = 16 * r + Prec<PR>::row(i, bk);
       double so = 0.0, se = 0.0;
       if (col < m && p < h1) {
         const double a = (double)ao[t][i];
@@ -202,8 +181,8 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
         const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
         const T au = SoT[frag_at(r, KS, kk, lane)];
         const T ad = SeT[frag_at(r, KS, kk, lane)];
-        ao[t] = TPrec<PR>::mfma(au, bu, ao[t]);
-        ae[t] = TPrec<PR>::mfma(ad, bd, ae[t]);
+        ao[t] = Prec<PR>::mfma(au, bu, ao[t]);
+        ae[t] = Prec<PR>::mfma(ad, bd, ae[t]);
       }
     }
   }
@@ -219,7 +198,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
     if (col >= m) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int p = 16 * r + TPrec<PR>::row(i, bk);
+      const int p = 16 * r + Prec<PR>::row(i, bk);
       const double a = (double)ao[t][i], b = (double)ae[t][i];
       if (p < h2) {
         out[(size_t)p * m + col] = a + b;
@@ -235,20 +214,141 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
   }
 }
 
+// hp >= 256: one folded block per pass (fewer live accumulators), results through LDS.
+// One block: C columns, all n levels; four waves, all on the matrix cores.
+template <int HP, int C, int MODE, int PR>
+__global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
+                                              double *__restrict__ part, const Scal *__restrict__ gate) {
+  typedef typename Prec<PR>::T T;
+  typedef typename Prec<PR>::Acc Acc;
+  if (gate && gate->status != RUNNING) return;
+  constexpr int LD = C + 1;                   // LDS pitch
+  constexpr int RPW = (HP / 16 + 3) / 4, CT = C / 16;
+  extern __shared__ double lds_raw[];
+  T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
+  T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
+  __shared__ double red[4];
+  const T *So = reinterpret_cast<const T *>(tp.So), *Se = reinterpret_cast<const T *>(tp.Se);
+  const T *SoT = reinterpret_cast<const T *>(tp.SoT), *SeT = reinterpret_cast<const T *>(tp.SeT);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col0 = blockIdx.x * C;
+  const int n = tp.n, m = tp.m, h1 = tp.h1, h2 = tp.h2;
+
+  // 1. butterfly load (zero padding rows and columns beyond m)
+  for (int e = tid; e < HP * C; e += 256) {
+    const int p = e / C, c = e - p * C;
+    const int col = col0 + c;
+    double u = 0.0, d = 0.0;
+    if (col < m) {
+      if (p < h2) {
+        const double a = in[(size_t)p * m + col], b = in[(size_t)(n - 1 - p) * m + col];
+        u = a + b;
+        d = a - b;
+      } else if (p < h1) {                   // odd n: middle level
+        u = in[(size_t)p * m + col];
+      }
+    }
+    U[p * LD + c] = (T)u;
+    D[p * LD + c] = (T)d;
+  }
+  __syncthreads();
+
+  // 2. [S_o u | S_e d], each result back to LDS once every wave is done reading its block
+  Acc acc[RPW][CT];
+  gemm_tiles<HP, C, PR>(So, U, wave, lane, acc);
+  __syncthreads();
+  store_acc<HP, C, PR>(acc, U, wave, lane);
+  gemm_tiles<HP, C, PR>(Se, D, wave, lane, acc);
+  __syncthreads();
+  store_acc<HP, C, PR>(acc, D, wave, lane);
+  __syncthreads();
+
+  if (MODE == 0) {
+    // y_{2p} (odd modes) and y_{2p+1} (even modes), 0-based rows
+    for (int e = tid; e < HP * C; e += 256) {
+      const int p = e / C, c = e - p * C, col = col0 + c;
+      if (col >= m) continue;
+      if (p < h1) out[(size_t)(2 * p) * m + col] = (double)U[p * LD + c];
+      if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (double)D[p * LD + c];
+    }
+    return;
+  }
+
+  // 3. scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
+  double g2 = 0.0;
+  for (int e = tid; e < HP * C; e += 256) {
+    const int p = e / C, c = e - p * C, col = col0 + c;
+    const bool okc = col < m;
+    const double tm = tp.tmu[okc ? col : m - 1];
+    double so = 0.0, se = 0.0;
+    if (okc && p < h1) {
+      const double a = (double)U[p * LD + c];
+      so = a * inv_sigma(tp, 2 * p, tm);
+      g2 += a * so;
+    }
+    if (okc && p < h2) {
+      const double a = (double)D[p * LD + c];
+      se = a * inv_sigma(tp, 2 * p + 1, tm);
+      g2 += a * se;
+    }
+    U[p * LD + c] = (T)so;
+    D[p * LD + c] = (T)se;
+  }
+  __syncthreads();
+
+  // 4. the transposed blocks
+  gemm_tiles<HP, C, PR>(SoT, U, wave, lane, acc);
+  __syncthreads();
+  store_acc<HP, C, PR>(acc, U, wave, lane);
+  gemm_tiles<HP, C, PR>(SeT, D, wave, lane, acc);
+  __syncthreads();
+  store_acc<HP, C, PR>(acc, D, wave, lane);
+  __syncthreads();
+
+  // 5. output butterfly z_p = u'_p + d'_p, z_{n-1-p} = u'_p - d'_p (odd n: middle row once)
+  for (int e = tid; e < HP * C; e += 256) {
+    const int p = e / C, c = e - p * C, col = col0 + c;
+    if (col >= m) continue;
+    const double a = (double)U[p * LD + c], b = (double)D[p * LD + c];
+    if (p < h2) {
+      out[(size_t)p * m + col] = a + b;
+      out[(size_t)(n - 1 - p) * m + col] = a - b;
+    } else if (p < h1) {
+      out[(size_t)p * m + col] = a;
+    }
+  }
+  if (part) {
+    const double s = block_sum256(g2, red);
+    if (tid == 0) part[blockIdx.x] = s;
+  }
+}
+
 template <int HP, int C, int PR>
 hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int mode, double *part, int *nb,
                     const Scal *gate) {
   const int blocks = (tp.m + C - 1) / C;
   if (nb) *nb = blocks;
-  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename TPrec<PR>::T);
-  if (shmem > 65536) {
-    (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
+  if constexpr (HP >= 256) {
+    if (shmem > 65536) {
+      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    }
+    if (mode == 0) hipLaunchKernelGGL((k_time<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+    else hipLaunchKernelGGL((k_time<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+  } else {
+    if (shmem > 65536) {
+      (void)hipFuncSetAttribute((const void *)k_time_pair<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem);
+      (void)hipFuncSetAttribute((const void *)k_time_pair<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem);
+    }
+    if (mode == 0)
+      hipLaunchKernelGGL((k_time_pair<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+    else
+      hipLaunchKernelGGL((k_time_pair<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
   }
-  if (mode == 0)
-    hipLaunchKernelGGL((k_time<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
-  else
-    hipLaunchKernelGGL((k_time<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
   return hipGetLastError();
 }
 
@@ -270,7 +370,7 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
 }  // namespace
 
 int time_blocks(const Plan *p) {
-  const int C = p->hp >= 256 ? 16 : 32;   // two blocks per CU: 2 * hp * (C + 1) doubles of LDS each
+  const int C = p->hp >= 256 ? 16 : 32;   // two blocks per CU: 2 * hp * (C + 1) values of LDS each
   return (p->m + C - 1) / C;
 }
 
