@@ -38,11 +38,16 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_spec_cn2d_N127_n256.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc", "k_spec.hip")
+KERNEL_HDR = os.path.join(os.path.dirname(KERNEL_SRC), "mfma_tiles.h")   # its matrix-core tiles
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the fused kernel's sources (the kernel file and its matrix-core tile header)."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, KERNEL_HDR):
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_entry():
