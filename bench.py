@@ -63,7 +63,7 @@ def traffic_entry():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(p, iters: int = 10):
+def cpu_baseline(p, iters: int = 40):
     """The FP64 CPU oracle timed on this host: the first `iters` MINRES iterations of
     the same workload (single thread: scipy.fft workers=1, scipy.sparse)."""
     from oracle.system import System
