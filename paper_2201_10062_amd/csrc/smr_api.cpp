@@ -777,20 +777,22 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
   int issued = 0;                   // launches j = 1..issued enqueued
   const int last = maxit + 2;       // launch maxit + 2 takes the stop decision on iteration maxit
   int pend[2], npend = 0, slot_next = 0;
-  // enqueue the next chunk and a snapshot of the state after it (pinned host copy + event)
-  auto enqueue_next = [&]() -> smr_status {
-    if (issued < 5 || !graph) {
-      const int todo = std::min(issued < 5 ? 5 - issued : 6, last - issued);
+  // enqueue up to `cap` launches (a captured chunk of six when aligned) and a snapshot of the
+  // state after them (pinned host copy + event)
+  auto enqueue_next = [&](int cap) -> smr_status {
+    const bool aligned = issued >= 5 && (issued + 1) % 6 == 0;
+    if (graph && aligned && cap >= 6 && last - issued >= 6) {
+      ProfScope ps(PROF_SPEC, s, 6);
+      HIP_TRY(hipGraphLaunch(p.steady6, s));
+      issued += 6;
+    } else {
+      const int todo = std::min(std::min(cap, issued < 5 ? 5 - issued : 6), last - issued);
       for (int it = 0; it < todo; ++it) {
         const int j = issued + it + 1;
         if (ext) LAUNCH(PROF_KSLICE, launch_kslice(c, 1, j, Xh, Bh));
         LAUNCH(PROF_SPEC, launch_spec(c, j == 1 ? 1 : 2, j, Xh, Bh));
       }
       issued += todo;
-    } else {                        // issued + 1 is a multiple of 6 here
-      ProfScope ps(PROF_SPEC, s, 6);
-      HIP_TRY(hipGraphLaunch(p.steady6, s));
-      issued += 6;
     }
     HIP_TRY(hipMemcpyAsync(&p.snap[slot_next], p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(p.snap_ev[slot_next], s));
@@ -798,13 +800,35 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
     slot_next ^= 1;
     return SMR_OK;
   };
+  // Stop prediction: the true residuals evaluated so far (the snapshot's relres whenever the
+  // count of evaluated residuals grew) decay at a rate per iteration; once two are known the
+  // host enqueues only the launches up to the predicted stop (one spare) instead of whole
+  // chunks, so that few launches run past convergence.  A wrong prediction costs one host
+  // round trip, never a result: the device takes the stop decision itself.
+  int obs_it[2] = {-1, -1}, seen_nres = 0, spent = 1 << 30;
+  double obs_r[2] = {0.0, 0.0};
+  auto predicted_cap = [&]() -> int {
+    if (issued >= spent) return 6;                       // a prediction fell short: whole chunks again
+    if (obs_it[0] < 0 || obs_it[1] <= obs_it[0] || !(obs_r[1] > 0.0) || !(obs_r[0] > obs_r[1])) return 6;
+    const double rho = std::pow(obs_r[1] / obs_r[0], 1.0 / (obs_it[1] - obs_it[0]));
+    if (!(rho > 0.0 && rho < 1.0)) return 6;
+    const double more = obs_r[1] <= rtol ? 0.0 : std::ceil(std::log(rtol / obs_r[1]) / std::log(rho));
+    if (!(more < 1e6)) return 6;
+    const int reach = obs_it[1] + (int)more + 2 + 2;    // launch stop + 2 decides; two spare
+    spent = std::min(spent, reach);
+    return std::max(0, std::min(6, reach - issued));
+  };
   // keep one chunk in flight ahead of the status being checked, so the device never waits
-  st = enqueue_next();
+  st = enqueue_next(6);
   if (st != SMR_OK) return st;
   for (;;) {
     if (issued < last && npend < 2) {
-      st = enqueue_next();
-      if (st != SMR_OK) return st;
+      int cap = predicted_cap();
+      if (npend == 0) cap = std::max(cap, 1);          // the solve is still running
+      if (cap > 0) {
+        st = enqueue_next(cap);
+        if (st != SMR_OK) return st;
+      }
     }
     const int slot = pend[0];
     pend[0] = pend[1];
@@ -813,6 +837,13 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
     h = p.snap[slot];
     if (h.status != RUNNING) break;
     if (npend == 0 && issued >= last) break;
+    if (h.nres > seen_nres) {                           // a new true residual
+      obs_it[0] = obs_it[1];
+      obs_r[0] = obs_r[1];
+      obs_it[1] = h.nres == 1 ? 0 : h.iter;
+      obs_r[1] = h.relres;
+      seen_nres = h.nres;
+    }
   }
   // launches after the decision pass the state on: the latest slot holds the final state
   HIP_TRY(hipMemcpyAsync(&h, p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
