@@ -452,13 +452,14 @@ namespace {
 
 // One spatial DST-I pass over a 2D field (N + 1 = 32 R): along x (DIR 0, rows) or y (DIR 1,
 // columns) of every time slice.  A block owns up to kTL lines of one slice, loads them
-// coalesced into LDS (rows: contiguous; columns: kTL neighbours per row), every wave runs line
-// pairs through the register FFT, and the block stores them back (all loads finish before any
-// store, so in == out is allowed).  scale_mode 1 divides by the Chebyshev inner diagonal
+// coalesced into LDS (rows: contiguous; columns: kTL neighbours per row), every wave takes a
+// line pair through the register FFT, and the block stores them back (all loads finish before
+// any store, so in == out is allowed).  Small tiles keep many blocks per CU, so that some
+// stream while others transform (measured at N = 255: 8 lines per 256-thread block beat 16 and
+// 32 lines, and 128-thread blocks).  scale_mode 1 divides by the Chebyshev inner diagonal
 // ez[s] + ez[n + s] abar tmu_lap[q].
-constexpr int kTL = 32;
-constexpr int kTT = 256;    // threads of a tile block: two blocks share a CU, one loads or stores
-                            // while the other transforms
+constexpr int kTL = 8;
+constexpr int kTT = 256;    // threads of a tile block: one line pair per wave
 struct TileP {
   int N, n, tiles;            // tiles per slice
   long sin, sout;
