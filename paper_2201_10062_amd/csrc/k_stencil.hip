@@ -6,6 +6,7 @@
 // block later adds the partials in a fixed order.
 #include "smr_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace smr {
@@ -121,31 +122,76 @@ __device__ __forceinline__ bool tile_point(int t, int ni, int nj, int N, int dim
 
 // MODE 0: y = Y T (xs x), partial <y, xs x>.   MODE 1: r = Y rhs - Y T x (written to y
 // if y != null), partials ||r||^2 (slot 0) and ||rhs||^2 (slot 1).
+// A block owns a spatial tile (64 x 4 points in 2D, 256 in 1D) and a run of kr time levels;
+// each thread marches up its run keeping the previous levels and K x_{k-1} in registers, so
+// that one 5-point stencil per level serves both terms of the theta scheme (K is linear).
+struct MarchP {
+  int ni, nj, nkc, kr;        // spatial tiles per axis, time runs, levels per run
+};
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_apply_YT(SP s, TileInfo ti, const double *__restrict__ x,
+__global__ __launch_bounds__(256) void k_apply_YT(SP s, MarchP mp, const double *__restrict__ x,
                                                   const double *__restrict__ d_xscale, double *__restrict__ y,
                                                   const double *__restrict__ rhs, double *__restrict__ part,
                                                   const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   __shared__ double red[16];
   const double xs = d_xscale ? *d_xscale : 1.0;
+  const int N = s.N, m = s.m;
+  const int b = blockIdx.x;
+  const int it = b % mp.ni, jt = (b / mp.ni) % mp.nj, kc = b / (mp.ni * mp.nj);
+  const int i = s.dim == 1 ? it * kT1 + threadIdx.x : it * kTX + threadIdx.x;
+  const int j = s.dim == 1 ? 0 : jt * kTY + threadIdx.y;
+  const bool ok = i < N && j < (s.dim == 1 ? 1 : N);
+  const int k0 = kc * mp.kr, k1 = min(s.n, k0 + mp.kr);
   double acc0 = 0.0, acc1 = 0.0;
-  for (int t = blockIdx.x; t < ti.ntiles; t += gridDim.x) {
-    int k, j, i;
-    if (!tile_point(t, ti.ni, ti.nj, s.N, s.dim, k, j, i)) continue;
-    const int q = (s.dim == 1) ? i : j * s.N + i;
-    const size_t o = (size_t)(s.n - 1 - k) * s.m + q;   // Y: time level k lands at n-1-k
-    const double tv = Tapply(s, x, k, j, i);
-    if (MODE == 0) {
-      const double val = xs * tv;
-      if (y) y[o] = val;
-      acc0 += val * (xs * x[o]);
+  if (ok) {
+    const int q = s.dim == 1 ? i : j * N + i;
+    // neighbour offsets (0 = outside: the Dirichlet value 0) and face coefficients
+    const bool hw = i > 0, he = i < N - 1, hs = s.dim == 2 && j > 0, hn = s.dim == 2 && j < N - 1;
+    double aw, ae, as = 0.0, an = 0.0;
+    if (s.dim == 1) {
+      aw = s.ax[i];
+      ae = s.ax[i + 1];
     } else {
-      const double bk = rhs[(size_t)k * s.m + q];
-      const double r = bk - tv;
-      if (y) y[o] = r;
-      acc0 += r * r;
-      acc1 += bk * bk;
+      aw = s.ax[j * (N + 1) + i];
+      ae = s.ax[j * (N + 1) + i + 1];
+      as = s.ay[j * N + i];
+      an = s.ay[(j + 1) * N + i];
+    }
+    auto kx = [&](const double *xl, double &c) {   // c = x_l at q, returns (K x_l) at q
+      c = xl[q];
+      const double uw = hw ? xl[q - 1] : 0.0, ue = he ? xl[q + 1] : 0.0;
+      const double us = hs ? xl[q - N] : 0.0, un = hn ? xl[q + N] : 0.0;
+      return s.h2inv * (aw * (c - uw) + ae * (c - ue) + as * (c - us) + an * (c - un));
+    };
+    double x1 = 0.0, x2 = 0.0, kx1 = 0.0;           // x_{k-1}, x_{k-2}, (K x)_{k-1}
+    if (k0 >= 1) {
+      if (s.scheme == SMR_THETA) kx1 = kx(x + (size_t)(k0 - 1) * m, x1);
+      else x1 = x[(size_t)(k0 - 1) * m + q];
+    }
+    if (k0 >= 2 && s.scheme != SMR_THETA) x2 = x[(size_t)(k0 - 2) * m + q];
+    for (int k = k0; k < k1; ++k) {
+      double x0;
+      const double kx0 = kx(x + (size_t)k * m, x0);
+      double tv;
+      if (s.scheme == SMR_THETA) tv = x0 - x1 + s.tau * (s.theta * kx0 + (1.0 - s.theta) * kx1);
+      else tv = 1.5 * x0 - 2.0 * x1 + 0.5 * x2 + s.tau * kx0;
+      const size_t o = (size_t)(s.n - 1 - k) * m + q;   // Y: time level k lands at n-1-k
+      if (MODE == 0) {
+        const double val = xs * tv;
+        if (y) y[o] = val;
+        acc0 += val * (xs * x[o]);
+      } else {
+        const double bk = rhs[(size_t)k * m + q];
+        const double r = bk - tv;
+        if (y) y[o] = r;
+        acc0 += r * r;
+        acc1 += bk * bk;
+      }
+      x2 = x1;
+      x1 = x0;
+      kx1 = kx0;
     }
   }
   if (part) {
@@ -428,13 +474,20 @@ inline int grid_for(size_t work, int per_block) {
 hipError_t launch_apply_YT(Ctx c, const double *x, const double *d_xscale, double *y, const double *rhs,
                            double *part, int *nblocks_out, const Scal *gate) {
   const Plan *p = c.p;
-  TileInfo ti = tiles_of(p, p->n);
-  const int g = ti.ntiles < kRedSlots ? ti.ntiles : kRedSlots;
+  const TileInfo ti = tiles_of(p, 1);               // spatial tiles of one level
+  MarchP mp{ti.ni, ti.nj, 1, p->n};
+  // runs of >= 16 levels, as many as the partial-sum slots allow
+  const int maxrun = kRedSlots / ti.ntiles > 0 ? kRedSlots / ti.ntiles : 1;
+  mp.nkc = std::max(1, std::min((p->n + 15) / 16, maxrun));
+  mp.kr = (p->n + mp.nkc - 1) / mp.nkc;
+  mp.nkc = (p->n + mp.kr - 1) / mp.kr;
+  const int g = ti.ntiles * mp.nkc;
+  if (g > kRedSlots) return hipErrorInvalidValue;   // more spatial tiles than partial-sum slots
   if (nblocks_out) *nblocks_out = g;
   if (rhs)
-    hipLaunchKernelGGL(k_apply_YT<1>, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, x, d_xscale, y, rhs, part, gate);
+    hipLaunchKernelGGL(k_apply_YT<1>, dim3(g), block_of(p), 0, c.st, make_sp(p), mp, x, d_xscale, y, rhs, part, gate);
   else
-    hipLaunchKernelGGL(k_apply_YT<0>, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, x, d_xscale, y, rhs, part, gate);
+    hipLaunchKernelGGL(k_apply_YT<0>, dim3(g), block_of(p), 0, c.st, make_sp(p), mp, x, d_xscale, y, rhs, part, gate);
   return hipGetLastError();
 }
 
