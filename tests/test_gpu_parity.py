@@ -68,6 +68,8 @@ OPS = [
     (2, 1, 3, "theta", 0.5, "var"),
     (2, 255, 4, "theta", 1.0, "var"),
     (2, 255, 3, "bdf2", 1.0, "smooth"),
+    (2, 15, 300, "bdf2", 1.0, "var"),       # hp = 256: one folded block per pass
+    (2, 7, 600, "theta", 0.5, "var"),       # hp = 512
 ]
 
 
@@ -88,7 +90,8 @@ def test_apply_P_inv_parity(dim, N, n, scheme, theta, kind):
 
 
 @pytest.mark.parametrize("dim,N,n,theta,k", [(2, 15, 12, 1.0, 1), (2, 31, 9, 0.5, 3), (1, 31, 16, 1.0, 4),
-                                             (2, 7, 6, 1.0, 2), (2, 127, 5, 1.0, 2), (2, 255, 3, 1.0, 2)])
+                                             (2, 7, 6, 1.0, 2), (2, 127, 5, 1.0, 2), (2, 255, 3, 1.0, 2),
+                                             (2, 15, 300, 1.0, 2)])
 def test_apply_P_theta_cheb_parity(dim, N, n, theta, k):
     g, o = _pair(dim, N, n, "theta", theta, precond="PTHETA_CHEB", kind="var", cheb_k=k)
     v = np.random.default_rng(3).standard_normal(n * g.m)
@@ -303,7 +306,7 @@ def test_mixed_fp32_solve(dim, N, n, scheme, theta):
     assert rel(x, _n(x64)) > 1e-13
 
 
-@pytest.mark.parametrize("case", ["var-N15", "ptheta", "general-const", "1d-var"])
+@pytest.mark.parametrize("case", ["var-N15", "ptheta", "general-const", "1d-var", "hp256-var"])
 def test_mixed_fp32_physical_basis(case):
     """Float32 time transforms on the physical-basis path (variable a with N + 1 outside
     {32, 64, 128}, P_theta, the forced general path, 1D variable a): the float64 true residual
@@ -315,6 +318,7 @@ def test_mixed_fp32_physical_basis(case):
         "ptheta": (2, 15, 24, 1.0, "PTHETA_CHEB", "smooth", False),
         "general-const": (2, 31, 32, 0.5, "PH", "const", True),
         "1d-var": (1, 63, 64, 1.0, "PH", "var", False),
+    "hp256-var": (2, 15, 300, 1.0, "PH", "var", False),
     }[case]
     ax, ay = _faces(kind, N, dim)
     kw = dict(scheme="theta", theta=theta, precond=precond, cheb_k=3, ax=ax, ay=ay, general_path=general)
