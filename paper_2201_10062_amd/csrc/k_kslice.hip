@@ -21,6 +21,7 @@
 // (S b)_k = Re Z_{k+1} / sqrt(2L).
 #include "smr_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace smr {
@@ -455,9 +456,8 @@ namespace {
 // coalesced into LDS (rows: contiguous; columns: kTL neighbours per row), every wave takes a
 // line pair through the register FFT, and the block stores them back (all loads finish before
 // any store, so in == out is allowed).  Small tiles keep many blocks per CU, so that some
-// stream while others transform (measured at N = 255: 8 lines per 256-thread block beat 16 and
-// 32 lines, and 128-thread blocks).  scale_mode 1 divides by the Chebyshev inner diagonal
-// ez[s] + ez[n + s] abar tmu_lap[q].
+// stream while others transform.  N + 1 = 256 runs the persistent variant further down.
+// scale_mode 1 divides by the Chebyshev inner diagonal ez[s] + ez[n + s] abar tmu_lap[q].
 constexpr int kTL = 8;
 constexpr int kTT = 256;    // threads of a tile block: one line pair per wave
 struct TileP {
@@ -468,6 +468,16 @@ struct TileP {
   int scale_mode;
 };
 
+// Workgroups go to the 8 XCDs round-robin in block order; give each XCD a contiguous range of
+// tiles instead, so that the tiles sharing cache lines (column tiles of one slice) meet in the
+// same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  constexpr int kXcd = 8;
+  const int x = bid % kXcd, local = bid / kXcd;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 template <int R, int DIR>
 __global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restrict__ in, double *__restrict__ out,
                                                   const Scal *__restrict__ gate) {
@@ -476,7 +486,8 @@ __global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restr
   constexpr int N = 32 * R - 1;
   constexpr int LP = DIR == 0 ? N + 2 : kTL + 1;   // LDS pitch of a line (DIR 0) or a position (DIR 1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int s = blockIdx.x / d.tiles, i0 = (blockIdx.x - s * d.tiles) * kTL;
+  const int bid = xcd_block(blockIdx.x, gridDim.x);
+  const int s = bid / d.tiles, i0 = (bid - s * d.tiles) * kTL;
   const int nl = min(kTL, N - i0);
   const double *src = in + (size_t)s * d.sin;
   double *dst = out + (size_t)s * d.sout;
@@ -516,19 +527,184 @@ __global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restr
   }
 }
 
+// N + 1 = 256 (M = 512): the line pair's DFT regroups its values through LDS instead of six
+// cross-lane exchange stages.  With n = 64 n1 + n2 (n2 = lane) and k = k1 + 8 k2, an in-lane
+// 8-point DFT over n1 and the twiddle W_512^{n2 k1} leave a 64-point DFT over n2 for every k1;
+// it is split as n2 = 8 a + b, k2 = c + 8 d into an 8-point DFT over a, the twiddle
+// W_64^{b c} and an 8-point DFT over b, each done in-lane after the values are regrouped in
+// LDS (real parts, then imaginary parts).  On return lane 8 k1 + c holds Z[k1 + 8 c + 64 d]
+// in v[d].  T: this wave's 8 rows of kTP doubles; every wave of the block must call it.
+constexpr int kTP = 72;    // row pitch of the regrouping buffer (64 values + one pad per 8)
+__device__ __forceinline__ void pair_dft512(double2 (&v)[8], int lane, const double2 (&wa)[7],
+                                            const double2 (&wb)[7], double *T) {
+  lane_dft8(v);                                                   // over n1 -> k1
+#pragma unroll
+  for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], wa[k1 - 1]);   // W_512^{n2 k1}
+  const int rk = lane >> 3, rb = lane & 7;                          // reader: k1, b
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {     // lane n2 writes row k1 at n2 + n2 / 8
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) T[k1 * kTP + lane + (lane >> 3)] = part == 0 ? v[k1].x : v[k1].y;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double t = T[rk * kTP + 9 * a + rb];                  // n2 = 8 a + b
+      if (part == 0) v[a].x = t; else v[a].y = t;
+    }
+    __syncthreads();
+  }
+  lane_dft8(v);                                                   // over a -> c
+#pragma unroll
+  for (int c = 1; c < 8; ++c) v[c] = cmul(v[c], wb[c - 1]);        // W_64^{b c}
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {     // lane (k1, b) writes row k1 at 9 c + b
+#pragma unroll
+    for (int c = 0; c < 8; ++c) T[rk * kTP + 9 * c + rb] = part == 0 ? v[c].x : v[c].y;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {                                 // reader: k1, c = lane % 8
+      const double t = T[rk * kTP + 9 * rb + b];
+      if (part == 0) v[b].x = t; else v[b].y = t;
+    }
+    __syncthreads();
+  }
+  lane_dft8(v);                                                   // over b -> d
+}
+
+// One DST-I pass for N + 1 = 256.  Persistent blocks walk the tiles of an XCD-contiguous
+// range, holding the next tile's loads in registers while the current tile is transformed
+// (loads of one tile and stores of another touch different lines, so in == out is allowed);
+// the regrouping buffers alias the tile once the line pairs are in registers.
+constexpr int kLds512 = 4 * 8 * kTP;   // doubles: >= one tile in either direction (2056, 2295)
+template <int DIR>
+__global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__restrict__ in,
+                                                     double *__restrict__ out, const Scal *__restrict__ gate,
+                                                     int total) {
+  if (gate && gate->status != RUNNING) return;
+  __shared__ double X[kLds512];
+  constexpr int N = 255, M = 512, L = 256, TL = kTL, TILES = (N + TL - 1) / TL;
+  constexpr int LP = DIR == 0 ? N + 2 : TL + 1;
+  constexpr int PF = (TL * N + kTT - 1) / kTT;
+  static_assert(TL == 2 * (kTT / 64), "one line pair per wave");
+  static_assert((DIR == 0 ? TL * LP : N * LP) <= kLds512, "the tile fits");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *T = X + wave * 8 * kTP;
+  const int xcd = blockIdx.x % 8, nbx = gridDim.x / 8;
+  const int per = (total + 7) / 8, tend = min(total, (xcd + 1) * per);
+  const double2 *tw = reinterpret_cast<const double2 *>(d.tw);
+  double2 wa[7], wb[7];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    wa[k - 1] = twid(tw, lane * k, M);
+    wb[k - 1] = twid(tw, 8 * (lane & 7) * k, M);
+  }
+  auto at = [&](int line, int pos) { return DIR == 0 ? line * LP + pos : pos * LP + line; };
+  double pre[PF];
+  auto load = [&](int t) {
+    const int s = t / TILES, i0 = (t - s * TILES) * TL, nl = min(TL, N - i0);
+    const double *src = in + (size_t)s * d.sin;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * kTT;
+      if (DIR == 0) {
+        pre[k] = e < nl * N ? src[(size_t)i0 * N + e] : 0.0;       // rows i0.. are contiguous
+      } else {
+        const int j = e / TL, c = e - j * TL;
+        pre[k] = (e < TL * N && c < nl) ? src[(size_t)j * N + i0 + c] : 0.0;
+      }
+    }
+  };
+  int t = xcd * per + blockIdx.x / 8;
+  if (t < tend) load(t);
+  for (; t < tend; t += nbx) {
+    const int s = t / TILES, i0 = (t - s * TILES) * TL, nl = min(TL, N - i0);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * kTT;
+      if (DIR == 0) {
+        if (e < nl * N) {
+          const int c = e / N, j = e - c * N;
+          X[c * LP + j] = pre[k];
+        }
+      } else if (e < TL * N) {
+        const int j = e / TL, c = e - j * TL;
+        X[j * LP + c] = pre[k];
+      }
+    }
+    __syncthreads();
+    if (t + nbx < tend) load(t + nbx);
+    // the wave's line pair, oddly extended to M points (lines past nl read as zero)
+    const int la = min(2 * wave, nl - 1), lb = min(2 * wave + 1, nl - 1);
+    const bool oka = 2 * wave < nl, okb = 2 * wave + 1 < nl;
+    double2 v[8];
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1) {
+      const int jn = 64 * j1 + lane;
+      const bool lo = jn >= 1 && jn <= N, hi = jn > L;
+      const int sp = lo ? jn - 1 : hi ? M - jn - 1 : 0;
+      const double sg = lo ? 1.0 : hi ? -1.0 : 0.0;
+      v[j1] = make_double2(oka ? sg * X[at(la, sp)] : 0.0, okb ? sg * X[at(lb, sp)] : 0.0);
+    }
+    __syncthreads();
+    pair_dft512(v, lane, wa, wb, T);
+    __syncthreads();
+    // (S a)_k = -Im Z_{k+1} / sqrt(2L), (S b)_k = Re Z_{k+1} / sqrt(2L); k + 1 < 256 needs d < 4
+    const int k1 = lane >> 3, c = lane & 7;
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+      const int K = k1 + 8 * c + 64 * dd;
+      if (K >= 1) {
+        if (oka) X[at(la, K - 1)] = -v[dd].y * d.scale;
+        if (okb) X[at(lb, K - 1)] = v[dd].x * d.scale;
+      }
+    }
+    __syncthreads();
+    double *dst = out + (size_t)s * d.sout;
+    auto fin = [&](double x, size_t q) {
+      return d.scale_mode == 1 ? x / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : x;
+    };
+    if (DIR == 0) {
+      for (int e = tid; e < nl * N; e += kTT) {
+        const int c2 = e / N, j = e - c2 * N;
+        const size_t q = (size_t)i0 * N + e;
+        dst[q] = fin(X[c2 * LP + j], q);
+      }
+    } else {
+      for (int e = tid; e < TL * N; e += kTT) {
+        const int j = e / TL, c2 = e - j * TL;
+        if (c2 < nl) {
+          const size_t q = (size_t)j * N + i0 + c2;
+          dst[q] = fin(X[j * LP + c2], q);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// resident blocks of the persistent pass (LDS allows 8 per CU); measured at N = 255, n = 512
+constexpr int kGrid512[2] = {2048, 4096};
+
 template <int R>
 hipError_t run_dst_tile(hipStream_t st, int dir, const TileP &d, int nslices, const double *in, double *out,
                         const Scal *gate) {
-  constexpr int N = 32 * R - 1;
-  const size_t sh = (size_t)(dir == 0 ? kTL * (N + 2) : N * (kTL + 1)) * sizeof(double);
-  const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0> : (const void *)k_dst_tile<R, 1>;
-  if (sh > 65536) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (e != hipSuccess) return e;
+  if constexpr (R == 8) {
+    const long total = (long)nslices * d.tiles;
+    const int grid = (int)std::min<long>(kGrid512[dir], (total + 7) / 8 * 8);
+    if (dir == 0) hipLaunchKernelGGL(k_dst_tile512<0>, dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
+    else hipLaunchKernelGGL(k_dst_tile512<1>, dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
+  } else {
+    constexpr int N = 32 * R - 1;
+    const size_t sh = (size_t)(dir == 0 ? kTL * (N + 2) : N * (kTL + 1)) * sizeof(double);
+    const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0> : (const void *)k_dst_tile<R, 1>;
+    if (sh > 65536) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      if (e != hipSuccess) return e;
+    }
+    const unsigned blocks = (unsigned)((long)nslices * d.tiles);
+    if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
+    else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
   }
-  const unsigned blocks = (unsigned)((long)nslices * d.tiles);
-  if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
-  else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
   return hipGetLastError();
 }
 
