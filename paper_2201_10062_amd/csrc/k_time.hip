@@ -37,14 +37,16 @@ __device__ __forceinline__ double inv_sigma(const TimeP &tp, int tmode, double t
   return 1.0 / sqrt(re * re + im * im);
 }
 
-__device__ __forceinline__ double block_sum256(double v, double *red) {
+// sum over the NWV waves of the block, in a fixed order; valid in thread 0
+template <int NWV>
+__device__ __forceinline__ double block_sum(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < 4; ++w) s += red[w];
+    for (int w = 0; w < NWV; ++w) s += red[w];
   return s;
 }
 
@@ -209,25 +211,28 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
     }
   }
   if (part) {
-    const double s = block_sum256(g2, red);
+    const double s = block_sum<4>(g2, red);
     if (tid == 0) part[blockIdx.x] = s;
   }
 }
 
 // hp >= 256: one folded block per pass (fewer live accumulators), results through LDS.
-// One block: C columns, all n levels; four waves, all on the matrix cores.
-template <int HP, int C, int MODE, int PR>
-__global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
-                                              double *__restrict__ part, const Scal *__restrict__ gate) {
+// One block: C columns, all n levels; NW waves, all on the matrix cores (eight, so that a
+// CU holding a single block of the largest tiles still runs two waves per SIMD).
+template <int HP, int C, int MODE, int PR, int NW>
+__global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__restrict__ in,
+                                                  double *__restrict__ out, double *__restrict__ part,
+                                                  const Scal *__restrict__ gate) {
   typedef typename Prec<PR>::T T;
   typedef typename Prec<PR>::Acc Acc;
   if (gate && gate->status != RUNNING) return;
+  constexpr int NT = 64 * NW;
   constexpr int LD = C + 1;                   // LDS pitch
-  constexpr int RPW = (HP / 16 + 3) / 4, CT = C / 16;
+  constexpr int RPW = (HP / 16 + NW - 1) / NW, CT = C / 16;
   extern __shared__ double lds_raw[];
   T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
   T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
-  __shared__ double red[4];
+  __shared__ double red[NW];
   const T *So = reinterpret_cast<const T *>(tp.So), *Se = reinterpret_cast<const T *>(tp.Se);
   const T *SoT = reinterpret_cast<const T *>(tp.SoT), *SeT = reinterpret_cast<const T *>(tp.SeT);
 
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
   const int n = tp.n, m = tp.m, h1 = tp.h1, h2 = tp.h2;
 
   // 1. butterfly load (zero padding rows and columns beyond m)
-  for (int e = tid; e < HP * C; e += 256) {
+  for (int e = tid; e < HP * C; e += NT) {
     const int p = e / C, c = e - p * C;
     const int col = col0 + c;
     double u = 0.0, d = 0.0;
@@ -256,17 +261,17 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
 
   // 2. [S_o u | S_e d], each result back to LDS once every wave is done reading its block
   Acc acc[RPW][CT];
-  gemm_tiles<HP, C, PR>(So, U, wave, lane, acc);
+  gemm_tiles<HP, C, PR, NW>(So, U, wave, lane, acc);
   __syncthreads();
-  store_acc<HP, C, PR>(acc, U, wave, lane);
-  gemm_tiles<HP, C, PR>(Se, D, wave, lane, acc);
+  store_acc<HP, C, PR, NW>(acc, U, wave, lane);
+  gemm_tiles<HP, C, PR, NW>(Se, D, wave, lane, acc);
   __syncthreads();
-  store_acc<HP, C, PR>(acc, D, wave, lane);
+  store_acc<HP, C, PR, NW>(acc, D, wave, lane);
   __syncthreads();
 
   if (MODE == 0) {
     // y_{2p} (odd modes) and y_{2p+1} (even modes), 0-based rows
-    for (int e = tid; e < HP * C; e += 256) {
+    for (int e = tid; e < HP * C; e += NT) {
       const int p = e / C, c = e - p * C, col = col0 + c;
       if (col >= m) continue;
       if (p < h1) out[(size_t)(2 * p) * m + col] = (double)U[p * LD + c];
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
 
   // 3. scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
   double g2 = 0.0;
-  for (int e = tid; e < HP * C; e += 256) {
+  for (int e = tid; e < HP * C; e += NT) {
     const int p = e / C, c = e - p * C, col = col0 + c;
     const bool okc = col < m;
     const double tm = tp.tmu[okc ? col : m - 1];
@@ -298,16 +303,16 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
   __syncthreads();
 
   // 4. the transposed blocks
-  gemm_tiles<HP, C, PR>(SoT, U, wave, lane, acc);
+  gemm_tiles<HP, C, PR, NW>(SoT, U, wave, lane, acc);
   __syncthreads();
-  store_acc<HP, C, PR>(acc, U, wave, lane);
-  gemm_tiles<HP, C, PR>(SeT, D, wave, lane, acc);
+  store_acc<HP, C, PR, NW>(acc, U, wave, lane);
+  gemm_tiles<HP, C, PR, NW>(SeT, D, wave, lane, acc);
   __syncthreads();
-  store_acc<HP, C, PR>(acc, D, wave, lane);
+  store_acc<HP, C, PR, NW>(acc, D, wave, lane);
   __syncthreads();
 
   // 5. output butterfly z_p = u'_p + d'_p, z_{n-1-p} = u'_p - d'_p (odd n: middle row once)
-  for (int e = tid; e < HP * C; e += 256) {
+  for (int e = tid; e < HP * C; e += NT) {
     const int p = e / C, c = e - p * C, col = col0 + c;
     if (col >= m) continue;
     const double a = (double)U[p * LD + c], b = (double)D[p * LD + c];
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(256) void k_time(TimeP tp, const double *__restrict
     }
   }
   if (part) {
-    const double s = block_sum256(g2, red);
+    const double s = block_sum<NW>(g2, red);
     if (tid == 0) part[blockIdx.x] = s;
   }
 }
@@ -331,12 +336,17 @@ hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int m
   if (nb) *nb = blocks;
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if constexpr (HP >= 256) {
+    constexpr int NW = 8;
     if (shmem > 65536) {
-      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem);
+      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem);
     }
-    if (mode == 0) hipLaunchKernelGGL((k_time<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
-    else hipLaunchKernelGGL((k_time<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_time<HP, C, 0, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
+    else
+      hipLaunchKernelGGL((k_time<HP, C, 1, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
   } else {
     if (shmem > 65536) {
       (void)hipFuncSetAttribute((const void *)k_time_pair<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -360,7 +370,7 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
     case 32: return run_time<32, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 64: return run_time<64, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 128: return run_time<128, 32, PR>(c, tp, in, out, mode, part, nb, gate);
-    case 256: return run_time<256, 16, PR>(c, tp, in, out, mode, part, nb, gate);
+    case 256: return run_time<256, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 512: return run_time<512, 16, PR>(c, tp, in, out, mode, part, nb, gate);
     default: break;
   }
@@ -368,11 +378,6 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
 }
 
 }  // namespace
-
-int time_blocks(const Plan *p) {
-  const int C = p->hp >= 256 ? 16 : 32;   // two blocks per CU: 2 * hp * (C + 1) values of LDS each
-  return (p->m + C - 1) / C;
-}
 
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nb, const Scal *gate,
                        bool f32) {

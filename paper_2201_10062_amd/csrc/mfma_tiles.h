@@ -1,7 +1,7 @@
 // Matrix-core tiles of the folded time-axis sine transform (gfx950), shared by the fused
 // sine-basis kernel and the physical-basis time transform.  A block holds C columns of a
-// butterflied half (HP rows, LDS pitch C + 1); the four matrix-core waves (wave 0..3) each own
-// the 16-row tiles r = wave + 4 i, and one pass multiplies the block by one folded sine table.
+// butterflied half (HP rows, LDS pitch C + 1); the NW matrix-core waves (wave 0..NW-1) each own
+// the 16-row tiles r = wave + NW i, and one pass multiplies the block by one folded sine table.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,18 +35,18 @@ template <> struct Prec<1> {
   static __device__ __forceinline__ int row(int q, int bk) { return 4 * bk + q; }
 };
 
-// GEMM of the four matrix-core waves: for the 16-row tiles r = wave + 4 i (i < RPW) and all
+// GEMM of the NW matrix-core waves: for the 16-row tiles r = wave + NW i (i < RPW) and all
 // CT column tiles, acc[i][ct] += A[r] * B[:, ct] over the k dimension, with B the LDS block.
 // One A fragment feeds CT MFMAs.  The tables hold the fragments of k-steps 2q and 2q+1 side
 // by side per lane, so one load fetches two k-steps; loads run two such pairs ahead.
-template <int HP, int C, int PR>
+template <int HP, int C, int PR, int NW = 4>
 __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restrict__ A,
                                            const typename Prec<PR>::T *Bs, int wave, int lane,
-                                           typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16]) {
+                                           typename Prec<PR>::Acc (&acc)[(HP / 16 + NW - 1) / NW][C / 16]) {
   typedef typename Prec<PR>::T T;
   typedef typename std::conditional<PR == 0, double2, float2>::type T2;
   constexpr int LD = C + 1;
-  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
+  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + NW - 1) / NW;
   constexpr int KS = HP / 4, KP = KS / 2;         // k-steps, k-step pairs
   const int bk = lane >> 4, bj = lane & 15;
   const T2 *__restrict__ A2 = reinterpret_cast<const T2 *>(A);
@@ -59,7 +59,7 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
   T2 q0[RPW], qn[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
+    const int r = wave + NW * i;
     q0[i] = r < RT ? A2[(size_t)r * KP * 64 + lane] : zero2;
     qn[i] = (r < RT && 1 < KP) ? A2[((size_t)r * KP + 1) * 64 + lane] : zero2;
   }
@@ -67,7 +67,7 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
     T2 q1[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-      const int r = wave + 4 * i;
+      const int r = wave + NW * i;
       q1[i] = qn[i];
       qn[i] = (r < RT && kp + 2 < KP) ? A2[((size_t)r * KP + kp + 2) * 64 + lane] : zero2;
     }
@@ -79,7 +79,7 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
       for (int ct = 0; ct < CT; ++ct) b[ct] = Bs[(4 * kk + bk) * LD + 16 * ct + bj];
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        if (wave + 4 * i < RT) {
+        if (wave + NW * i < RT) {
           const T a = h ? q0[i].y : q0[i].x;
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) acc[i][ct] = Prec<PR>::mfma(a, b[ct], acc[i][ct]);
@@ -91,17 +91,17 @@ __device__ __forceinline__ void gemm_tiles(const typename Prec<PR>::T *__restric
   }
 }
 
-// Accumulator tiles of the four matrix-core waves -> LDS rows, in the accumulator layout of
+// Accumulator tiles of the NW matrix-core waves -> LDS rows, in the accumulator layout of
 // the transform's precision.
-template <int HP, int C, int PR>
-__device__ __forceinline__ void store_acc(const typename Prec<PR>::Acc (&acc)[(HP / 16 + 3) / 4][C / 16],
+template <int HP, int C, int PR, int NW = 4>
+__device__ __forceinline__ void store_acc(const typename Prec<PR>::Acc (&acc)[(HP / 16 + NW - 1) / NW][C / 16],
                                           typename Prec<PR>::T *Dst, int wave, int lane) {
   constexpr int LD = C + 1;
-  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + 3) / 4;
+  constexpr int RT = HP / 16, CT = C / 16, RPW = (RT + NW - 1) / NW;
   const int bk = lane >> 4, bj = lane & 15;
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
+    const int r = wave + NW * i;
     if (r >= RT) continue;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {

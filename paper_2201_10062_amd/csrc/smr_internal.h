@@ -102,7 +102,6 @@ hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices
 // float32 matrix cores with the plan's float32 sine tables (pprec SMR_FP32 plans only).
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nblocks_out,
                        const Scal *gate, bool f32 = false);
-int time_blocks(const Plan *p);
 
 // Elementwise / reductions / scalar steps.
 hipError_t launch_vupdate(Ctx c, const double *q, const double *v, double *vold_inout, const Scal *gate);
