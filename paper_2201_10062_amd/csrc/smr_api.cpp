@@ -845,9 +845,8 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
       seen_nres = h.nres;
     }
   }
-  // launches after the decision pass the state on: the latest slot holds the final state
-  HIP_TRY(hipMemcpyAsync(&h, p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  // h is final: a stopped state is passed on unchanged by the launches after the decision, and
+  // the iteration-limit exit read the snapshot taken after the last launch
   if (g_prof.on) {   // keep the records of the launches that did work (j = 1 .. iter + 1)
     g_prof.keep_launches(m0, PROF_SPEC, std::min(issued, h.iter + 1));
     if (ext) g_prof.keep_launches(m0, PROF_KSLICE, std::min(issued, h.iter + 1));
@@ -1163,12 +1162,13 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
     };
     smr_status st0 = enqueue_next();
     if (st0 != SMR_OK) return st0;
+    int slot = 0;
     for (;;) {
       if (issued < last && npend < 2) {
         st0 = enqueue_next();
         if (st0 != SMR_OK) return st0;
       }
-      const int slot = pend[0];
+      slot = pend[0];
       pend[0] = pend[1];
       --npend;
       HIP_TRY(hipEventSynchronize(bs.ev[slot]));
@@ -1177,10 +1177,9 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       if (!running) break;
       if (npend == 0 && issued >= last) break;
     }
-    // launches after each instance's decision pass its state on: the latest slots are final
-    HIP_TRY(launch_gather_scal(s, d_table, ns, issued & 1, d_scal));
-    HIP_TRY(hipMemcpyAsync(hs.data(), d_scal, sizeof(Scal) * ns, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // the snapshot just read is final: a stopped instance's state is passed on unchanged, and
+    // the iteration-limit exit read the snapshot taken after the last launch
+    std::copy(bs.h + (size_t)slot * bs.cap, bs.h + (size_t)slot * bs.cap + ns, hs.begin());
     for (int k = 0; k < ns; ++k) {
       const int i = spec_ids[k];
       const Plan &p = plans[i]->p;
