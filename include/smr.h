@@ -61,7 +61,7 @@ typedef enum {
   SMR_ENOTSPD = 4,       /* gamma^2 <= 0 or not finite: P is not SPD on the residual    */
   SMR_EBREAKDOWN = 5,    /* Lanczos/QR breakdown with a non-zero residual               */
   SMR_ENOTCONV = 6,      /* maxit reached; x holds the last iterate, info is filled     */
-  SMR_EUNSUPPORTED = 7   /* valid request this build does not implement                 */
+  SMR_EUNSUPPORTED = 7   /* valid request that the library does not implement         */
 } smr_status;
 
 typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;

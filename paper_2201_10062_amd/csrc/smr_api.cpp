@@ -168,7 +168,7 @@ smr_status validate(const smr_desc *d) {
   if (d->precond == SMR_P_THETA_CHEB && (d->cheb_k < 1 || d->cheb_k > 16))
     return fail(SMR_EINVAL, "cheb_k must be in [1, 16] (got %d)", d->cheb_k);
   if (d->pprec != SMR_FP64 && d->pprec != SMR_FP32)
-    return fail(SMR_EUNSUPPORTED, "pprec %d is not available in this build", d->pprec);
+    return fail(SMR_EUNSUPPORTED, "pprec %d is not implemented", d->pprec);
   if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
     return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
   const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32;
