@@ -157,8 +157,7 @@ static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nsl
   const long nblocks = (d.nlines + lpb - 1) / lpb;
   const size_t shmem = ((size_t)d.ppb * d.M + d.M / 2) * sizeof(double2);
   if (shmem > 65536) {
-    hipError_t e = hipFuncSetAttribute(dir == 0 ? (const void *)k_dst<0> : (const void *)k_dst<1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipError_t e = lds_limit(dir == 0 ? (const void *)k_dst<0> : (const void *)k_dst<1>, shmem);
     if (e != hipSuccess) return e;
   }
   if (dir == 0)

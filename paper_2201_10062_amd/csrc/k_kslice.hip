@@ -370,9 +370,12 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
 
 // Orthonormal 2D DST-I of every time level in one pass: the level (input slice stride sin)
 // goes into LDS, through the row and column transforms, and out with slice stride sout.
+// stop_gate: when given, the transform runs only once that scalar state has stopped.
 template <int R>
 __global__ __launch_bounds__(kKT) void k_dst2d(const double *__restrict__ in, double *__restrict__ out, long sin,
-                                               long sout, const double *__restrict__ tw, double scale) {
+                                               long sout, const double *__restrict__ tw, double scale,
+                                               const Scal *__restrict__ stop_gate) {
+  if (stop_gate && stop_gate->status == RUNNING) return;
   extern __shared__ double X[];
   constexpr int N = 32 * R - 1, LP = N + 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -421,10 +424,10 @@ template <int R, int PR>
 hipError_t run_ks(hipStream_t st, const KsP *K, const KsP *table, int ninst, int blocks, int mode, int jfull) {
   const size_t sh = ks_shmem<R, PR>();
   if (sh > 65536) {
-    hipFuncSetAttribute((const void *)k_kslice<R, PR, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipFuncSetAttribute((const void *)k_kslice<R, PR, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipFuncSetAttribute((const void *)k_kslice_multi<R, PR, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipFuncSetAttribute((const void *)k_kslice_multi<R, PR, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    lds_limit((const void *)k_kslice<R, PR, 0>, sh);
+    lds_limit((const void *)k_kslice<R, PR, 1>, sh);
+    lds_limit((const void *)k_kslice_multi<R, PR, 0>, sh);
+    lds_limit((const void *)k_kslice_multi<R, PR, 1>, sh);
   }
   if (K) {
     if (mode == 0) hipLaunchKernelGGL((k_kslice<R, PR, 0>), dim3(blocks), dim3(kKT), sh, st, *K, jfull);
@@ -698,7 +701,7 @@ hipError_t run_dst_tile(hipStream_t st, int dir, const TileP &d, int nslices, co
     const size_t sh = (size_t)(dir == 0 ? kTL * (N + 2) : N * (kTL + 1)) * sizeof(double);
     const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0> : (const void *)k_dst_tile<R, 1>;
     if (sh > 65536) {
-      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      const hipError_t e = lds_limit(f, sh);
       if (e != hipSuccess) return e;
     }
     const unsigned blocks = (unsigned)((long)nslices * d.tiles);
@@ -744,19 +747,19 @@ bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L
 
 template <int R>
 static hipError_t run_dst2d(hipStream_t st, int n, const double *in, double *out, long sin, long sout,
-                            const double *tw) {
+                            const double *tw, const Scal *stop_gate) {
   const size_t sh = (size_t)(32 * R - 1) * (32 * R + 1) * sizeof(double);
-  if (sh > 65536) hipFuncSetAttribute((const void *)k_dst2d<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL(k_dst2d<R>, dim3(n), dim3(kKT), sh, st, in, out, sin, sout, tw, 1.0 / sqrt(64.0 * R));
+  if (sh > 65536) lds_limit((const void *)k_dst2d<R>, sh);
+  hipLaunchKernelGGL(k_dst2d<R>, dim3(n), dim3(kKT), sh, st, in, out, sin, sout, tw, 1.0 / sqrt(64.0 * R), stop_gate);
   return hipGetLastError();
 }
 
-hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride) {
+hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride, const Scal *stop_gate) {
   const Plan *p = c.p;
   switch (p->L) {
-    case 32: return run_dst2d<1>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
-    case 64: return run_dst2d<2>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
-    case 128: return run_dst2d<4>(c.st, p->n, in, out, in_stride, out_stride, p->tw);
+    case 32: return run_dst2d<1>(c.st, p->n, in, out, in_stride, out_stride, p->tw, stop_gate);
+    case 64: return run_dst2d<2>(c.st, p->n, in, out, in_stride, out_stride, p->tw, stop_gate);
+    case 128: return run_dst2d<4>(c.st, p->n, in, out, in_stride, out_stride, p->tw, stop_gate);
     default: break;
   }
   return hipErrorInvalidValue;

@@ -474,10 +474,10 @@ template <int HP, int C, int PR>
 hipError_t run_spec(hipStream_t st, const SpecP &P, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
-    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec<HP, C, 3, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)lds_limit((const void *)k_spec<HP, C, 0, PR>, shmem);
+    (void)lds_limit((const void *)k_spec<HP, C, 1, PR>, shmem);
+    (void)lds_limit((const void *)k_spec<HP, C, 2, PR>, shmem);
+    (void)lds_limit((const void *)k_spec<HP, C, 3, PR>, shmem);
   }
   if (mode == 0) hipLaunchKernelGGL((k_spec<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
   else if (mode == 1) hipLaunchKernelGGL((k_spec<HP, C, 1, PR>), dim3(blocks), dim3(kThreads), shmem, st, P, jph, pmode);
@@ -490,10 +490,10 @@ template <int HP, int C, int PR>
 hipError_t run_spec_multi(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int jph, int pmode) {
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
   if (shmem > 65536) {
-    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 2, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    (void)hipFuncSetAttribute((const void *)k_spec_multi<HP, C, 3, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    (void)lds_limit((const void *)k_spec_multi<HP, C, 0, PR>, shmem);
+    (void)lds_limit((const void *)k_spec_multi<HP, C, 1, PR>, shmem);
+    (void)lds_limit((const void *)k_spec_multi<HP, C, 2, PR>, shmem);
+    (void)lds_limit((const void *)k_spec_multi<HP, C, 3, PR>, shmem);
   }
   if (mode == 0)
     hipLaunchKernelGGL((k_spec_multi<HP, C, 0, PR>), dim3(blocks), dim3(kThreads), shmem, st, table, ninst, jph, pmode);

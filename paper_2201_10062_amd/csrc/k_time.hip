@@ -338,10 +338,8 @@ hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int m
   if constexpr (HP >= 256) {
     constexpr int NW = 8;
     if (shmem > 65536) {
-      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 0, PR, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem);
-      (void)hipFuncSetAttribute((const void *)k_time<HP, C, 1, PR, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem);
+      (void)lds_limit((const void *)k_time<HP, C, 0, PR, NW>, shmem);
+      (void)lds_limit((const void *)k_time<HP, C, 1, PR, NW>, shmem);
     }
     if (mode == 0)
       hipLaunchKernelGGL((k_time<HP, C, 0, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
@@ -349,10 +347,8 @@ hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int m
       hipLaunchKernelGGL((k_time<HP, C, 1, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
   } else {
     if (shmem > 65536) {
-      (void)hipFuncSetAttribute((const void *)k_time_pair<HP, C, 0, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem);
-      (void)hipFuncSetAttribute((const void *)k_time_pair<HP, C, 1, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem);
+      (void)lds_limit((const void *)k_time_pair<HP, C, 0, PR>, shmem);
+      (void)lds_limit((const void *)k_time_pair<HP, C, 1, PR>, shmem);
     }
     if (mode == 0)
       hipLaunchKernelGGL((k_time_pair<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);

@@ -11,6 +11,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "smr_internal.h"
@@ -20,6 +22,20 @@ struct smr_plan {
 };
 
 namespace smr {
+
+hipError_t lds_limit(const void *kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, size_t> set;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &have = set[{kernel, dev}];
+  if (bytes <= have) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) have = bytes;
+  return e;
+}
 namespace {
 
 thread_local std::string g_err;
@@ -777,6 +793,24 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
   int issued = 0;                   // launches j = 1..issued enqueued
   const int last = maxit + 2;       // launch maxit + 2 takes the stop decision on iteration maxit
   int pend[2], npend = 0, slot_next = 0;
+  long pend_seq[2], seq = 0;        // order of the enqueued snapshots
+  // Stop prediction.  Every snapshot carries |eta| / gamma_1, the relative residual in the
+  // P^{-1} norm (monotone in MINRES), and, once true residuals are evaluated, their ratio to
+  // it.  From its decay between the last two snapshots and the latest ratio the host predicts
+  // the stopping iteration, enqueues only the launches up to it (two spare) and then waits for
+  // the snapshot after them before enqueueing more.  A wrong prediction costs a host round
+  // trip, never a result: the device takes the stop decision itself.
+  // The transform of the result back from the sine basis follows those launches, gated on the
+  // stopped state, so that a right prediction costs no round trip at the end either; it ran iff
+  // the snapshot after it (and every later one) read a stopped state.
+  int e_it[2] = {-1, -1}, seen_nres = 1;
+  double e_v[2] = {0.0, 0.0}, ratio = 1.0;
+  int spent = 1 << 30;              // last launch of the prediction, once enqueued
+  long spent_seq = -1;              // the snapshot taken right after it
+  bool short_pred = false;          // that snapshot or a later one read RUNNING
+  const bool ahead_ok = kslice_supported(&p) && Xh != x;   // the one-pass transform
+  bool ahead = false;
+  Ctx cx{&p, s};
   // enqueue up to `cap` launches (a captured chunk of six when aligned) and a snapshot of the
   // state after them (pinned host copy + event)
   auto enqueue_next = [&](int cap) -> smr_status {
@@ -794,29 +828,36 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
       }
       issued += todo;
     }
+    if (spent_seq < 0 && issued >= spent) {
+      if (ahead_ok) {
+        LAUNCH(PROF_DST, launch_dst2d(cx, Xh, x, p.ld, p.m, p.sc + (issued & 1)));
+        ahead = true;
+      }
+      spent_seq = seq;
+    }
     HIP_TRY(hipMemcpyAsync(&p.snap[slot_next], p.sc + (issued & 1), sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(p.snap_ev[slot_next], s));
+    pend_seq[npend] = seq++;
     pend[npend++] = slot_next;
     slot_next ^= 1;
     return SMR_OK;
   };
-  // Stop prediction: the true residuals evaluated so far (the snapshot's relres whenever the
-  // count of evaluated residuals grew) decay at a rate per iteration; once two are known the
-  // host enqueues only the launches up to the predicted stop (one spare) instead of whole
-  // chunks, so that few launches run past convergence.  A wrong prediction costs one host
-  // round trip, never a result: the device takes the stop decision itself.
-  int obs_it[2] = {-1, -1}, seen_nres = 0, spent = 1 << 30;
-  double obs_r[2] = {0.0, 0.0};
   auto predicted_cap = [&]() -> int {
-    if (issued >= spent) return 6;                       // a prediction fell short: whole chunks again
-    if (obs_it[0] < 0 || obs_it[1] <= obs_it[0] || !(obs_r[1] > 0.0) || !(obs_r[0] > obs_r[1])) return 6;
-    const double rho = std::pow(obs_r[1] / obs_r[0], 1.0 / (obs_it[1] - obs_it[0]));
+    if (short_pred) return 6;                            // the prediction fell short: whole chunks
+    if (spent_seq >= 0) return 0;                        // wait for its verdict
+    if (e_it[0] < 0 || e_it[1] <= e_it[0] || !(e_v[1] > 0.0) || !(e_v[0] > e_v[1])) return 6;
+    const double rho = std::pow(e_v[1] / e_v[0], 1.0 / (e_it[1] - e_it[0]));
     if (!(rho > 0.0 && rho < 1.0)) return 6;
-    const double more = obs_r[1] <= rtol ? 0.0 : std::ceil(std::log(rtol / obs_r[1]) / std::log(rho));
+    const double est = ratio * e_v[1];                   // true relative residual, estimated
+    const double more = est <= rtol ? 0.0 : std::ceil(std::log(rtol / est) / std::log(rho));
     if (!(more < 1e6)) return 6;
-    const int reach = obs_it[1] + (int)more + 2 + 2;    // launch stop + 2 decides; two spare
-    spent = std::min(spent, reach);
-    return std::max(0, std::min(6, reach - issued));
+    const int reach = e_it[1] + (int)more + 2 + 2;      // launch stop + 2 decides; two spare
+    if (reach - issued > 6) return 6;
+    // the last chunk: a captured one whole where one is due (launches enqueued one by one
+    // behind a graph replay start late), else the launches up to the predicted stop
+    const bool aligned = graph && issued >= 5 && (issued + 1) % 6 == 0 && last - issued >= 6;
+    spent = aligned ? issued + 6 : std::max(reach, issued + 1);
+    return spent - issued;
   };
   // keep one chunk in flight ahead of the status being checked, so the device never waits
   st = enqueue_next(6);
@@ -831,17 +872,24 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
       }
     }
     const int slot = pend[0];
+    const long sq = pend_seq[0];
     pend[0] = pend[1];
+    pend_seq[0] = pend_seq[1];
     --npend;
     HIP_TRY(hipEventSynchronize(p.snap_ev[slot]));
     h = p.snap[slot];
+    if (h.status == RUNNING && spent_seq >= 0 && sq >= spent_seq) short_pred = true;
     if (h.status != RUNNING) break;
     if (npend == 0 && issued >= last) break;
-    if (h.nres > seen_nres) {                           // a new true residual
-      obs_it[0] = obs_it[1];
-      obs_r[0] = obs_r[1];
-      obs_it[1] = h.nres == 1 ? 0 : h.iter;
-      obs_r[1] = h.relres;
+    const double pr = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
+    if (h.iter > e_it[1]) {
+      e_it[0] = e_it[1];
+      e_v[0] = e_v[1];
+      e_it[1] = h.iter;
+      e_v[1] = pr;
+    }
+    if (h.nres > seen_nres && pr > 0.0) {               // a true residual of the steady phase
+      ratio = h.relres / pr;
       seen_nres = h.nres;
     }
   }
@@ -851,9 +899,10 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
     g_prof.keep_launches(m0, PROF_SPEC, std::min(issued, h.iter + 1));
     if (ext) g_prof.keep_launches(m0, PROF_KSLICE, std::min(issued, h.iter + 1));
   }
+  const bool ahead_ran = ahead && !short_pred && h.status != RUNNING;
   if (h.status == DONE_CONV && h.bnorm == 0.0) {
     LAUNCH(PROF_VEC, launch_zero(c, x, p.len));
-  } else {
+  } else if (!ahead_ran) {
     st = from_sine_basis(p, s, Xh, x);
     if (st != SMR_OK) return st;
   }

@@ -81,6 +81,10 @@ struct Ctx {
   hipStream_t st;
 };
 
+// Raises a kernel's dynamic LDS limit to `bytes` on the current device, calling the runtime
+// only the first time (per kernel, device and larger size) instead of on every launch.
+hipError_t lds_limit(const void *kernel, size_t bytes);
+
 // y = Y T (xs * x) with xs = *d_xscale (or 1 if null); optional partial sums of
 // y . (xs*x) into part[0..G).  When rhs != null computes r = Y rhs - Y T x instead and
 // accumulates ||r||^2 (slot 0) and ||rhs||^2 (slot 1) and writes r if y != null.
@@ -159,8 +163,10 @@ struct KsP {
 };
 bool kslice_supported(const Plan *p);
 // 2D spatial sine transform of every time level in one pass (dim 2, N + 1 in {32, 64, 128});
-// out may equal in only when the strides agree
-hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride);
+// out may equal in only when the strides agree.  stop_gate: run only once that scalar state
+// is no longer RUNNING (a transform enqueued ahead of a predicted stop).
+hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, long out_stride,
+                        const Scal *stop_gate = nullptr);
 // One DST-I pass (the arguments of launch_dst) as line tiles through the register FFT, for 2D
 // plans with N + 1 in {32, 64, 128, 256}; launch_dst takes it where it applies.
 bool dst_tile_supported(const Plan *p);
