@@ -420,3 +420,26 @@ def test_repeated_solves_replay_captured_iterations(kind):
         assert rel(_n(x), ref.x) < 1e-9
         y = g.apply_A(_t(b))                     # eager work between the solves
         assert rel(_n(y), o.apply_YT(b)) < 1e-12
+
+
+@pytest.mark.parametrize("kind,N,n", [("const", 31, 64), ("const", 63, 40), ("var", 31, 48)],
+                         ids=["const-31", "const-63", "var-31"])
+def test_stop_points_and_transform_ahead(kind, N, n):
+    """The host predicts the stopping iteration from the snapshots and enqueues the transform
+    back from the sine basis behind the predicted last chunk, gated on the stopped state; a
+    short prediction must leave it to the normal transform.  Stopping at many points (several
+    tolerances, iteration limits before and inside the captured chunks), on one plan one solve
+    after another, every iterate equals the oracle's at the same count."""
+    g, o = _pair(2, N, n, "theta", 0.5, kind=kind)
+    rng = np.random.default_rng(31)
+    b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m))
+    for rtol in (1e-2, 1e-4, 1e-6, 1e-7, 1e-9, 1e-11):
+        ref = o.solve(b, rtol=rtol, maxit=400)
+        x, info = g.solve(_t(b), rtol=rtol, maxit=400)
+        assert info["status"] == "ok" and info["iters"] == ref.iters, (rtol, info, ref.iters)
+        assert rel(_n(x), ref.x) < 1e-9, rtol
+    for k in (2, 6, 11, 12, 17, 23):
+        ref = o.solve(b, rtol=1e-300, maxit=k)
+        x, info = g.solve(_t(b), rtol=1e-300, maxit=k)
+        assert info["iters"] == k and info["status"] == "enotconv", (k, info)
+        assert rel(_n(x), ref.x) < 1e-9, k
