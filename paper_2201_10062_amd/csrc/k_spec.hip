@@ -33,6 +33,7 @@ namespace {
 constexpr int kThreads = 512;         // 8 waves
 
 constexpr int kWaves = kThreads / 64;
+constexpr int kUS = 4;                // levels per batch of loads in the streams
 
 // MODE_EARLY: a steady iteration of launch 2 or 3, where w_{j-2} or w_{j-3} does not exist yet
 enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2, MODE_EARLY = 3 };
@@ -276,24 +277,44 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     if (bt0 >= 1) { const size_t i = vat(ld, bt0 - 1, bcc); bx1 = xv[i] + ceta * wnew(i); }
     if (bt0 >= 2) { const size_t i = vat(ld, bt0 - 2, bcc); bx2 = xv[i] + ceta * wnew(i); }
   }
-  auto bstream = [&](int ta, int tb) {
+  // kUS levels at a time, all their loads issued before any store (see the v stream below;
+  // w_{j-1} overwrites w_{j-3} in place, each element read before it is written)
+  auto bstream_t = [&](auto res, int ta, int tb) {
+    constexpr bool RES = decltype(res)::value;
     const Coef k = coef_of(P, P.tmu[bcc]);
-#pragma unroll 4
-    for (int t = ta; t < tb; ++t) {
-      const size_t i = vat(ld, t, bcc);
-      const double w = wnew(i);
-      const double x0 = xv[i] + ceta * w;
-      if (bok) {
-        wb[i] = w;
-        xv[i] = x0;
-        if (bres) {       // (variable a: the per-level matvec takes the true residual)
-          const double r = bh[i] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
-          acc_r += r * r;
-        }
+    for (int t0 = ta; t0 < tb; t0 += kUS) {
+      double zp[kUS], w3[kUS], w2[kUS], xo[kUS], bt[kUS];
+#pragma unroll
+      for (int u = 0; u < kUS; ++u) {
+        const size_t i = vat(ld, min(t0 + u, tb - 1), bcc);   // past tb: valid, unused
+        zp[u] = (double)zprev[i];
+        w3[u] = wbr[i];
+        w2[u] = war[i];
+        xo[u] = xv[i];
+        bt[u] = RES ? bh[i] : 0.0;
       }
-      bx2 = bx1;
-      bx1 = x0;
+#pragma unroll
+      for (int u = 0; u < kUS; ++u) {
+        if (t0 + u >= tb) break;
+        const size_t i = vat(ld, t0 + u, bcc);
+        const double w = (zsl * zp[u] - a3e * w3[u] - a2e * w2[u]) * ra1;
+        const double x0 = xo[u] + ceta * w;
+        if (bok) {
+          wb[i] = w;
+          xv[i] = x0;
+          if (RES) {      // (variable a: the per-level matvec takes the true residual)
+            const double r = bt[u] - (k.l0 * x0 + k.l1 * bx1 + k.l2 * bx2);
+            acc_r += r * r;
+          }
+        }
+        bx2 = bx1;
+        bx1 = x0;
+      }
     }
+  };
+  auto bstream = [&](int ta, int tb) {
+    if (bres) bstream_t(std::true_type{}, ta, tb);
+    else bstream_t(std::false_type{}, ta, tb);
   };
 
   // ---- A. v_{j+1}[o] (or v_1), o = n-1-t, streamed over time levels t in ascending order
@@ -312,28 +333,44 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? (xz ? 0.0 : xv[i]) : (double)zcur[i]; };
     double y1 = (!ext && t0 >= 1) ? src(vat(ld, t0 - 1, cc)) : 0.0;
     double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
-#pragma unroll 4
-    for (int t = t0; t < t1; ++t) {
-      const int o = n - 1 - t;
-      const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
-      const double y0 = ext ? 0.0 : src(it);
-      const double ty = ext ? (xz ? 0.0 : P.qext[it]) : k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
-      double v;
-      if (MODE == MODE_INIT) {
-        const double bt = bh[it];
-        v = bt - ty;                                 // (Y b)_o - ((Y T)^ x0)_o
-        if (ok) { acc_r += v * v; acc_b += bt * bt; }
-        if (xz && ok) xv[it] = 0.0;
-      } else if (MODE == MODE_FIRST) {
-        v = zs * ty - va * vcur[io];                 // v_0 = 0
-      } else {
-        v = zs * ty - va * vcur[io] - vb * vold[io];
+    // kUS levels at a time, all their loads issued before any store (the stores of one level
+    // would otherwise hold back the loads of the next: the compiler cannot separate them)
+    for (int tb = t0; tb < t1; tb += kUS) {
+      double ys[kUS], qs[kUS], vc[kUS], vo[kUS], bs[kUS];
+#pragma unroll
+      for (int u = 0; u < kUS; ++u) {
+        const int t = min(tb + u, t1 - 1);           // past t1: a valid level, value unused
+        const size_t it = vat(ld, t, cc), io = vat(ld, n - 1 - t, cc);
+        ys[u] = ext ? 0.0 : src(it);
+        qs[u] = ext && !xz ? P.qext[it] : 0.0;
+        vc[u] = MODE == MODE_INIT ? 0.0 : vcur[io];
+        vo[u] = STEADY ? vold[io] : 0.0;
+        bs[u] = MODE == MODE_INIT ? bh[it] : 0.0;
       }
-      if (ok) vold[io] = v;
-      if (o < h1) U[o * LD + c] = ok ? (T)v : T(0);
-      else D[t * LD + c] = ok ? (T)v : T(0);
-      y2 = y1;
-      y1 = y0;
+#pragma unroll
+      for (int u = 0; u < kUS; ++u) {
+        const int t = tb + u;
+        if (t >= t1) break;
+        const int o = n - 1 - t;
+        const size_t it = vat(ld, t, cc), io = vat(ld, o, cc);
+        const double y0 = ys[u];
+        const double ty = ext ? qs[u] : k.l0 * y0 + k.l1 * y1 + k.l2 * y2;
+        double v;
+        if (MODE == MODE_INIT) {
+          v = bs[u] - ty;                              // (Y b)_o - ((Y T)^ x0)_o
+          if (ok) { acc_r += v * v; acc_b += bs[u] * bs[u]; }
+          if (xz && ok) xv[it] = 0.0;
+        } else if (MODE == MODE_FIRST) {
+          v = zs * ty - va * vc[u];                    // v_0 = 0
+        } else {
+          v = zs * ty - va * vc[u] - vb * vo[u];
+        }
+        if (ok) vold[io] = v;
+        if (o < h1) U[o * LD + c] = ok ? (T)v : T(0);
+        else D[t * LD + c] = ok ? (T)v : T(0);
+        y2 = y1;
+        y1 = y0;
+      }
     }
     // padding rows
     for (int e = tid; e < (HP - h1) * C; e += kThreads) U[(h1 + e / C) * LD + e % C] = T(0);
