@@ -322,14 +322,27 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     uku_level<R, KMAX>(X, K, tid, wave, lane);
     double *q = K.q + (size_t)t * ld;
     const T *sf = s + (size_t)(n - 1 - t) * ld;
-    for (int e = tid; e < m; e += kKT) {
-      const double v0 = (double)st[e];
-      const double v1 = s1 ? (double)s1[e] : 0.0;
-      const double v2 = s2 ? (double)s2[e] : 0.0;
-      const int jr = e / NC, ir = e - jr * NC;
-      const double v = c0 * v0 + c1 * v1 + c2 * v2 + K.tau * X[jr * LP + ir];
-      q[e] = v;
-      if (MODE == 1) acc_d += v * (double)sf[e];
+    // four elements at a time, all their loads issued before any store of q (a store held
+    // back the next element's loads)
+    for (int e0 = tid; e0 < m; e0 += 4 * kKT) {
+      double a0[4], a1[4], a2[4], af[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * kKT, m - 1);      // past m: a valid element, value unused
+        a0[u] = (double)st[e];
+        a1[u] = s1 ? (double)s1[e] : 0.0;
+        a2[u] = s2 ? (double)s2[e] : 0.0;
+        af[u] = MODE == 1 ? (double)sf[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kKT;
+        if (e >= m) break;
+        const int jr = e / NC, ir = e - jr * NC;
+        const double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[jr * LP + ir];
+        q[e] = v;
+        if (MODE == 1) acc_d += v * af[u];
+      }
     }
   }
   // ---- true residual ||b^ - (T x)^||^2 on level t
