@@ -469,6 +469,15 @@ inline int grid_for(size_t work, int per_block) {
   return (int)g;
 }
 
+// Grid of a kernel without block partial sums: one block per `per_block` items, so that no
+// thread walks several items one after another (capped only by the grid-stride loops' reach)
+inline int grid_all(size_t work, int per_block) {
+  size_t g = (work + per_block - 1) / per_block;
+  if (g > (size_t)(1 << 20)) g = 1 << 20;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
 }  // namespace
 
 hipError_t launch_apply_YT(Ctx c, const double *x, const double *d_xscale, double *y, const double *rhs,
@@ -522,12 +531,12 @@ hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const dou
 }
 
 hipError_t launch_vupdate(Ctx c, const double *q, const double *v, double *vold, const Scal *gate) {
-  hipLaunchKernelGGL(k_vupdate, dim3(grid_for(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, q, v, vold, gate);
+  hipLaunchKernelGGL(k_vupdate, dim3(grid_all(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, q, v, vold, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_wxupdate(Ctx c, const double *z, double *wold, const double *w, double *x, const Scal *gate) {
-  hipLaunchKernelGGL(k_wxupdate, dim3(grid_for(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, z, wold, w, x, gate);
+  hipLaunchKernelGGL(k_wxupdate, dim3(grid_all(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, z, wold, w, x, gate);
   return hipGetLastError();
 }
 
@@ -561,7 +570,7 @@ hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, cons
 
 hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, double a_d, double a_t, int first,
                             const Scal *gate) {
-  hipLaunchKernelGGL(k_cheb_axpy, dim3(grid_for(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, x, dvec, tmp, a_d,
+  hipLaunchKernelGGL(k_cheb_axpy, dim3(grid_all(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, x, dvec, tmp, a_d,
                      a_t, first, gate);
   return hipGetLastError();
 }
@@ -569,7 +578,7 @@ hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, d
 hipError_t launch_cheb_resid(Ctx c, double *res, const double *dvec, const Scal *gate) {
   const Plan *p = c.p;
   TileInfo ti = tiles_of(p, p->n);
-  const int g = ti.ntiles < kRedSlots ? ti.ntiles : kRedSlots;
+  const int g = grid_all(ti.ntiles, 1);
   hipLaunchKernelGGL(k_cheb_resid, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, p->ez, res, dvec, gate);
   return hipGetLastError();
 }
