@@ -29,6 +29,7 @@ namespace smr {
 namespace {
 
 constexpr int kKT = 512;                 // 8 waves per block
+constexpr int kLB = 8;                   // elements per thread whose loads are issued together
 constexpr int kKW = kKT / 64;
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -312,11 +313,21 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const T *st = s + (size_t)t * ld;
     const T *s1 = t >= 1 ? st - ld : nullptr;
     const T *s2 = t >= 2 ? st - 2 * ld : nullptr;
-    for (int e = tid; e < m; e += kKT) {
-      const double v0 = (double)st[e];
-      const double v1 = s1 ? (double)s1[e] : 0.0;
-      const int jr = e / NC, ir = e - jr * NC;
-      X[jr * LP + ir] = b0 * v0 + b1 * v1;
+    for (int e0 = tid; e0 < m; e0 += kLB * kKT) {   // kLB elements' loads in flight
+      double a0[kLB], a1[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int e = min(e0 + u * kKT, m - 1);
+        a0[u] = (double)st[e];
+        a1[u] = s1 ? (double)s1[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int e = e0 + u * kKT;
+        if (e >= m) break;
+        const int jr = e / NC, ir = e - jr * NC;
+        X[jr * LP + ir] = b0 * a0[u] + b1 * a1[u];
+      }
     }
     __syncthreads();
     uku_level<R, KMAX>(X, K, tid, wave, lane);
@@ -352,11 +363,21 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const double *x1 = t >= 1 ? xt - ld : nullptr;
     const double *x2 = t >= 2 ? xt - 2 * ld : nullptr;
     const double *bt = K.bh + (size_t)t * ld;
-    for (int e = tid; e < m; e += kKT) {
-      const double v0 = xt[e];
-      const double v1 = x1 ? x1[e] : 0.0;
-      const int jr = e / NC, ir = e - jr * NC;
-      X[jr * LP + ir] = b0 * v0 + b1 * v1;
+    for (int e0 = tid; e0 < m; e0 += kLB * kKT) {
+      double a0[kLB], a1[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int e = min(e0 + u * kKT, m - 1);
+        a0[u] = xt[e];
+        a1[u] = x1 ? x1[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int e = e0 + u * kKT;
+        if (e >= m) break;
+        const int jr = e / NC, ir = e - jr * NC;
+        X[jr * LP + ir] = b0 * a0[u] + b1 * a1[u];
+      }
     }
     __syncthreads();
     uku_level<R, KMAX>(X, K, tid, wave, lane);
@@ -393,9 +414,17 @@ __global__ __launch_bounds__(kKT) void k_dst2d(const double *__restrict__ in, do
   constexpr int N = 32 * R - 1, LP = N + 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double *src = in + (size_t)blockIdx.x * sin;
-  for (int e = tid; e < N * N; e += kKT) {
-    const int j = e / N, i = e - j * N;
-    X[j * LP + i] = src[e];
+  for (int e0 = tid; e0 < N * N; e0 += kLB * kKT) {   // kLB elements' loads in flight
+    double a[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) a[u] = src[min(e0 + u * kKT, N * N - 1)];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kKT;
+      if (e >= N * N) break;
+      const int j = e / N, i = e - j * N;
+      X[j * LP + i] = a[u];
+    }
   }
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(tw), lane);
