@@ -33,7 +33,8 @@ namespace {
 constexpr int kThreads = 512;         // 8 waves
 
 constexpr int kWaves = kThreads / 64;
-constexpr int kUS = 4;                // levels per batch of loads in the streams
+constexpr int kUS = 4;                // levels per batch of loads in the w/x stream
+constexpr int kUA = 8;                // levels per batch of loads in the v stream
 
 // MODE_EARLY: a steady iteration of launch 2 or 3, where w_{j-2} or w_{j-3} does not exist yet
 enum { MODE_INIT = 0, MODE_FIRST = 1, MODE_STEADY = 2, MODE_EARLY = 3 };
@@ -335,10 +336,10 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
     // kUS levels at a time, all their loads issued before any store (the stores of one level
     // would otherwise hold back the loads of the next: the compiler cannot separate them)
-    for (int tb = t0; tb < t1; tb += kUS) {
-      double ys[kUS], qs[kUS], vc[kUS], vo[kUS], bs[kUS];
+    for (int tb = t0; tb < t1; tb += kUA) {
+      double ys[kUA], qs[kUA], vc[kUA], vo[kUA], bs[kUA];
 #pragma unroll
-      for (int u = 0; u < kUS; ++u) {
+      for (int u = 0; u < kUA; ++u) {
         const int t = min(tb + u, t1 - 1);           // past t1: a valid level, value unused
         const size_t it = vat(ld, t, cc), io = vat(ld, n - 1 - t, cc);
         ys[u] = ext ? 0.0 : src(it);
@@ -348,7 +349,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
         bs[u] = MODE == MODE_INIT ? bh[it] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kUS; ++u) {
+      for (int u = 0; u < kUA; ++u) {
         const int t = tb + u;
         if (t >= t1) break;
         const int o = n - 1 - t;
