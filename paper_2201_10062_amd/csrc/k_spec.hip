@@ -334,7 +334,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? (xz ? 0.0 : xv[i]) : (double)zcur[i]; };
     double y1 = (!ext && t0 >= 1) ? src(vat(ld, t0 - 1, cc)) : 0.0;
     double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
-    // kUS levels at a time, all their loads issued before any store (the stores of one level
+    // kUA levels at a time, all their loads issued before any store (the stores of one level
     // would otherwise hold back the loads of the next: the compiler cannot separate them)
     for (int tb = t0; tb < t1; tb += kUA) {
       double ys[kUA], qs[kUA], vc[kUA], vo[kUA], bs[kUA];
