@@ -196,11 +196,50 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   //         alternate between two slots by launch parity.
   if (MODE != MODE_INIT) {
     const Scal *sprev = P.sc + ((j + 1) & 1);
-    Scal *snew = P.sc + (j & 1);
     if (sprev->status != RUNNING) {             // stopped earlier: pass the state on
-      if (tile == 0 && tid == 0) *snew = *sprev;
+      if (tile == 0 && tid == 0) P.sc[j & 1] = *sprev;
       return;
     }
+  }
+  const T *__restrict__ zcur = reinterpret_cast<const T *>(P.Z[(j + 2) % 3]);
+  const T *__restrict__ zprev = reinterpret_cast<const T *>(P.Z[(j + 1) % 3]);
+  T *__restrict__ znext = reinterpret_cast<T *>(MODE == MODE_INIT ? P.Z[0] : P.Z[j % 3]);
+  const double *__restrict__ vcur = P.V[j % 2];
+  double *__restrict__ vold = MODE == MODE_INIT ? P.V[1] : P.V[(j + 1) % 2];
+  const double *__restrict__ wa = P.W[j % 2];
+  double *__restrict__ wb = P.W[(j + 1) % 2];
+  const double *__restrict__ bh = P.bh;
+  double *__restrict__ xv = P.x;
+  constexpr bool STEADY = MODE == MODE_STEADY || MODE == MODE_EARLY;
+
+  // the v stream's column and levels (phase A), and its first batch of loads, issued before
+  // the scalar step so that they are in flight during it (they do not depend on the scalars)
+  const int ac = tid % C, ag = tid / C;
+  const bool aok = col0 + ac < m;
+  const int acc_c = aok ? col0 + ac : m - 1;         // clamped column for loads
+  const int aR = (n + G - 1) / G;
+  const int at0 = min(n, ag * aR), at1 = min(n, at0 + aR);   // groups past n: no level, no carry
+  const bool aext = P.qext != nullptr;               // (T z)^ given by the per-level matvec
+  const bool axz = MODE == MODE_INIT && P.x0zero;    // x0 = 0: no x read, (T x0)^ = 0
+  auto asrc = [&](size_t i) -> double { return MODE == MODE_INIT ? (axz ? 0.0 : xv[i]) : (double)zcur[i]; };
+  double ys[kUA], qs[kUA], vc[kUA], vo[kUA], bs[kUA];
+  auto a_load = [&](int tb) {
+#pragma unroll
+    for (int u = 0; u < kUA; ++u) {
+      const int t = min(tb + u, at1 - 1);            // past at1: a valid level, value unused
+      const size_t it = vat(ld, t, acc_c), io = vat(ld, n - 1 - t, acc_c);
+      ys[u] = aext ? 0.0 : asrc(it);
+      qs[u] = aext && !axz ? P.qext[it] : 0.0;
+      vc[u] = MODE == MODE_INIT ? 0.0 : vcur[io];
+      vo[u] = STEADY ? vold[io] : 0.0;
+      bs[u] = MODE == MODE_INIT ? bh[it] : 0.0;
+    }
+  };
+  if (at0 < at1) a_load(at0);
+
+  if (MODE != MODE_INIT) {
+    const Scal *sprev = P.sc + ((j + 1) & 1);
+    Scal *snew = P.sc + (j & 1);
     if (tid == 0) S = *sprev;      // in flight with the partial sums below
     const double *pp = P.part + (size_t)((j + 1) & 1) * 4 * P.tiles;
     double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // t[4]: residuals skipped by the per-level matvec
@@ -234,20 +273,10 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   }
   const double va = uni(S.va), vb = uni(S.vb), zs = uni(S.zs);
   const double a1 = uni(S.a1), a2 = uni(S.a2), a3 = uni(S.a3), ceta = uni(S.ceta), zsl = uni(S.gamma_new);
-  const T *__restrict__ zcur = reinterpret_cast<const T *>(P.Z[(j + 2) % 3]);
-  const T *__restrict__ zprev = reinterpret_cast<const T *>(P.Z[(j + 1) % 3]);
-  T *__restrict__ znext = reinterpret_cast<T *>(MODE == MODE_INIT ? P.Z[0] : P.Z[j % 3]);
-  const double *__restrict__ vcur = P.V[j % 2];
-  double *__restrict__ vold = MODE == MODE_INIT ? P.V[1] : P.V[(j + 1) % 2];
-  const double *__restrict__ wa = P.W[j % 2];
-  double *__restrict__ wb = P.W[(j + 1) % 2];
-  const double *__restrict__ bh = P.bh;
-  double *__restrict__ xv = P.x;
 
   double acc_r = 0.0, acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
   // the true residual of x_{j-1} is needed only once sqrt(min sigma) |eta| (a lower bound of
   // ||r||_2, |eta| being ||r||_{P^-1}) no longer excludes convergence, or at the iteration limit
-  constexpr bool STEADY = MODE == MODE_STEADY || MODE == MODE_EARLY;
   const bool bres = STEADY && !P.qext &&
                     (P.sqsigmin * fabs(S.eta) <= 2.0 * S.rtol * S.bnorm || S.iter >= S.maxit);
   if (STEADY && !P.qext && !bres && tid == 0) acc_b = 1.0;
@@ -322,32 +351,16 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
   //        so that the stencil's previous level is a register carry.  LDS mirror layout:
   //        U[o] for o < h1, D[t] for o >= h1 (so that U[p] pairs with D[p] = row n-1-p).
   {
-    const int c = tid % C, g = tid / C;
-    const int col = col0 + c;
-    const bool ok = col < m;
-    const int cc = ok ? col : m - 1;                 // clamped column for loads
+    const int c = ac, cc = acc_c, t0 = at0, t1 = at1;
+    const bool ok = aok, ext = aext, xz = axz;
     const Coef k = coef_of(P, P.tmu[cc]);
-    const int R = (n + G - 1) / G;
-    const int t0 = g * R, t1 = min(n, t0 + R);
-    const bool ext = P.qext != nullptr;               // (T z)^ given by the per-level matvec
-    const bool xz = MODE == MODE_INIT && P.x0zero;    // x0 = 0: no x read, (T x0)^ = 0
-    auto src = [&](size_t i) -> double { return MODE == MODE_INIT ? (xz ? 0.0 : xv[i]) : (double)zcur[i]; };
-    double y1 = (!ext && t0 >= 1) ? src(vat(ld, t0 - 1, cc)) : 0.0;
-    double y2 = (!ext && t0 >= 2) ? src(vat(ld, t0 - 2, cc)) : 0.0;
+    double y1 = (!ext && t0 >= 1) ? asrc(vat(ld, t0 - 1, cc)) : 0.0;
+    double y2 = (!ext && t0 >= 2) ? asrc(vat(ld, t0 - 2, cc)) : 0.0;
     // kUA levels at a time, all their loads issued before any store (the stores of one level
-    // would otherwise hold back the loads of the next: the compiler cannot separate them)
+    // would otherwise hold back the loads of the next: the compiler cannot separate them);
+    // the first batch was loaded before the scalar step
     for (int tb = t0; tb < t1; tb += kUA) {
-      double ys[kUA], qs[kUA], vc[kUA], vo[kUA], bs[kUA];
-#pragma unroll
-      for (int u = 0; u < kUA; ++u) {
-        const int t = min(tb + u, t1 - 1);           // past t1: a valid level, value unused
-        const size_t it = vat(ld, t, cc), io = vat(ld, n - 1 - t, cc);
-        ys[u] = ext ? 0.0 : src(it);
-        qs[u] = ext && !xz ? P.qext[it] : 0.0;
-        vc[u] = MODE == MODE_INIT ? 0.0 : vcur[io];
-        vo[u] = STEADY ? vold[io] : 0.0;
-        bs[u] = MODE == MODE_INIT ? bh[it] : 0.0;
-      }
+      if (tb != t0) a_load(tb);
 #pragma unroll
       for (int u = 0; u < kUA; ++u) {
         const int t = tb + u;
@@ -447,7 +460,7 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const bool ok = col < m;
     const Coef k = coef_of(P, P.tmu[ok ? col : m - 1]);
     const int R = (n + G - 1) / G;
-    const int t0 = g * R, t1 = min(n, t0 + R);
+    const int t0 = min(n, g * R), t1 = min(n, t0 + R);   // groups past n take no level
     // z_p = u'_p + d'_p and z_{n-1-p} = u'_p - d'_p (p < h2); odd n: the middle z_p = u'_p
     auto zrow = [&](int t) -> double {
       if (t < h1) return t < h2 ? (double)(T)(U[t * LD + c] + D[t * LD + c]) : (double)U[t * LD + c];
