@@ -271,7 +271,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the solve is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(the solve runs on one GPU)", file=sys.stderr)
         return 2
 
     import torch

@@ -844,7 +844,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
   };
   auto predicted_cap = [&]() -> int {
     if (short_pred) return 6;                            // the prediction fell short: whole chunks
-    if (spent_seq >= 0) return 0;                        // wait for its verdict
+    if (spent_seq >= 0) return 0;                        // wait for its outcome
     if (e_it[0] < 0 || e_it[1] <= e_it[0] || !(e_v[1] > 0.0) || !(e_v[0] > e_v[1])) return 6;
     const double rho = std::pow(e_v[1] / e_v[0], 1.0 / (e_it[1] - e_it[0]));
     if (!(rho > 0.0 && rho < 1.0)) return 6;
