@@ -79,22 +79,27 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
   const int col0 = blockIdx.x * C;
   const int n = tp.n, m = tp.m, h1 = tp.h1, h2 = tp.h2;
 
-  // 1. butterfly load (zero padding rows and columns beyond m)
-  for (int e = tid; e < HP * C; e += 256) {
-    const int p = e / C, c = e - p * C;
-    const int col = col0 + c;
-    double u = 0.0, d = 0.0;
-    if (col < m) {
-      if (p < h2) {
-        const double a = in[(size_t)p * m + col], b = in[(size_t)(n - 1 - p) * m + col];
-        u = a + b;
-        d = a - b;
-      } else if (p < h1) {                   // odd n: middle level
-        u = in[(size_t)p * m + col];
-      }
+  // 1. butterfly load (zero padding rows and columns beyond m), eight elements per thread
+  //    with all their loads issued before the LDS stores
+  for (int e0 = tid; e0 < HP * C; e0 += 8 * 256) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      const int p = e / C, col = col0 + (e - p * C);
+      const bool okc = e < HP * C && col < m;
+      a[u] = okc && p < h1 ? in[(size_t)p * m + col] : 0.0;
+      b[u] = okc && p < h2 ? in[(size_t)(n - 1 - p) * m + col] : 0.0;
     }
-    U[p * LD + c] = (T)u;
-    D[p * LD + c] = (T)d;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e >= HP * C) break;
+      const int p = e / C, c = e - p * C;
+      // p < h2: (u, d) = (a + b, a - b); odd n, p = h2: the middle level u = a, d = 0
+      U[p * LD + c] = (T)(a[u] + b[u]);
+      D[p * LD + c] = (T)(p < h2 ? a[u] - b[u] : 0.0);
+    }
   }
   __syncthreads();
 
