@@ -33,8 +33,13 @@
  *   Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *     device work is enqueued on it.  smr_setup and the solves synchronise it before
  *     returning; the apply/build/grad calls are asynchronous.
- *   Concurrency: one call in flight per plan (a plan owns its workspace).  Distinct
- *     plans with distinct workspaces are independent.
+ *   Concurrency: one call in flight per plan (a plan owns its workspace, its captured
+ *     iterations and its pinned status buffer).  Calls on distinct plans with distinct
+ *     workspaces are independent and may run from different threads.  The batched solves
+ *     share one capture stream, graph cache and pinned status buffer per device; the
+ *     library serialises them (a batched call waits for any other batched call on the same
+ *     device to return).  smr_profile_enable / smr_profile_read are process-wide and not
+ *     thread-safe (diagnostics only).
  *   Errors: every call returns an smr_status; no exception crosses the ABI.  On any
  *     status other than SMR_OK a human-readable reason is available from
  *     smr_last_error() (thread-local, valid until the next call on the thread).
@@ -181,8 +186,10 @@ smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans,
  * general path.  plans, d_b, d_x and infos_host are host
  * arrays of length count; d_x0 is a host array of length count or NULL (every x0 = 0);
  * d_b[i] / d_x0[i] / d_x[i] follow the conventions of smr_minres_solve.
- * d_ws: caller-owned device workspace of smr_batch_workspace_size bytes.  Returns SMR_OK when
- * every instance converged, else the first failing status (each info holds its own). */
+ * d_ws: caller-owned device workspace of smr_batch_workspace_size bytes.  Every instance
+ * iterates in its own plan's workspace, so a plan may appear only once per call (SMR_EINVAL
+ * otherwise, before any work is enqueued).  Returns SMR_OK when every instance converged,
+ * else the first failing status (each info holds its own). */
 smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
                                     const double *const *d_b, const double *const *d_x0,
                                     double *const *d_x, double rtol, int32_t maxit, void *d_ws,
@@ -194,7 +201,8 @@ smr_status smr_solve_adjoint(const smr_plan *plan, const double *d_g, double *d_
                              double rtol, int32_t maxit, smr_info *info_host, void *stream);
 
 /* Batched adjoint solves T_i^T lambda_i = g_i for `count` plans (same flip-solve-flip as
- * smr_solve_adjoint, iterating together like smr_minres_solve_batched; same workspace). */
+ * smr_solve_adjoint, iterating together like smr_minres_solve_batched; same workspace; each
+ * plan at most once). */
 smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans,
                                      const double *const *d_g, double *const *d_lambda, double rtol,
                                      int32_t maxit, void *d_ws, size_t ws_bytes, smr_info *infos_host,

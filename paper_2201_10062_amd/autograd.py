@@ -16,6 +16,39 @@ import torch
 from .smr import Batch, Plan
 
 
+# Plans and batch of the latest (dim, N, n, theta, precond, batch size, device): a call with the
+# same coefficient reuses them as they are; a new coefficient rebuilds the plans' tables in the
+# same workspaces with the same column-tile widths (no allocation, no tile timing) and keeps the
+# batch workspace, so the batched solve replays its captured iterations.
+_CACHE: dict = {}
+
+
+def _plans_for(dim, N, n, theta, precond, B, a_host, dev):
+    key = (dim, N, n, float(theta), precond, B, str(dev))
+    a_bytes = a_host.tobytes()
+    ent = _CACHE.get(key)
+    if ent is not None and ent["a"] == a_bytes:
+        return ent["plans"], ent["batch"]
+    old_plans = ent["plans"] if ent is not None else [None] * B
+    plans = []
+    for old in old_plans:
+        ws = cols = None
+        if old is not None:
+            ws, cols = old.raw_workspace, (old.tile_cols or None)
+            old.release()
+        plans.append(Plan(dim, N, n, theta=theta, a_nodal=a_host, precond=precond, device=dev,
+                          workspace=ws, tile_cols=cols))
+    batch = Batch(plans, workspace=ent["batch"].raw_workspace if ent is not None else None)
+    _CACHE.clear()
+    _CACHE[key] = {"a": a_bytes, "plans": plans, "batch": batch}
+    return plans, batch
+
+
+def clear_cache():
+    """Drop the cached plans (their workspaces are freed with them)."""
+    _CACHE.clear()
+
+
 class HeatSolve(torch.autograd.Function):
     """u = T(a)^{-1} f_H(f, u0).  f: (B, n+1, m) float64 on the GPU; a_nodal: (N+2)^dim
     nodal coefficient (float64, any device); u0: (m,) or None.  Returns u of shape (B, n, m)."""
@@ -25,13 +58,11 @@ class HeatSolve(torch.autograd.Function):
         if f.dim() == 2:
             f = f.unsqueeze(0)
         B = f.shape[0]
-        a_host = a_nodal.detach().to("cpu", torch.float64).numpy().reshape((N + 2,) * dim)
+        a_host = np.ascontiguousarray(a_nodal.detach().to("cpu", torch.float64).numpy().reshape((N + 2,) * dim))
         dev = f.device
-        plans = [Plan(dim, N, n, theta=theta, a_nodal=np.ascontiguousarray(a_host), precond=precond, device=dev)
-                 for _ in range(B)]
+        plans, batch = _plans_for(dim, N, n, theta, precond, B, a_host, dev)
         u0c = None if u0 is None else u0.detach().contiguous().to(dev, torch.float64)
         bs = [p.build_rhs(f[i].contiguous().reshape(-1), u0c) for i, p in enumerate(plans)]
-        batch = Batch(plans)
         xs, infos = batch.solve(bs, rtol=rtol, maxit=maxit)
         u = torch.stack(xs).reshape(B, n, -1)
         ctx.plans, ctx.batch, ctx.rtol, ctx.maxit = plans, batch, rtol, maxit
@@ -43,6 +74,9 @@ class HeatSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gu):
+        if any(p.handle is None for p in ctx.plans):
+            raise RuntimeError("the plans of this solve were rebuilt by a later forward call with another "
+                               "coefficient; run backward before the next forward with a new coefficient")
         u, u0c = ctx.saved_tensors
         B = u.shape[0]
         gs = [gu[i].contiguous().reshape(-1).to(torch.float64) for i in range(B)]

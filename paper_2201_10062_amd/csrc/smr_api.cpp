@@ -13,6 +13,7 @@
 #include <string>
 #include <map>
 #include <mutex>
+#include <unordered_set>
 #include <vector>
 
 #include "smr_internal.h"
@@ -567,6 +568,7 @@ smr_status smr_destroy(smr_plan *plan) {
     if (p.snap) hipHostFree(p.snap);
     for (hipEvent_t e : p.snap_ev)
       if (e) hipEventDestroy(e);
+    if (p.cap) hipStreamDestroy(p.cap);
   }
   delete plan;
   return SMR_OK;
@@ -681,12 +683,12 @@ smr_status ensure_snapshots(const Plan &p) {
   return SMR_OK;
 }
 
-// Stream that graphs are captured on (the caller's stream may be the legacy default stream,
-// which cannot be captured); default priority, never used to run work.
-hipStream_t capture_stream() {
-  static hipStream_t cs = nullptr;
-  if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
-  return cs;
+// Graphs are captured on a stream of their own (the caller's stream may be the legacy default
+// stream, which cannot be captured); default priority, never used to run work.  A plan owns
+// the one its single solves capture on (made on first use, destroyed with the plan).
+hipStream_t plan_capture_stream(const Plan &p) {
+  if (!p.cap && hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking) != hipSuccess) p.cap = nullptr;
+  return p.cap;
 }
 
 // Six consecutive steady launches j = 6..11 of the sine-basis solve (with the per-level
@@ -695,7 +697,7 @@ hipStream_t capture_stream() {
 // launches 6k..6k+5 for every k >= 1.  The vectors are the plan's own (b^ in T1, x^ in T2).
 smr_status ensure_steady_graph(const Plan &p, double *Xh, const double *Bh) {
   if (p.steady6) return SMR_OK;
-  hipStream_t cs = capture_stream();
+  hipStream_t cs = plan_capture_stream(p);
   if (!cs) return fail(SMR_EDEVICE, "no capture stream");
   Ctx cc{&p, cs};
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -719,52 +721,68 @@ smr_status ensure_steady_graph(const Plan &p, double *Xh, const double *Bh) {
   return SMR_OK;
 }
 
-// Captured steady iterations of batched solves, keyed by the batch workspace address and the
-// class layout of the launches (a few recent layouts are kept).
-template <typename F>
-hipGraphExec_t batch_graph(const std::vector<long> &key, F &&enqueue) {
+// Host-side state of the batched solves on one device: the capture stream, the captured steady
+// iterations (keyed by the batch workspace address and the class layout of the launches; a few
+// recent layouts are kept) and the pinned status snapshots.  Every batched call holds `mu` from
+// start to end, so concurrent batched calls on one device run one after another and never
+// share a snapshot buffer, a capture or a cached graph while another call uses it.
+struct BatchState {
+  std::mutex mu;
+  hipStream_t cs = nullptr;
   struct Entry {
     std::vector<long> key;
     hipGraphExec_t ex;
   };
-  static std::vector<Entry> cache;
-  for (const Entry &en : cache)
+  std::vector<Entry> cache;
+  Scal *snap = nullptr;        // two slots of `cap` instances
+  int cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+BatchState &batch_state() {
+  static std::mutex mu;
+  static std::map<int, BatchState> per_device;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  return per_device[dev];   // std::map never moves its elements
+}
+
+// The steady-iteration graph of a batch layout (captured on first use); bs.mu must be held.
+template <typename F>
+hipGraphExec_t batch_graph(BatchState &bs, const std::vector<long> &key, F &&enqueue) {
+  for (const BatchState::Entry &en : bs.cache)
     if (en.key == key) return en.ex;
-  hipStream_t cs = capture_stream();
-  if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-  const hipError_t e = enqueue(cs);
+  if (!bs.cs && hipStreamCreateWithFlags(&bs.cs, hipStreamNonBlocking) != hipSuccess) bs.cs = nullptr;
+  if (!bs.cs || hipStreamBeginCapture(bs.cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  const hipError_t e = enqueue(bs.cs);
   hipGraph_t g = nullptr;
-  const hipError_t e2 = hipStreamEndCapture(cs, &g);
+  const hipError_t e2 = hipStreamEndCapture(bs.cs, &g);
   hipGraphExec_t ex = nullptr;
   if (e == hipSuccess && e2 == hipSuccess && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
   if (g) hipGraphDestroy(g);
   if (!ex) return nullptr;
-  if (cache.size() >= 8) {
-    hipGraphExecDestroy(cache.front().ex);
-    cache.erase(cache.begin());
+  if (bs.cache.size() >= 8) {
+    hipGraphExecDestroy(bs.cache.front().ex);   // no other call can be replaying it (bs.mu)
+    bs.cache.erase(bs.cache.begin());
   }
-  cache.push_back(Entry{key, ex});
+  bs.cache.push_back(BatchState::Entry{key, ex});
   return ex;
 }
 
-// Pinned host status snapshots for batched solves (two slots of `cap` instances).
-struct BatchSnap {
-  Scal *h = nullptr;
-  int cap = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-};
-BatchSnap &batch_snapshots(int count) {
-  static BatchSnap bs;
+// Pinned host status snapshots for `count` instances (two slots); bs.mu must be held, and the
+// previous call's copies into the old buffer have completed (each call synchronises before
+// it returns).
+bool batch_snapshots(BatchState &bs, int count) {
   if (count > bs.cap) {
-    if (bs.h) hipHostFree(bs.h);
-    bs.h = nullptr;
+    if (bs.snap) hipHostFree(bs.snap);
+    bs.snap = nullptr;
     bs.cap = 0;
-    if (hipHostMalloc((void **)&bs.h, 2 * sizeof(Scal) * (size_t)count, hipHostMallocDefault) == hipSuccess)
+    if (hipHostMalloc((void **)&bs.snap, 2 * sizeof(Scal) * (size_t)count, hipHostMallocDefault) == hipSuccess)
       bs.cap = count;
   }
   for (hipEvent_t &e : bs.ev)
     if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
-  return bs;
+  return bs.snap && bs.ev[0] && bs.ev[1];
 }
 
 // Constant coefficients: the whole MINRES runs in the spatial sine basis with one fused
@@ -1043,19 +1061,23 @@ smr_status smr_batch_workspace_size(int32_t count, const smr_plan *const *plans,
   return SMR_OK;
 }
 
-smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans, const double *const *b,
-                                    const double *const *x0, double *const *x, double rtol, int32_t maxit,
-                                    void *d_ws, size_t ws_bytes, smr_info *infos, void *stream) {
-  if (count < 0 || (count > 0 && (!plans || !b || !x || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
-  if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
-  size_t need = 0;
-  smr_batch_workspace_size(count, plans, &need);
-  if (count > 0 && (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < need))
-    return fail(SMR_EWORKSPACE, "batch workspace missing, misaligned or smaller than %zu bytes", need);
-  for (int i = 0; i < count; ++i) {
-    if (!plans[i] || !b[i] || !x[i]) return fail(SMR_EINVAL, "instance %d: NULL plan or vector", i);
-    if (b[i] == x[i]) return fail(SMR_EINVAL, "instance %d: b and x must be distinct", i);
-  }
+}  // extern "C"
+
+namespace smr {
+namespace {
+
+// Every instance of a batch iterates in its own plan's vectors and scalars, so a plan may
+// appear only once.
+smr_status check_distinct_plans(int count, const smr_plan *const *plans) {
+  std::unordered_set<const smr_plan *> seen;
+  for (int i = 0; i < count; ++i)
+    if (!seen.insert(plans[i]).second) return fail(SMR_EINVAL, "instance %d: plan repeated within the batch", i);
+  return SMR_OK;
+}
+
+smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *const *plans, const double *const *b,
+                                const double *const *x0, double *const *x, double rtol, int32_t maxit, void *d_ws,
+                                smr_info *infos, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   SpecP *d_table = (SpecP *)d_ws;
   const size_t c1 = (size_t)std::max(count, 1);
@@ -1174,14 +1196,18 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
       std::vector<long> key{(long)(uintptr_t)d_ws};
       for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
       for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec});
-      g6 = batch_graph(key, [&](hipStream_t cs) {
+      g6 = batch_graph(bst, key, [&](hipStream_t cs) {
         hipError_t e = hipSuccess;
         for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration(cs, j);
         return e;
       });
     }
-    BatchSnap &bs = batch_snapshots(ns);
-    if (!bs.h) return fail(SMR_EDEVICE, "pinned status buffer");
+    if (!batch_snapshots(bst, ns)) return fail(SMR_EDEVICE, "pinned status buffer");
+    struct {
+      Scal *h;
+      int cap;
+      hipEvent_t *ev;
+    } bs{bst.snap, bst.cap, bst.ev};
     std::vector<Scal> hs(ns);
     int issued = 0;
     const int last = maxit + 2;
@@ -1252,6 +1278,31 @@ smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans,
   return first_bad;
 }
 
+}  // namespace
+}  // namespace smr
+
+extern "C" {
+
+smr_status smr_minres_solve_batched(int32_t count, const smr_plan *const *plans, const double *const *b,
+                                    const double *const *x0, double *const *x, double rtol, int32_t maxit,
+                                    void *d_ws, size_t ws_bytes, smr_info *infos, void *stream) {
+  if (count < 0 || (count > 0 && (!plans || !b || !x || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
+  if (!(rtol > 0.0) || maxit < 0) return fail(SMR_EINVAL, "need rtol > 0 and maxit >= 0");
+  size_t need = 0;
+  smr_batch_workspace_size(count, plans, &need);
+  if (count > 0 && (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < need))
+    return fail(SMR_EWORKSPACE, "batch workspace missing, misaligned or smaller than %zu bytes", need);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !b[i] || !x[i]) return fail(SMR_EINVAL, "instance %d: NULL plan or vector", i);
+    if (b[i] == x[i]) return fail(SMR_EINVAL, "instance %d: b and x must be distinct", i);
+  }
+  smr_status st = check_distinct_plans(count, plans);
+  if (st != SMR_OK) return st;
+  BatchState &bst = batch_state();
+  std::lock_guard<std::mutex> lock(bst.mu);
+  return solve_batched_locked(bst, count, plans, b, x0, x, rtol, maxit, d_ws, infos, stream);
+}
+
 smr_status smr_solve_adjoint(const smr_plan *pl, const double *g, double *lam, double rtol, int32_t maxit,
                              smr_info *info, void *stream) {
   smr_status st = check_plan(pl);
@@ -1276,6 +1327,10 @@ smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans
                                      double *const *lam, double rtol, int32_t maxit, void *d_ws, size_t ws_bytes,
                                      smr_info *infos, void *stream) {
   if (count < 0 || (count > 0 && (!plans || !g || !lam || !infos))) return fail(SMR_EINVAL, "bad batch arguments");
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) return fail(SMR_EINVAL, "instance %d: NULL plan", i);
+  smr_status st0 = check_distinct_plans(count, plans);
+  if (st0 != SMR_OK) return st0;
   hipStream_t s = (hipStream_t)stream;
   std::vector<const double *> bs(count);
   for (int i = 0; i < count; ++i) {

@@ -70,6 +70,7 @@ struct Plan {
   mutable hipGraphExec_t steady6 = nullptr;          // six captured steady iterations
   mutable Scal *snap = nullptr;                      // two pinned host status snapshots
   mutable hipEvent_t snap_ev[2] = {nullptr, nullptr};
+  mutable hipStream_t cap = nullptr;                 // stream the steady graph is captured on
   Scal *sc_host;              // pinned host mirror
   size_t ws_bytes;
 };

@@ -166,7 +166,9 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda", general_path: bool = False, tile_cols=None):
+                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None):
+        """workspace: a uint8 device tensor to build the plan in (e.g. the ``raw_workspace``
+        of a plan that is no longer used); a new one is allocated when it is None or too small."""
         import torch
         self.lib = load()
         self.dim, self.N, self.n = dim, N, n
@@ -179,7 +181,10 @@ class Plan:
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
-        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        raw = workspace
+        if raw is None or raw.device != self.device or raw.dtype != torch.uint8 or \
+                raw.numel() < self.ws_bytes + (-raw.data_ptr()) % 256:
+            raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         self._raw = raw
         self.ws = raw[off:off + self.ws_bytes]
@@ -196,11 +201,21 @@ class Plan:
         _check(self.lib.smr_tile_cols(self.handle, ctypes.byref(c)))
         return c.value
 
-    def __del__(self):
+    @property
+    def raw_workspace(self):
+        """The device tensor holding the workspace (reusable by a later plan once this one is
+        released)."""
+        return self._raw
+
+    def release(self):
+        """Destroy the host-side plan now (its workspace tensor stays valid for reuse)."""
         h = getattr(self, "handle", None)
         if h is not None and h.value:
             self.lib.smr_destroy(h)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.release()
 
     # --- helpers
     def _vec(self, t, n_levels=None):
@@ -280,7 +295,9 @@ class Plan:
 class Batch:
     """A fixed set of plans solved together; owns the batch workspace (descriptor table)."""
 
-    def __init__(self, plans: Sequence[Plan]):
+    def __init__(self, plans: Sequence[Plan], workspace=None):
+        """workspace: a uint8 device tensor to reuse (e.g. ``raw_workspace`` of an earlier
+        batch of the same plan layout, whose captured iterations are then replayed)."""
         import torch
         self.plans = list(plans)
         n = len(self.plans)
@@ -289,10 +306,17 @@ class Batch:
         nbytes = ctypes.c_size_t(0)
         _check(load().smr_batch_workspace_size(n, self._hp, ctypes.byref(nbytes)))
         dev = self.plans[0].ws.device if n else torch.device("cuda")
-        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        raw = workspace
+        if raw is None or raw.device != dev or raw.dtype != torch.uint8 or \
+                raw.numel() < nbytes.value + (-raw.data_ptr()) % 256:
+            raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
         off = (-raw.data_ptr()) % 256
         self._raw = raw
         self.ws = raw[off:off + nbytes.value]
+
+    @property
+    def raw_workspace(self):
+        return self._raw
 
     def solve(self, bs, x0s=None, rtol=1e-8, maxit=500):
         """Solve every (plan, b) pair from x0s (None: every x0 = 0); returns (xs, infos)."""

@@ -99,3 +99,31 @@ def test_inverse_problem_full_size_sampled():
     gf, ga, _ = _oracle_grads(N, n, 1.0, a1, f, u0, uobs)
     assert float(np.abs(at.grad.cpu().numpy() - ga).max() / np.abs(ga).max()) < 1e-7
     assert float(np.abs(ft.grad.cpu().numpy() - gf).max() / np.abs(gf).max()) < 1e-7
+
+
+def test_plans_cached_across_calls():
+    """Repeated forward/backward passes reuse the cached plans and batch for the same
+    coefficient, and rebuild the plan tables in the same workspaces for a new one; every pass's
+    gradient still equals the oracle's."""
+    from paper_2201_10062_amd import autograd as ag
+    dev = _dev()
+    N, n, B, theta = 7, 8, 2, 1.0
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal((B, n + 1, N * N))
+    uobs = rng.standard_normal((B, n, N * N))
+    ag.clear_cache()
+    seen = []
+    for a in (np.ones((N + 2, N + 2)), np.ones((N + 2, N + 2)), rng.uniform(0.7, 1.3, (N + 2, N + 2))):
+        ft = torch.tensor(f, device=dev, requires_grad=True)
+        at = torch.tensor(a, device=dev, requires_grad=True)
+        u = ag.heat_solve(ft, at, None, theta=theta, rtol=1e-13)
+        ((u - torch.tensor(uobs, device=dev)) ** 2).sum().backward()
+        ent = next(iter(ag._CACHE.values()))
+        seen.append((ent["plans"], [p.raw_workspace.data_ptr() for p in ent["plans"]],
+                     ent["batch"].raw_workspace.data_ptr()))
+        gf, ga, _ = _oracle_grads(N, n, theta, a, f, np.zeros(N * N), uobs)
+        assert float(np.abs(at.grad.cpu().numpy() - ga).max() / np.abs(ga).max()) < 1e-9
+        assert float(np.abs(ft.grad.cpu().numpy() - gf).max() / np.abs(gf).max()) < 1e-9
+    assert seen[1][0] is seen[0][0]                      # same coefficient: the same plans
+    assert seen[2][0] is not seen[0][0]                  # new coefficient: new plans ...
+    assert seen[2][1] == seen[0][1] and seen[2][2] == seen[0][2]   # ... in the same workspaces

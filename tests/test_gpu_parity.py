@@ -443,3 +443,18 @@ def test_stop_points_and_transform_ahead(kind, N, n):
         x, info = g.solve(_t(b), rtol=1e-300, maxit=k)
         assert info["iters"] == k and info["status"] == "enotconv", (k, info)
         assert rel(_n(x), ref.x) < 1e-9, k
+
+
+def test_batch_rejects_a_repeated_plan():
+    """Every batch instance iterates in its own plan's vectors, so a plan may appear once."""
+    from paper_2201_10062_amd import Batch, Plan, SmrError
+    _dev()
+    p = Plan(2, 7, 8)
+    q = Plan(2, 7, 8)
+    b = _t(np.ones(8 * 49))
+    with pytest.raises(SmrError, match="repeated"):
+        Batch([p, q, p]).solve([b, b, b])
+    with pytest.raises(SmrError, match="repeated"):
+        Batch([p, p]).solve_adjoint([b, b])
+    xs, infos = Batch([p, q]).solve([b, b], rtol=1e-8)
+    assert all(i["status"] == "ok" for i in infos)
