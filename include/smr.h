@@ -163,6 +163,20 @@ smr_status smr_apply_A(const smr_plan *plan, const double *d_x, double *d_y, voi
  * (d_z == d_v) is allowed. */
 smr_status smr_apply_P_inv(const smr_plan *plan, const double *d_v, double *d_z, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): d_z = P^{-1} d_v exactly as
+ * smr_apply_P_inv (same kernels, same result bit for bit), but its intermediate vectors live
+ * in a static device array owned by the library, SMR_STATIC_SCRATCH_BYTES per GPU, held until
+ * the process ends, instead of the plan's workspace.  The call allocates nothing.  It needs
+ * 2 (P_H, Phat) or 4 (P_theta) vectors of n*m doubles, each rounded up to 256 bytes, within
+ * that size (SMR_EINVAL beyond it; n*m <= 4194304 for P_H, 2097152 for P_theta); P = I needs
+ * none.  Every call on a GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, threads or processes' streams on this library instance) race and
+ * corrupt each other's results; serialise them, e.g. on one stream.  Asynchronous; in-place
+ * (d_z == d_v) is allowed. */
+#define SMR_STATIC_SCRATCH_BYTES (64ull << 20)
+smr_status smr_apply_P_inv_static(const smr_plan *plan, const double *d_v, double *d_z, void *stream);
+
 /* Preconditioned MINRES on Y T x = Y b (b = the unpermuted f_H, n*m device).  d_x0: the
  * initial guess (n*m device, read only, may equal d_x) or NULL for x0 = 0, the choice of
  * the paper's experiments (Sec. 5), which also skips transforming a guess.  d_x (n*m, not

@@ -584,10 +584,16 @@ smr_status check_plan(const smr_plan *pl) {
   return SMR_OK;
 }
 
+// Intermediate vectors of one P^{-1} application (n*m doubles each; t3, t4 for P_theta only).
+struct PinvBufs {
+  double *t1, *t2, *t3, *t4;
+};
+PinvBufs plan_bufs(const Plan &p) { return PinvBufs{p.T1, p.T2, p.T3, p.T4}; }
+
 // z = P^{-1} v; gamma^2 partials (Parseval or an explicit dot) into part2, count in *nb2.
 // f32: the time transforms on the float32 matrix cores (the solve of an SMR_FP32 plan)
 smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, double *part2, int *nb2,
-                      const Scal *gate, bool f32) {
+                      const Scal *gate, bool f32, const PinvBufs &tb) {
   Ctx c{&p, s};
   if (p.precond == SMR_P_NONE) {
     HIP_TRY(hipMemcpyAsync(z, v, p.len * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -595,15 +601,15 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
     return SMR_OK;
   }
   if (p.precond == SMR_P_H) {
-    LAUNCH(PROF_DST, launch_dst(c, 0, v, p.T1, p.n, 0, gate));
-    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T1, p.T1, p.n, 0, gate));
-    LAUNCH(PROF_TIME, launch_time(c, p.T1, p.T2, 1, part2, nb2, gate, f32));
-    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, p.T2, p.T2, p.n, 0, gate));
-    LAUNCH(PROF_DST, launch_dst(c, 0, p.T2, z, p.n, 0, gate));
+    LAUNCH(PROF_DST, launch_dst(c, 0, v, tb.t1, p.n, 0, gate));
+    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, tb.t1, tb.t1, p.n, 0, gate));
+    LAUNCH(PROF_TIME, launch_time(c, tb.t1, tb.t2, 1, part2, nb2, gate, f32));
+    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, tb.t2, tb.t2, p.n, 0, gate));
+    LAUNCH(PROF_DST, launch_dst(c, 0, tb.t2, z, p.n, 0, gate));
     return SMR_OK;
   }
   // P_theta with k-step Chebyshev per time mode: res = T1, x = T2, dvec = T3, tmp = T4
-  LAUNCH(PROF_TIME, launch_time(c, v, p.T1, 0, nullptr, nullptr, gate, f32));
+  LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
   auto binv = [&](const double *in, double *out) -> smr_status {
     if (p.dim == 1) {
@@ -617,22 +623,22 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
     }
     return SMR_OK;
   };
-  smr_status st = binv(p.T1, p.T4);
+  smr_status st = binv(tb.t1, tb.t4);
   if (st != SMR_OK) return st;
-  LAUNCH(PROF_VEC, launch_cheb_axpy(c, p.T2, p.T3, p.T4, 0.0, 1.0 / cc, 1, gate));
+  LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, 0.0, 1.0 / cc, 1, gate));
   if (dd > 0.0) {
     const double s1 = cc / dd;
     double rho = 1.0 / s1;
     for (int i = 1; i < p.cheb_k; ++i) {
-      LAUNCH(PROF_STENCIL, launch_cheb_resid(c, p.T1, p.T3, gate));
-      st = binv(p.T1, p.T4);
+      LAUNCH(PROF_STENCIL, launch_cheb_resid(c, tb.t1, tb.t3, gate));
+      st = binv(tb.t1, tb.t4);
       if (st != SMR_OK) return st;
       const double rn = 1.0 / (2.0 * s1 - rho);
-      LAUNCH(PROF_VEC, launch_cheb_axpy(c, p.T2, p.T3, p.T4, rn * rho, 2.0 * rn / dd, 0, gate));
+      LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, rn * rho, 2.0 * rn / dd, 0, gate));
       rho = rn;
     }
   }
-  LAUNCH(PROF_TIME, launch_time(c, p.T2, z, 0, nullptr, nullptr, gate, f32));
+  LAUNCH(PROF_TIME, launch_time(c, tb.t2, z, 0, nullptr, nullptr, gate, f32));
   if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
   return SMR_OK;
 }
@@ -949,7 +955,7 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
   // v_1 = Y b - Y T x0, ||v_1||^2, ||b||^2
   LAUNCH(PROF_STENCIL, launch_apply_YT(c, x, nullptr, p.V[1], b, part, &nb, nullptr));
   const bool f32 = p.pprec == SMR_FP32;
-  smr_status st = apply_pinv(p, s, p.V[1], p.Z[0], part2, &nb2, nullptr, f32);
+  smr_status st = apply_pinv(p, s, p.V[1], p.Z[0], part2, &nb2, nullptr, f32, plan_bufs(p));
   if (st != SMR_OK) return st;
   LAUNCH(PROF_SCALAR, launch_scalar_step(c, 0, part, nb, part2, nb2));
   int cv = 1, cz = 0, cw = 1;   // v_j = V[cv], v_{j-1} = V[1-cv]; z_j = Z[cz]; w_{j-1} = W[cw], w_{j-2} = W[1-cw]
@@ -970,7 +976,7 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
       LAUNCH(PROF_STENCIL, launch_apply_YT(c, zj, zs, p.Q, nullptr, part, &nb, gate));
       LAUNCH(PROF_SCALAR, launch_scalar_step(c, 1, part, nb, nullptr, 0));
       LAUNCH(PROF_VEC, launch_vupdate(c, p.Q, vj, vo, gate));
-      st = apply_pinv(p, s, vo, zn, part2, &nb2, gate, f32);
+      st = apply_pinv(p, s, vo, zn, part2, &nb2, gate, f32, plan_bufs(p));
       if (st != SMR_OK) return st;
       LAUNCH(PROF_SCALAR, launch_scalar_step(c, 2, part2, nb2, part2, nb2));
       LAUNCH(PROF_VEC, launch_wxupdate(c, zj, w2, w1, x, gate));
@@ -1040,7 +1046,60 @@ smr_status smr_apply_P_inv(const smr_plan *pl, const double *v, double *z, void 
   smr_status st = check_plan(pl);
   if (st != SMR_OK) return st;
   if (!v || !z) return fail(SMR_EINVAL, "v and z must be non-NULL");
-  return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr, false);
+  return apply_pinv(pl->p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr, false, plan_bufs(pl->p));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- static scratch
+// Intermediate vectors of smr_apply_P_inv_static: a library-owned array in device memory, one
+// copy per GPU, alive until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name only stands in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[SMR_STATIC_SCRATCH_BYTES];
+
+namespace smr {
+namespace {
+
+smr_status static_scratch(double **out) {
+  static std::mutex mu;
+  static std::map<int, void *> ptr;   // device -> address of its copy of `scratch`
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptr.find(dev);
+  if (it == ptr.end()) {
+    void *a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !a)
+      return fail(SMR_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    it = ptr.emplace(dev, a).first;
+  }
+  *out = (double *)it->second;
+  return SMR_OK;
+}
+
+}  // namespace
+}  // namespace smr
+
+extern "C" {
+
+smr_status smr_apply_P_inv_static(const smr_plan *pl, const double *v, double *z, void *stream) {
+  smr_status st = check_plan(pl);
+  if (st != SMR_OK) return st;
+  if (!v || !z) return fail(SMR_EINVAL, "v and z must be non-NULL");
+  const Plan &p = pl->p;
+  const int nvec = p.precond == SMR_P_H ? 2 : p.precond == SMR_P_THETA_CHEB ? 4 : 0;
+  const size_t vbytes = align256(p.len * sizeof(double));
+  if ((size_t)nvec * vbytes > (size_t)SMR_STATIC_SCRATCH_BYTES)
+    return fail(SMR_EINVAL, "P^{-1} of this plan needs %d vectors of %zu bytes, more than the %llu bytes of static "
+                "scratch", nvec, vbytes, (unsigned long long)SMR_STATIC_SCRATCH_BYTES);
+  double *base = nullptr;
+  st = static_scratch(&base);
+  if (st != SMR_OK) return st;
+  const size_t stride = vbytes / sizeof(double);
+  const PinvBufs tb{base, base + stride, nvec == 4 ? base + 2 * stride : nullptr, nvec == 4 ? base + 3 * stride : nullptr};
+  return apply_pinv(p, (hipStream_t)stream, v, z, nullptr, nullptr, nullptr, false, tb);
 }
 
 smr_status smr_minres_solve(const smr_plan *pl, const double *b, const double *x0, double *x, double rtol,

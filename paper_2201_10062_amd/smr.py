@@ -28,7 +28,9 @@ EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
     "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_solve_adjoint_batched", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error", "smr_tile_cols",
+    "smr_apply_P_inv_static",
 )
+STATIC_SCRATCH_BYTES = 64 << 20   # SMR_STATIC_SCRATCH_BYTES
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5, "kslice": 6}
 
 
@@ -77,6 +79,7 @@ def load() -> ctypes.CDLL:
     lib.smr_build_rhs.argtypes = [P, P, P, P, P]
     lib.smr_apply_A.argtypes = [P, P, P, P]
     lib.smr_apply_P_inv.argtypes = [P, P, P, P]
+    lib.smr_apply_P_inv_static.argtypes = [P, P, P, P]
     lib.smr_minres_solve.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SmrInfo), P]
     lib.smr_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]
     lib.smr_minres_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P),
@@ -246,6 +249,14 @@ class Plan:
         self._vec(v)
         z = self.empty() if out is None else self._vec(out)
         _check(self.lib.smr_apply_P_inv(self.handle, _ptr(v), _ptr(z), _stream()))
+        return z
+
+    def apply_P_inv_static(self, v, out=None):
+        """P^{-1} v with the intermediate vectors in the library's static device scratch
+        (allocates nothing in the library; calls overlapping on one GPU race)."""
+        self._vec(v)
+        z = self.empty() if out is None else self._vec(out)
+        _check(self.lib.smr_apply_P_inv_static(self.handle, _ptr(v), _ptr(z), _stream()))
         return z
 
     def solve(self, b, x0=None, rtol=1e-8, maxit=500, raise_on_fail=True):
