@@ -1,23 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the sine-transform-preconditioned MINRES hot path on one MI355X.
 
-Workload (the 2D Crank-Nicolson configuration): heat equation on the unit square,
-a = 1, N = 127 interior points per axis (m = 16129), n = 256 Crank-Nicolson steps,
-T = 1, f from u = sin(pi x) sin(pi y) e^{-t} plus N(0, 1e-3^2) noise (seed 0),
-P_H preconditioner (3D sine transform + diagonal), plain float64.
+Headline workload: the 64-instance BDF2 batch of uneven sizes (instance i: N = (31, 63,
+127)[i % 3], n = (64, 128, 256)[(i // 3) % 3], a = 1 or 1 + 0.5 cos(pi x) when (i // 9) is
+odd, b_i ~ N(0, 1) from one seed-2 stream, 66.1 M unknowns), solved to a true relative
+residual of 1e-8 from x0 = 0 with Phat (Phat(Kbar) for the variable coefficient).  One step
+is one solve of the whole batch in the mixed + batched form: float64 MINRES, matvec and
+residual, float32 time transform and z, every iteration one per-level matvec launch per N
+class and one fused launch per time-size class over all instances.  `value` is MINRES
+iterations per second summed over the instances (inputs resident in HBM before the timed
+region), `ms_per_step` the time-to-1e-8 of the batch; the plain float64 form (the same
+plans in float64, instances one after another on one stream) is timed beside it.  The two
+batched kernels are timed live with the library's HIP events on their launch stream over
+the timed steps and priced against their rooflines; the FP64 CPU oracle is timed on a
+bounded sample of the instances (one thread and all cores).
 
-One step = assemble f_H on the GPU and run preconditioned MINRES from x0 = 0 to a true
-relative residual of 1e-8.  The reported value is MINRES iterations per second over the
-K timed steps (inputs resident in HBM before the timed region); time-to-1e-8 is reported
-beside it.  The dominant kernel (the fused sine-basis MINRES iteration) is timed live with
-HIP events on its launch stream and priced against the HBM roofline (and, beside it, its
-two folded time GEMMs against the FP64 matrix peak).
+Extra keys: the 2D Crank-Nicolson workload (N = 127, n = 256) with its fused kernel's
+roofline, the 1D manufactured solution, the largest row of each of the paper's Tables 1-4,
+the N = 255, n = 512 variable-coefficient solves, and the differentiable 16-source solve.
 
-Beside it: the 64-instance BDF2 batch of uneven sizes, plain float64 (instances one after
-another) against mixed precision + batched (float32 time transform, one launch per size
-class per iteration), time-to-1e-8 for the whole batch.
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
@@ -34,27 +36,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_FP64_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X dense FP64 vector peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_spec_cn2d_N127_n256.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc", "k_spec.hip")
-KERNEL_HDR = os.path.join(os.path.dirname(KERNEL_SRC), "mfma_tiles.h")   # its matrix-core tiles
+TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_k_spec_multi_bdf2_batch64.json")
+CSRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc")
 
 
-def kernel_hash() -> str:
-    """Hash of the fused kernel's sources (the kernel file and its matrix-core tile header)."""
+def kernel_hash(files=("k_spec.hip", "mfma_tiles.h")) -> str:
+    """Hash of a kernel's sources (the fused kernel's file and its matrix-core tile header)."""
     h = hashlib.sha256()
-    for path in (KERNEL_SRC, KERNEL_HDR):
-        with open(path, "rb") as fh:
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_entry():
-    """HBM bytes per launch of the time kernel from the committed rocprofv3 --pmc summary,
-    or None when the kernel source changed since the counters were taken."""
+def traffic_entry(path=TRAFFIC_FILE):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 --pmc summary, or None when
+    the kernel's source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -63,65 +66,263 @@ def traffic_entry():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(p, iters: int = 40):
-    """The FP64 CPU oracle timed on this host: the first `iters` MINRES iterations of
-    the same workload (single thread: scipy.fft workers=1, scipy.sparse)."""
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline_batch(probs, sample, rtol):
+    """The FP64 CPU oracle timed on this host on a bounded sample of the batch's instances
+    (the same seeded right-hand sides, zero initial guess, true-residual stop), once on one
+    thread and once with every core (scipy.fft workers and BLAS threads = os.cpu_count();
+    scipy.sparse products stay single-threaded).  Returns the baseline record and the oracle
+    solutions (for the error of the GPU forms)."""
+    import scipy.fft
+    from threadpoolctl import threadpool_limits
     from oracle.system import System
-    s = System(2, p.N, p.n, theta=p.theta)
-    fH = s.rhs(p.f, p.u0)
-    t0 = time.perf_counter()
-    r = s.solve(fH, rtol=1e-300, maxit=iters)
-    dt = time.perf_counter() - t0
-    return {"value": r.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r.iters} MINRES iterations of the N=127, n=256 Crank-Nicolson workload "
-                      f"(P_H, true residual each iteration), {dt:.1f} s on one host core"}
+    out = {"kind": "oracle", "unit": "iters/s", **cpu_info()}
+    sols = {}
+    for label, workers in (("single_thread", 1), ("all_cores", os.cpu_count() or 1)):
+        with threadpool_limits(limits=workers), scipy.fft.set_workers(workers):
+            t0 = time.perf_counter()
+            iters = 0
+            for i in sample:
+                q = probs[i]
+                o = System(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay)
+                r = o.solve(q.b.reshape(-1), rtol=rtol, maxit=1000)
+                iters += r.iters
+                sols[i] = r
+            dt = time.perf_counter() - t0
+        out[label] = {"value": iters / dt, "iters": iters, "seconds": dt, "threads": workers}
+    out["value"] = out["single_thread"]["value"]
+    out["cores"] = 1
+    out["sample"] = (f"instances {list(sample)} of the 64-instance BDF2 batch ({', '.join(probs[i].name for i in sample)}), "
+                     f"solved to rtol {rtol} from x0 = 0; value = single-thread iters/s, all-cores beside it")
+    return out, sols
 
 
-def batched_bdf2_leg(dev, warmup: int, steps: int, rtol: float):
+def batch_algorithmic(probs, infos, pprec_bytes):
+    """Algorithmic HBM bytes of the fused batched launches and bytes + flops of the per-level
+    matvec launches over one batched solve, from each instance's iteration and residual counts.
+    Fused launch, per degree of freedom (z in the transform precision, pprec_bytes = 4 for
+    float32): init 24 + z (read b^, write v_1, z_1, x = 0), first 16 + 2 z (read z_1 or
+    (T z_1)^, v_1; write v_2, z_2), steady 64 + 3 z (read z_j, z_{j-1}, v_j, v_{j-1}, w_{j-2},
+    w_{j-3}, x; write v, z, w, x) less the w's that do not exist in launches 2 and 3, + 8 for
+    each evaluated true residual (read b^); a variable coefficient reads (T z_j)^ (8) in place
+    of z_j and evaluates its residuals in the per-level kernel.  Per-level matvec (variable a,
+    launches 1 .. iters + 1): read z_j, write (T z_j)^ (z + 8), + 16 per evaluated residual
+    (read x, b^); flops: four one-dimensional sine transforms per point as packed complex
+    FFTs of M = 2 (N + 1) points, 2.5 M log2 M flops per line, the 5-point stencil with face
+    coefficients (13 per point) and the time combination (9 per point), twice when the
+    residual is evaluated."""
+    import math
+    z = pprec_bytes
+    spec_b = ks_b = ks_f = 0.0
+    for q, inf in zip(probs, infos):
+        dof = q.n * q.N * q.N
+        k, r = inf["iters"], inf["res_evals"]
+        var = q.ax is not None
+        steady = sum(64 + 3 * z + (8 - z if var else 0) - (16 if j == 2 else 8 if j == 3 else 0) for j in range(2, k + 2))
+        spec_b += dof * ((24 + z) + (16 + 2 * z + (8 - z if var else 0)) + steady + (0 if var else 8 * (r - 1)))
+        if var:
+            M = 2 * (q.N + 1)
+            per_level = 4 * q.N * 2.5 * M * math.log2(M) + 22 * q.N * q.N
+            ks_b += dof * ((z + 8) * (k + 1) + 16 * (r - 1))
+            ks_f += q.n * per_level * ((k + 1) + (r - 1))
+    return spec_b, ks_b, ks_f
+
+
+def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, profiled_only: bool = False):
     """The 64-instance BDF2 batch (uneven N in {31, 63, 127}, n in {64, 128, 256}, a = 1 or
-    1 + 0.5 cos(pi x), b ~ N(0, 1), seed 2): plain float64 (the same method, instances solved
-    back to back on one stream) against mixed + batched (float32 time transform, every
-    iteration one launch per size class over all instances).  Inputs resident in HBM."""
+    1 + 0.5 cos(pi x), b ~ N(0, 1), seed 2), inputs resident in HBM.  Mixed + batched (float64
+    MINRES, matvec and residual; float32 time transform and z; every iteration one per-level
+    matvec launch per N class and one fused launch per time-size class over all instances)
+    is the measured form; plain float64 (the same method, instances solved back to back on one
+    stream) beside it.  The kernel durations of the rooflines come from the same steps run a
+    second time with the library's per-launch HIP events on (launches in sequence); with
+    profiled_only only that pass runs (the command the rocprofv3 kernel trace is taken of)."""
     import torch
     import workloads as W
-    from paper_2201_10062_amd import Batch, Plan
+    from paper_2201_10062_amd import Batch, Plan, smr
     probs = W.bdf2_batch()
-    bs = [torch.from_numpy(p.b.reshape(-1)).to(dev) for p in probs]
-    plain = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, device=dev) for p in probs]
-    mixed = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, pprec="fp32", device=dev) for p in probs]
+    bs = [torch.from_numpy(q.b.reshape(-1)).to(dev) for q in probs]
+    plain = [] if profiled_only else [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, device=dev) for q in probs]
+    mixed = [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, pprec="fp32", device=dev) for q in probs]
     batch = Batch(mixed)
 
     def run_plain():
-        return [pl.solve(b, rtol=rtol, maxit=1000)[1] for pl, b in zip(plain, bs)]
+        return [pl.solve(b, rtol=rtol, maxit=1000) for pl, b in zip(plain, bs)]
 
     def run_mixed():
-        return batch.solve(bs, rtol=rtol, maxit=1000)[1]
+        xs, infos = batch.solve(bs, rtol=rtol, maxit=1000)
+        return list(zip(xs, infos))
 
-    def timed(fn):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
+    smr.profile_enable(profiled_only)       # profiled only: every launch in sequence, warm-up included
+    for _ in range(warmup):
+        run_mixed()
+        if not profiled_only:
+            run_plain()
+    torch.cuda.synchronize()
+    t_mixed = float("nan")
+    if not profiled_only:
         t0 = time.perf_counter()
         for _ in range(steps):
-            infos = fn()
+            rm = run_mixed()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, infos
-
-    t_plain, ip = timed(run_plain)
-    t_mixed, im = timed(run_mixed)
+        t_mixed = (time.perf_counter() - t0) / steps
+    # kernel durations: the same steps again with the library's HIP events around every launch
+    # (the launches then go one after another, without the captured graph's parallel branches)
+    smr.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rm = run_mixed()
+    torch.cuda.synchronize()
+    t_mixed_seq = (time.perf_counter() - t0) / steps
+    smr.profile_enable(False)
+    n_spec, ms_spec = smr.profile_read("spec")
+    n_ks, ms_ks = smr.profile_read("kslice")
+    if profiled_only:
+        return {"profiled_pass_ms": t_mixed_seq * 1e3, "spec_avg_launch_us": ms_spec * 1e3 / max(n_spec, 1),
+                "kslice_avg_launch_us": ms_ks * 1e3 / max(n_ks, 1)}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rp = run_plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    im = [i for _, i in rm]
+    ip = [i for _, i in rp]
     ok = all(i["status"] == "ok" and i["relres_true"] <= rtol for i in ip + im)
-    it_p = [i["iters"] for i in ip]
-    it_m = [i["iters"] for i in im]
-    ratio = max(b / a for a, b in zip(it_p, it_m) if a > 0)
-    nvar = sum(p.ax is not None for p in probs)
-    dof = sum(p.n * p.N * p.N for p in probs)
-    return {"workload": "bdf2_batch64_uneven", "instances": len(probs), "variable_coefficient": nvar,
-            "dof_total": dof, "rtol": rtol,
-            "plain_fp64_sequential_ms": t_plain * 1e3, "mixed_fp32_batched_ms": t_mixed * 1e3,
-            "speedup": t_plain / t_mixed,
-            "iters_total_plain": sum(it_p), "iters_total_mixed": sum(it_m),
-            "iters_max_ratio_mixed_over_plain": ratio, "all_converged": ok,
-            "mixed_iters_per_s": sum(it_m) / t_mixed, "plain_iters_per_s": sum(it_p) / t_plain}
+    it_m, it_p = sum(i["iters"] for i in im), sum(i["iters"] for i in ip)
+    ratio = max(b["iters"] / a["iters"] for a, b in zip(ip, im) if a["iters"] > 0)
+    spec_b, ks_b, ks_f = batch_algorithmic(probs, im, 4)
+    spec_s = ms_spec * 1e-3 / steps
+    ks_s = ms_ks * 1e-3 / steps
+    spec_gbs = spec_b / spec_s / 1e9
+    ks_gbs = ks_b / ks_s / 1e9
+    ks_tf = ks_f / ks_s / 1e12
+    roof_spec = {"bound": "hbm", "achieved": spec_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": spec_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(TRAFFIC_FILE_BATCH),
+                 "kernel": "k_spec_multi (fused batched MINRES iteration, every time-size class)",
+                 "launches": n_spec // steps, "avg_launch_us": ms_spec * 1e3 / max(n_spec, 1),
+                 "bytes_per_launch": spec_b / max(n_spec // steps, 1), "kernel_ms_per_solve": ms_spec / steps}
+    roof_ks = {"bound": "alu", "achieved": ks_tf, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+               "frac": ks_tf / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+               "kernel": "k_kslice_multi (per-level U K(a) U matvec, every N class)",
+               "launches": n_ks // steps, "avg_launch_us": ms_ks * 1e3 / max(n_ks, 1),
+               "flops_per_launch": ks_f / max(n_ks // steps, 1), "kernel_ms_per_solve": ms_ks / steps,
+               "hbm_achieved_gbs": ks_gbs, "hbm_frac": ks_gbs / PEAK_HBM_GBS}
+    dominant_spec = ms_spec >= ms_ks
+    dof = sum(q.n * q.N * q.N for q in probs)
+    rec = {
+        "value": it_m / t_mixed, "ms_per_step": t_mixed * 1e3,
+        "config": {"workload": "bdf2_batch64_uneven", "instances": len(probs),
+                   "N": [31, 63, 127], "n": [64, 128, 256], "variable_coefficient": sum(q.ax is not None for q in probs),
+                   "precond": "Phat / Phat(Kbar)", "precision": "f64 MINRES, matvec, residual; f32 time transform and z",
+                   "rtol": rtol, "dof_total": dof},
+        "time_to_1e-8_ms": t_mixed * 1e3, "time_to_1e-8_ms_profiled_sequential": t_mixed_seq * 1e3,
+        "plain_fp64": {"time_to_1e-8_ms": t_plain * 1e3, "iters_per_s": it_p / t_plain, "iters_total": it_p},
+        "speedup_mixed_batched_vs_plain": t_plain / t_mixed,
+        "iters_total_mixed": it_m, "iters_total_plain": it_p, "iters_max_ratio_mixed_over_plain": ratio,
+        "all_converged": ok,
+        "roofline": roof_spec if dominant_spec else roof_ks,
+        "roofline_other": roof_ks if dominant_spec else roof_spec,
+    }
+    if cpu:
+        sample = (0, 1, 2, 9, 10, 11)
+        base, sols = cpu_baseline_batch(probs, sample, rtol)
+        rec["cpu_baseline"] = base
+        errs_m, errs_p = {}, {}
+        for i in sample:
+            ref = sols[i].x
+            sc = float(np.abs(ref).max())
+            errs_m[probs[i].name] = float(np.abs(rm[i][0].cpu().numpy() - ref).max()) / sc
+            errs_p[probs[i].name] = float(np.abs(rp[i][0].cpu().numpy() - ref).max()) / sc
+            assert rp[i][1]["iters"] == sols[i].iters, (probs[i].name, rp[i][1]["iters"], sols[i].iters)
+        rec["rel_err_vs_oracle"] = {"mixed_batched": errs_m, "plain_fp64": errs_p}
+    return rec
+
+
+def cn2d_leg(dev, warmup: int, steps: int, rtol: float):
+    """The 2D Crank-Nicolson workload (N = 127, n = 256, a = 1, noisy source, seed 0, P_H),
+    plain float64, one solve per step; the fused sine-basis iteration kernel timed with HIP
+    events and priced against the HBM roofline (its two folded time GEMMs against the FP64
+    matrix peak beside it); the float32-transform form beside it."""
+    import torch
+    import workloads as W
+    from paper_2201_10062_amd import Plan, smr
+    p = W.crank_nicolson_2d_noisy()          # N = 127, n = 256, theta = 1/2, seed 0
+    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    plan = Plan(2, p.N, p.n, theta=p.theta, device=dev)
+    b = plan.empty()
+
+    def step():
+        plan.build_rhs(f, u0, out=b)
+        return plan.solve(b, rtol=rtol)[1]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    smr.profile_enable(True)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    smr.profile_enable(False)
+    n_spec, ms_spec = smr.profile_read("spec")
+    iters = [i["iters"] for i in infos]
+    dof = p.n * p.m
+
+    # Fused launch bytes per degree of freedom (float64): init 32 (read b^; write v_1, z_1,
+    # x = 0), first 32 (read z_1, v_1; write v_2, z_2), steady 88 (read z_j, z_{j-1}, v_j,
+    # v_{j-1}, w_{j-2}, w_{j-3}, x; write v, z, w, x) less the w's that do not exist in
+    # launches 2 and 3, + 8 (read b^) for each evaluated true residual; 2 n^2 m flops of
+    # folded time GEMMs per launch.
+    def steady_bytes(k):
+        return sum(88 - (16 if j == 2 else 8 if j == 3 else 0) for j in range(2, k + 2))
+    bytes_total = sum((32 + 32 + steady_bytes(i["iters"]) + 8 * (i["res_evals"] - 1)) * dof for i in infos)
+    flops_per_launch = 2.0 * p.n * p.n * p.m
+    avg_launch_s = (ms_spec / n_spec) * 1e-3 if n_spec else float("nan")
+    bytes_per_launch = bytes_total / max(n_spec, 1)
+    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+    achieved_tf = flops_per_launch / avg_launch_s / 1e12
+    out = {"workload": "cn2d_noisy_N127_n256", "dof": dof, "precond": "P_H", "pprec": "fp64", "rtol": rtol,
+           "iters_per_s": sum(iters) / dt, "time_to_1e-8_ms": dt / steps * 1e3, "iters_per_solve": iters[-1],
+           "residuals_evaluated_per_solve": infos[-1]["res_evals"], "relres_true": infos[-1]["relres_true"],
+           "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(),
+                        "kernel": "k_spec (fused sine-basis MINRES iteration)", "launches": n_spec,
+                        "launches_expected": sum(k + 2 for k in iters), "avg_launch_us": avg_launch_s * 1e6,
+                        "bytes_per_launch": bytes_per_launch},
+           "roofline_mfma": {"achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved_tf / PEAK_FP64_TFLOPS, "flops_per_launch": flops_per_launch}}
+    # the same workload with the float32 preconditioner (error vs the float64 solution, which
+    # equals the oracle's iterate to 1e-10 in the parity tests)
+    mplan = Plan(2, p.N, p.n, theta=p.theta, pprec="fp32", device=dev)
+    x64, _ = plan.solve(b, rtol=rtol)
+    for _ in range(warmup):
+        mplan.solve(b, rtol=rtol)
+    torch.cuda.synchronize()
+    tm0 = time.perf_counter()
+    for _ in range(steps):
+        plan.build_rhs(f, u0, out=b)
+        xm, minfo = mplan.solve(b, rtol=rtol)
+    torch.cuda.synchronize()
+    tm1 = time.perf_counter()
+    out["mixed_fp32"] = {"time_to_1e-8_ms": (tm1 - tm0) / steps * 1e3, "iters_per_solve": minfo["iters"],
+                         "iters_per_s": minfo["iters"] * steps / (tm1 - tm0), "relres_true": minfo["relres_true"],
+                         "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
+    return out
 
 
 def manufactured_1d_leg(dev, rtol: float, reps: int = 20):
@@ -187,7 +388,7 @@ def paper_tables_leg(dev, reps: int = 3):
     return out
 
 
-def variable_coef_leg(dev, rtol: float):
+def variable_coef_leg(dev, rtol: float, oracle: bool = True):
     """The variable-coefficient workload (N = 255, n = 512, backward Euler,
     a = 1 + 0.5 sin(2 pi x) sin(2 pi y) at faces, f ~ U(-1, 1), seed 1): P_theta with the
     3-step Chebyshev per-mode solve, and P_H(Kbar) beside it, each in float64 and with the
@@ -220,19 +421,49 @@ def variable_coef_leg(dev, rtol: float):
                 out[name]["mixed_fp32"] = rec
             del g, b
         del x, x64
+    if oracle:
+        out["reduced_shape_vs_oracle"] = variable_coef_reduced_vs_oracle(dev, rtol)
     return out
+
+
+def variable_coef_reduced_vs_oracle(dev, rtol: float, N: int = 63, n: int = 128):
+    """The variable-coefficient recipe at a reduced shape (the oracle finishes in seconds):
+    the float64 and float32-transform GPU solutions of both preconditioners against the FP64
+    oracle's solution to the same tolerance (relative max-norm error), iterations beside."""
+    import torch
+    import workloads as W
+    from oracle.system import System
+    from paper_2201_10062_amd import Plan
+    p = W.variable_coef_2d(N=N, n=n)
+    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    rec = {"workload": f"varcoef2d_N{N}_n{n}"}
+    for name, kw in (("P_theta_cheb3", {"precond": "PTHETA_CHEB", "cheb_k": 3}), ("P_H_kbar", {"precond": "PH"})):
+        o = System(2, N, n, theta=p.theta, ax=p.ax, ay=p.ay, **kw)
+        ref = o.solve(o.rhs(p.f, p.u0), rtol=rtol, maxit=400)
+        sc = float(np.abs(ref.x).max())
+        r = {"oracle_iters": ref.iters}
+        for pprec in ("fp64", "fp32"):
+            g = Plan(2, N, n, theta=p.theta, ax=p.ax, ay=p.ay, device=dev, pprec=pprec, **kw)
+            x, info = g.solve(g.build_rhs(f, u0), rtol=rtol, maxit=400)
+            r[pprec] = {"iters": info["iters"], "rel_err_vs_oracle": float(np.abs(x.cpu().numpy() - ref.x).max()) / sc}
+        rec[name] = r
+    return rec
 
 
 def differentiable_leg(dev, rtol: float):
     """The differentiable-solve workload (N = 127, n = 256, backward Euler, 16 Gaussian-bump
     sources, u0 = 0): loss = ||u(f, a) - u_obs||^2 at nodal a = 1 with u_obs solved at
     a = 1 + 0.3 x y; one forward (batched MINRES) + backward (batched adjoint MINRES, adjoint
-    right-hand side, coefficient gradient) through torch.autograd."""
+    right-hand side, coefficient gradient) through torch.autograd.  The first pass at a new
+    coefficient rebuilds the cached plans' tables (timed apart as setup); the timed pass reuses
+    them."""
     import torch
     import workloads as W
-    from paper_2201_10062_amd.autograd import heat_solve
+    from paper_2201_10062_amd.autograd import clear_cache, heat_solve
     probs, a_truth = W.inverse_problem_2d()
     f = torch.from_numpy(np.stack([q.f for q in probs])).to(dev)
+    clear_cache()
     with torch.no_grad():
         uobs = heat_solve(f, torch.from_numpy(a_truth).to(dev), None, rtol=rtol)
 
@@ -244,39 +475,45 @@ def differentiable_leg(dev, rtol: float):
         loss.backward()
         return at.grad
 
-    step()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()                                  # new coefficient: plan tables rebuilt in place
+    torch.cuda.synchronize()
+    t_first = (time.perf_counter() - t0) * 1e3
     t0 = time.perf_counter()
     ga = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
+    clear_cache()
     return {"workload": "inverse_problem_N127_n256_batch16", "dof_per_source": probs[0].n * probs[0].m,
-            "sources": len(probs), "forward_backward_ms": ms, "rtol": rtol,
-            "grad_a_norm": float(ga.norm())}
+            "sources": len(probs), "forward_backward_ms": ms, "first_pass_with_setup_ms": t_first,
+            "setup_ms": t_first - ms, "rtol": rtol, "grad_a_norm": float(ga.norm())}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-batch", action="store_true",
-                    help="only the headline workload (skip the batch, paper-table, variable-coefficient "
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline batch (skip the Crank-Nicolson, 1D, paper-table, variable-coefficient "
                          "and differentiable legs)")
+    ap.add_argument("--profiled-pass-only", action="store_true",
+                    help="only the headline's profiled pass (warm-up + the timed steps with per-launch events)")
+    ap.add_argument("--only-cn2d", action="store_true",
+                    help="only the 2D Crank-Nicolson leg (for profiling its fused kernel)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(the known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the solve runs on one GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the solver and every "
+              "workload here run on a single GPU (multi-GPU sharding is design only)", file=sys.stderr)
         return 2
 
     import torch
-    import workloads as W
-    from paper_2201_10062_amd import Plan, smr
 
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
@@ -289,104 +526,37 @@ def main() -> int:
         print(json.dumps({"copy_calibration_mib": args.copy_calibration_mib,
                           "bytes_read": nel * 8, "bytes_written": nel * 8}), flush=True)
         return 0
-    p = W.crank_nicolson_2d_noisy()          # N = 127, n = 256, theta = 1/2, seed 0
-    f = torch.from_numpy(p.f.reshape(-1)).to(dev)
-    u0 = torch.from_numpy(p.u0).to(dev)
-    plan = Plan(2, p.N, p.n, theta=p.theta, device=dev)
-    b = plan.empty()
-
-    def step():
-        plan.build_rhs(f, u0, out=b)
-        x, info = plan.solve(b, rtol=args.rtol)
-        return info
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    smr.profile_enable(True)
-    iters = []
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = step()
-        iters.append(info["iters"])
-        infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    smr.profile_enable(False)
-    n_spec, ms_spec = smr.profile_read("spec")
-    dt = t1 - t0
-    total_iters = sum(iters)
-    dof = p.n * p.m
-    # Dominant kernel: the fused sine-basis MINRES iteration (one launch per iteration,
-    # plus one initialising launch per solve).  Algorithmic HBM bytes per degree of freedom:
-    #   init 32 (zero guess: read b^; write v_1, z_1, x = 0), first 32 (read z_1, v_1; write
-    #   v_2, z_2), steady 88 (read z_j, z_{j-1}, v_j, v_{j-1}, w_{j-2}, w_{j-3}, x; write v, z,
-    #   w, x), less the w's that do not exist yet in launches 2 (w_0, w_-1) and 3 (w_0),
-    #   plus 8 (read b^) in the launches that evaluate the true residual (the library reports
-    #   how many it evaluated, the initial one included).
-    # Each launch also does the two folded time GEMMs: 2 n^2 m flops.
-    def steady_bytes(k):
-        return sum(88 - (16 if j == 2 else 8 if j == 3 else 0) for j in range(2, k + 2))
-    bytes_total = sum((32 + 32 + steady_bytes(i["iters"]) + 8 * (i["res_evals"] - 1)) * dof for i in infos)
-    launches_expected = sum(k + 2 for k in iters)
-    flops_per_launch = 2.0 * p.n * p.n * p.m
-    avg_launch_s = (ms_spec / n_spec) * 1e-3 if n_spec else float("nan")
-    bytes_per_launch = bytes_total / max(n_spec, 1)
-    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
-    achieved_tf = flops_per_launch / avg_launch_s / 1e12
-    traffic = traffic_entry()
+    if args.only_cn2d:
+        print(json.dumps({"cn2d": cn2d_leg(dev, args.warmup, args.steps, args.rtol)}), flush=True)
+        return 0
+    if args.profiled_pass_only:
+        print(json.dumps(batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=False,
+                                               profiled_only=True)), flush=True)
+        return 0
+    head = batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=not args.no_cpu)
+    print(f"headline done: {head['ms_per_step']:.1f} ms per batch solve", file=sys.stderr, flush=True)
     out = {
-        "metric": "MINRES iters/s to 1e-8 true relative residual (time-to-1e-8 beside it)",
-        "value": total_iters / dt,
+        "metric": "time-to-1e-8 residual & MINRES iters/s; mixed+batched vs plain FP64, same GPU",
+        "value": head.pop("value"),
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 outer / f32 P^-1",
         "data": "synthetic",
-        "config": {"workload": "cn2d_noisy_N127_n256", "dim": 2, "N": p.N, "n": p.n, "m": p.m,
-                   "theta": p.theta, "precond": "P_H", "pprec": "fp64", "rtol": args.rtol, "dof": dof},
-        "iters_per_solve": iters[-1],
-        "residuals_evaluated_per_solve": infos[-1]["res_evals"],
-        "time_to_1e-8_ms": dt / args.steps * 1e3,
-        "relres_true": infos[-1]["relres_true"],
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_spec (fused sine-basis MINRES iteration)",
-                     "launches": n_spec, "launches_expected": launches_expected,
-                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
-        "roofline_mfma": {"achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                          "frac": achieved_tf / PEAK_FP64_TFLOPS, "flops_per_launch": flops_per_launch},
+        "config": head.pop("config"),
+        **head,
     }
-    # the same workload with the float32 preconditioner (error vs the float64 solution reported)
-    mplan = Plan(2, p.N, p.n, theta=p.theta, pprec="fp32", device=dev)
-    x64, _ = plan.solve(b, rtol=args.rtol)
-    for _ in range(args.warmup):
-        mplan.solve(b, rtol=args.rtol)
-    torch.cuda.synchronize()
-    tm0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.build_rhs(f, u0, out=b)
-        xm, minfo = mplan.solve(b, rtol=args.rtol)
-    torch.cuda.synchronize()
-    tm1 = time.perf_counter()
-    out["mixed_fp32"] = {"time_to_1e-8_ms": (tm1 - tm0) / args.steps * 1e3, "iters_per_solve": minfo["iters"],
-                         "iters_per_s": minfo["iters"] * args.steps / (tm1 - tm0),
-                         "relres_true": minfo["relres_true"],
-                         "rel_err_vs_fp64": float((xm - x64).abs().max() / x64.abs().max())}
-    if not args.no_batch:
-        out["batched_bdf2"] = batched_bdf2_leg(dev, warmup=1, steps=2, rtol=args.rtol)
+    if not args.no_extras:
+        out["cn2d"] = cn2d_leg(dev, args.warmup, max(args.steps, 10), args.rtol)
         out["manufactured_1d"] = manufactured_1d_leg(dev, args.rtol)
         out["paper_tables_largest"] = paper_tables_leg(dev)
-        out["variable_coefficient"] = variable_coef_leg(dev, args.rtol)
+        out["variable_coefficient"] = variable_coef_leg(dev, args.rtol, oracle=not args.no_cpu)
         out["differentiable"] = differentiable_leg(dev, args.rtol)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
     return 0
 

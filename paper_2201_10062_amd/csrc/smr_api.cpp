@@ -743,6 +743,10 @@ struct BatchState {
   Scal *snap = nullptr;        // two slots of `cap` instances
   int cap = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // side streams and events of the captured iterations, whose size classes of one phase run
+  // on parallel branches (made on first use)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> cev;
 };
 BatchState &batch_state() {
   static std::mutex mu;
@@ -1239,13 +1243,58 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, 0, 0));
     // one iteration j: the per-level matvec of every N class, then the fused launch of every
     // time-size class
-    auto iteration = [&](hipStream_t st, int j) -> hipError_t {
+    // One captured iteration j: the per-level matvec of every N class, then the fused launch of
+    // every time-size class.  The classes of one phase touch disjoint instances, so each runs
+    // on a branch of its own (side streams forked from and joined back into the capture
+    // stream), letting a small class fill the compute units a large one leaves idle; the
+    // fused phase waits for every matvec class, the next iteration for every fused class.
+    // the side streams and events are made before the capture begins (one event per fork and
+    // per join of every phase of the six iterations)
+    {
+      const size_t nside = std::max(kclasses.size(), classes.size());
+      while (bst.side.size() + 1 < nside) {
+        hipStream_t st = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        bst.side.push_back(st);
+      }
+      while (bst.cev.size() < 6 * (kclasses.size() + classes.size())) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        bst.cev.push_back(e);
+      }
+    }
+    size_t nev = 0;
+    auto next_event = [&](hipEvent_t *out) -> hipError_t {
+      if (nev >= bst.cev.size()) return hipErrorInvalidValue;
+      *out = bst.cev[nev++];
+      return hipSuccess;
+    };
+    auto phase = [&](hipStream_t cs, int nbranch, auto launch_one) -> hipError_t {
       hipError_t e = hipSuccess;
-      for (const KClass &cl : kclasses)
-        if (e == hipSuccess) e = launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j);
-      for (const Class &cl : classes)
-        if (e == hipSuccess)
-          e = launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, j == 1 ? 1 : 2, j);
+      if (nbranch <= 1) return nbranch == 1 ? launch_one(cs, 0) : hipSuccess;
+      hipEvent_t fork = nullptr;
+      if (e == hipSuccess) e = next_event(&fork);
+      if (e == hipSuccess) e = hipEventRecord(fork, cs);
+      for (int c = 1; c < nbranch && e == hipSuccess; ++c) e = hipStreamWaitEvent(bst.side[c - 1], fork, 0);
+      for (int c = 0; c < nbranch && e == hipSuccess; ++c) e = launch_one(c == 0 ? cs : bst.side[c - 1], c);
+      for (int c = 1; c < nbranch && e == hipSuccess; ++c) {
+        hipEvent_t join = nullptr;
+        e = next_event(&join);
+        if (e == hipSuccess) e = hipEventRecord(join, bst.side[c - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, join, 0);
+      }
+      return e;
+    };
+    auto iteration_par = [&](hipStream_t cs, int j) -> hipError_t {
+      hipError_t e = phase(cs, (int)kclasses.size(), [&](hipStream_t st, int c) {
+        const KClass &cl = kclasses[c];
+        return launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j);
+      });
+      if (e == hipSuccess)
+        e = phase(cs, (int)classes.size(), [&](hipStream_t st, int c) {
+          const Class &cl = classes[c];
+          return launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, j == 1 ? 1 : 2, j);
+        });
       return e;
     };
     // steady iterations j >= 6 replay a captured graph of six (cached by workspace and class
@@ -1257,7 +1306,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec});
       g6 = batch_graph(bst, key, [&](hipStream_t cs) {
         hipError_t e = hipSuccess;
-        for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration(cs, j);
+        for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration_par(cs, j);
         return e;
       });
     }
