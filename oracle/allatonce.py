@@ -5,7 +5,8 @@ A0 = M + theta tau K on the diagonal and A1 = -M + (1-theta) tau K below it
 (eqn:symbol_h); f_H's first block carries (M - (1-theta) tau K) u0.
 BDF2 (Sec. 4, eqn:matrix_gen with l = 2): A0 = 1.5 I + tau K, A1 = -2 I,
 A2 = 0.5 I (the standard two-step backward difference multiplied by tau; the
-paper leaves the blocks unnamed), right-hand side given directly.
+paper leaves the blocks unnamed), right-hand side given directly; BDF-l (l = 3, 4)
+the same from the l-step backward difference formula (bdf_coefficients).
 Y = Y_n (x) I_m is the time flip of eqn:main_system; Y T is symmetric.
 M = I throughout (finite differences, Sec. 5).
 """
@@ -24,6 +25,28 @@ def theta_blocks(K, tau: float, theta: float):
 def bdf2_blocks(K, tau: float):
     I = sp.identity(K.shape[0], format="csr")
     return [(1.5 * I + tau * K).tocsr(), (-2.0 * I).tocsr(), (0.5 * I).tocsr()]
+
+
+def bdf_coefficients(l: int) -> np.ndarray:
+    """alpha_0..alpha_l of the l-step backward difference formula (Sec. 4 leaves the blocks
+    A_(k) to the scheme): tau u'(t_k) is approximated by sum_j nabla^j u^k / j over
+    j = 1..l, nabla u^k = u^k - u^{k-1}; expanding nabla^j = sum_k binom(j, k) (-1)^k E^k
+    (E u^k = u^{k-1}) gives alpha_k = (-1)^k sum_{j >= max(k, 1)} binom(j, k) / j."""
+    from math import comb
+    a = np.zeros(l + 1)
+    for j in range(1, l + 1):
+        for k in range(j + 1):
+            a[k] += (-1) ** k * comb(j, k) / j
+    return a
+
+
+def bdf_blocks(K, tau: float, l: int):
+    """Blocks of eqn:matrix_gen for BDF-l with M = I, multiplied by tau:
+    A_(0) = alpha_0 I + tau K, A_(k) = alpha_k I (k = 1..l); start-up values enter the
+    right-hand side, so the matrix stays block Toeplitz."""
+    a = bdf_coefficients(l)
+    I = sp.identity(K.shape[0], format="csr")
+    return [(a[0] * I + tau * K).tocsr()] + [(a[k] * I).tocsr() for k in range(1, l + 1)]
 
 
 def assemble_T(blocks, n: int) -> sp.csr_matrix:

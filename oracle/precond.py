@@ -7,8 +7,8 @@ P_H^{-1} v = three steps: transform, divide by sigma_{j,k} = |l0_k + l1_k e^{i p
 transform back (S_n and U are symmetric orthogonal, U = S_N or S_N (x) S_N).
 Variable a: K is replaced by the averaged Toeplitz Kbar in the preconditioner only.
 
-Phat (def:matrix_P_gen, Sec. 4): sqrt(I (x) qbar0 + P_n (x) qbar1 + P_n^2 (x) qbar2)
-for BDF2, whose eigenvalues are |ghat(phi_j)| with ghat the symbol eqn:symbol_h_gen.
+Phat (def:matrix_P_gen, Sec. 4): sqrt(I (x) qbar0 + P_n (x) qbar1 + ... + P_n^l (x) qbarl)
+for BDF-l, whose eigenvalues are |ghat(phi_j)| with ghat the symbol eqn:symbol_h_gen.
 
 P_theta (def:matrix_mod_P, Sec. 3.1.4 "Modified Preconditioner"):
 H (x) I + H_theta (x) tau K; in the time-sine basis it is block diagonal with
@@ -47,6 +47,17 @@ def sigma_bdf2(mu: np.ndarray, n: int, tau: float) -> np.ndarray:
     mu = np.asarray(mu, dtype=np.float64)
     e = np.exp(1j * phi(n))[:, None]
     return np.abs((1.5 + tau * mu)[None, :] - 2.0 * e + 0.5 * e * e)
+
+
+def sigma_bdf(mu: np.ndarray, n: int, tau: float, alpha) -> np.ndarray:
+    """|ghat(phi_j)| for BDF-l (eqn:symbol_h_gen evaluated on the spatial eigenvalue mu_k):
+    |(alpha_0 + tau mu_k) + sum_{k >= 1} alpha_k e^{i k phi_j}|.  Shape (n, len(mu))."""
+    mu = np.asarray(mu, dtype=np.float64)
+    e = np.exp(1j * phi(n))[:, None]
+    g = (alpha[0] + tau * mu)[None, :] + 0j
+    for k in range(1, len(alpha)):
+        g = g + alpha[k] * e ** k
+    return np.abs(g)
 
 
 def pinv_spectral(v: np.ndarray, sigma: np.ndarray, n: int, N: int, dim: int) -> np.ndarray:
@@ -95,6 +106,37 @@ def Phat_dense(blocks, n: int) -> np.ndarray:
     Pn = tridiag_half(n)
     In = np.eye(n)
     M2 = np.kron(In, q0 - 2 * q2) + np.kron(Pn, 2 * q1) + np.kron(Pn @ Pn, 4 * q2)
+    return sqrtm_spd(M2)
+
+
+def qbar_general(blocks):
+    """qbar_0..qbar_l of def:matrix_P_gen for any l: eqn:symbol_h_gen_poly gives
+    |ghat|^2 = q_0 + sum_{j >= 1} q_j 2 cos(j x) with q_j = sum_k A_(k) A_(k+j) (the blocks
+    are symmetric and commute), and 2 cos(j x) = 2 T_j(cos x) (Chebyshev polynomials), so
+    qbar_k collects the coefficient of cos^k x."""
+    from numpy.polynomial import chebyshev as C
+    A = [np.asarray(B.todense()) if sp.issparse(B) else np.asarray(B) for B in blocks]
+    l = len(A) - 1
+    q = [sum(A[k] @ A[k + j] for k in range(l + 1 - j)) for j in range(l + 1)]
+    qbar = [np.zeros_like(A[0]) for _ in range(l + 1)]
+    qbar[0] = qbar[0] + q[0]
+    for j in range(1, l + 1):
+        cj = C.cheb2poly([0.0] * j + [1.0])        # T_j in powers of cos x
+        for k, c in enumerate(cj):
+            if c != 0.0:
+                qbar[k] = qbar[k] + 2.0 * c * q[j]
+    return qbar
+
+
+def Phat_dense_general(blocks, n: int) -> np.ndarray:
+    """Phat = sqrt(sum_k P_n^k (x) qbar_k) of def:matrix_P_gen for any l."""
+    qb = qbar_general(blocks)
+    Pn = tridiag_half(n)
+    M2 = np.zeros((n * qb[0].shape[0],) * 2)
+    Pk = np.eye(n)
+    for k in range(len(qb)):
+        M2 = M2 + np.kron(Pk, qb[k])
+        Pk = Pk @ Pn
     return sqrtm_spd(M2)
 
 

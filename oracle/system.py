@@ -39,6 +39,9 @@ class System:
             self.blocks = aao.theta_blocks(self.K, self.tau, self.theta)
         elif scheme == "bdf2":
             self.blocks = aao.bdf2_blocks(self.K, self.tau)
+        elif scheme in ("bdf3", "bdf4"):
+            self.alpha = aao.bdf_coefficients(int(scheme[3]))
+            self.blocks = aao.bdf_blocks(self.K, self.tau, int(scheme[3]))
         else:
             raise ValueError(scheme)
         self.precond = precond
@@ -49,12 +52,14 @@ class System:
         self.mu = spatial.mu_kbar(N, dim, ax, ay)
         if scheme == "theta":
             self.sigma = pc.sigma_theta(self.mu, n, self.tau, self.theta)
-        else:
+        elif scheme == "bdf2":
             self.sigma = pc.sigma_bdf2(self.mu, n, self.tau)
+        else:
+            self.sigma = pc.sigma_bdf(self.mu, n, self.tau, self.alpha)
 
     # ------------------------------------------------------------ operators
     def rhs(self, f=None, u0=None, b=None) -> np.ndarray:
-        """Unpermuted f_H (theta scheme from f and u0) or the given b (BDF2)."""
+        """Unpermuted f_H (theta scheme from f and u0) or the given b (BDF-l)."""
         if b is not None:
             return np.asarray(b, dtype=np.float64).reshape(-1).copy()
         u0 = np.zeros(self.m) if u0 is None else np.asarray(u0, dtype=np.float64)
