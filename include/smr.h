@@ -9,11 +9,11 @@
  * (tau = T/n) with
  *   - the theta-method (eq. theta): T_H has A0 = I + theta tau K on the block
  *     diagonal and A1 = -I + (1-theta) tau K below it;
- *   - BDF2 (eqn:matrix_gen with l = 2): A0 = 1.5 I + tau K, A1 = -2 I, A2 = 0.5 I.
+ *   - BDF-l, l = 2, 3, 4 (eqn:matrix_gen): A0 = alpha_0 I + tau K, A_k = alpha_k I.
  * K = K(a) is the 3-point (1D) or 5-point (2D) stencil of eqn:matrix_Km_va built from
  * face values of a.  The library solves Y T u = Y f_H (eqn:main_system, Y the time
  * flip) by preconditioned MINRES with
- *   - SMR_P_H: P_H (def:matrix_P) or, for BDF2, Phat (def:matrix_P_gen); for
+ *   - SMR_P_H: P_H (def:matrix_P) or, for BDF-l, Phat (def:matrix_P_gen); for
  *     variable a the averaged Toeplitz Kbar of Sec. 3.1.1 replaces K inside P only.
  *     P^{-1} = (S_n (x) U) diag(1/sigma) (S_n (x) U), U the spatial sine transform,
  *     sigma_{j,k} = |ghat(phi_j)| evaluated at the eigenvalue mu_k of K (or Kbar);
@@ -44,7 +44,7 @@
  *     status other than SMR_OK a human-readable reason is available from
  *     smr_last_error() (thread-local, valid until the next call on the thread).
  *   Limits: dim in {1, 2}; N + 1 a power of two with 2 <= N + 1 <= 512; 1 <= n <= 1024
- *     (n >= 2 for BDF2); 0 <= theta <= 1; every face value finite and > 0.
+ *     (n >= l for BDF-l); 0 <= theta <= 1; every face value finite and > 0.
  */
 #ifndef SMR_H
 #define SMR_H
@@ -69,7 +69,12 @@ typedef enum {
   SMR_EUNSUPPORTED = 7   /* valid request that the library does not implement         */
 } smr_status;
 
-typedef enum { SMR_THETA = 0, SMR_BDF2 = 2 } smr_scheme;
+/* Time discretisation: the theta method, or the l-step backward difference formula BDF-l
+ * (Sec. 4, eqn:matrix_gen; the enum value is l), A_(0) = alpha_0 I + tau K, A_(k) = alpha_k I
+ * with alpha_k the coefficients of sum_{j=1}^{l} nabla^j / j (BDF2: 3/2, -2, 1/2; BDF3: 11/6,
+ * -3, 3/2, -1/3; BDF4: 25/12, -4, 3, -4/3, 1/4).  BDF right-hand sides are given directly
+ * (start-up values belong in them). */
+typedef enum { SMR_THETA = 0, SMR_BDF2 = 2, SMR_BDF3 = 3, SMR_BDF4 = 4 } smr_scheme;
 typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
 /* Arithmetic inside P^{-1} during the solves.  The matvec, the Lanczos recurrences, the
  * MINRES scalars and the true residual are always float64.  SMR_FP32 runs the time-axis sine
@@ -152,7 +157,7 @@ smr_status smr_destroy(smr_plan *plan);
 
 /* f_H of Sec. 1 (theta scheme): b_k = theta tau f^(k) + (1-theta) tau f^(k-1), k = 1..n,
  * plus (I - (1-theta) tau K) u0 on block 1.  d_f: (n+1)*m, d_u0: m (NULL = 0),
- * d_b: n*m (output, unpermuted).  SMR_EINVAL for the BDF2 scheme (its b is given). */
+ * d_b: n*m (output, unpermuted).  SMR_EINVAL for the BDF schemes (their b is given). */
 smr_status smr_build_rhs(const smr_plan *plan, const double *d_f, const double *d_u0,
                          double *d_b, void *stream);
 
@@ -231,7 +236,7 @@ smr_status smr_rhs_adjoint(const smr_plan *plan, const double *d_lambda, double 
 /* Gradient of a loss w.r.t. the coefficient, given the forward solution u (n*m), the
  * initial value u0 (m, NULL = 0) and the adjoint lambda (n*m):
  * grad a_e = -(tau/h^2) sum_k (D_e lambda_k)(D_e utilde_k), utilde_k = theta u_k + (1-theta) u_{k-1}
- * (u_0 = u0; BDF2: utilde_k = u_k), D_e the difference across face e.  Outputs (device,
+ * (u_0 = u0; BDF-l: utilde_k = u_k), D_e the difference across face e.  Outputs (device,
  * each may be NULL): face gradients d_gax (shaped like ax), d_gay (dim 2) and the nodal
  * gradient d_ga_nodal ((N+2)^dim, half the sum over the faces touching each node). */
 smr_status smr_grad_a(const smr_plan *plan, const double *d_u, const double *d_u0,

@@ -301,9 +301,12 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     do_res = jfull >= 3 &&
              (K.sqsigmin * fabs(sprev->eta) <= 2.0 * sprev->rtol * sprev->bnorm || sprev->iter >= sprev->maxit);
   }
-  double c0, c1, c2, b0, b1;
-  if (K.scheme == SMR_THETA) { c0 = 1.0; c1 = -1.0; c2 = 0.0; b0 = K.theta; b1 = 1.0 - K.theta; }
-  else { c0 = 1.5; c1 = -2.0; c2 = 0.5; b0 = 1.0; b1 = 0.0; }
+  // (T s)^_t = sum_r c_r s_{t-r} + tau U K(a) U (b0 s_t + b1 s_{t-1}): the scheme's time
+  // coefficients (theta: 1, -1; BDF-l: alpha_0 .. alpha_l) and weights of K
+  double tcs[5], kbs[2];
+  const bool far = scheme_coefs(K.scheme, K.theta, tcs, kbs) > 3;   // levels t-3, t-4 enter (BDF3, BDF4)
+  const double c0 = tcs[0], c1 = tcs[1], c2 = tcs[2], c3 = tcs[3], c4 = tcs[4];
+  const double b0 = kbs[0], b1 = kbs[1];
 
   double acc_r = 0.0, acc_d = 0.0;
   // ---- q = (T s)^ on level t for the source s (x0 or z_j)
@@ -313,6 +316,8 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const T *st = s + (size_t)t * ld;
     const T *s1 = t >= 1 ? st - ld : nullptr;
     const T *s2 = t >= 2 ? st - 2 * ld : nullptr;
+    const T *s3 = far && t >= 3 ? st - 3 * ld : nullptr;
+    const T *s4 = far && t >= 4 ? st - 4 * ld : nullptr;
     for (int e0 = tid; e0 < m; e0 += kLB * kKT) {   // kLB elements' loads in flight
       double a0[kLB], a1[kLB];
 #pragma unroll
@@ -350,7 +355,8 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
         const int e = e0 + u * kKT;
         if (e >= m) break;
         const int jr = e / NC, ir = e - jr * NC;
-        const double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[jr * LP + ir];
+        double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[jr * LP + ir];
+        if (far) v += (s3 ? c3 * (double)s3[e] : 0.0) + (s4 ? c4 * (double)s4[e] : 0.0);
         q[e] = v;
         if (MODE == 1) acc_d += v * af[u];
       }
@@ -362,6 +368,8 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
     const double *xt = K.x + (size_t)t * ld;
     const double *x1 = t >= 1 ? xt - ld : nullptr;
     const double *x2 = t >= 2 ? xt - 2 * ld : nullptr;
+    const double *x3 = far && t >= 3 ? xt - 3 * ld : nullptr;
+    const double *x4 = far && t >= 4 ? xt - 4 * ld : nullptr;
     const double *bt = K.bh + (size_t)t * ld;
     for (int e0 = tid; e0 < m; e0 += kLB * kKT) {
       double a0[kLB], a1[kLB];
@@ -385,8 +393,9 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
       const double v0 = xt[e];
       const double v1 = x1 ? x1[e] : 0.0;
       const double v2 = x2 ? x2[e] : 0.0;
+      const double v34 = (x3 ? c3 * x3[e] : 0.0) + (x4 ? c4 * x4[e] : 0.0);
       const int jr = e / NC, ir = e - jr * NC;
-      const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2) - K.tau * X[jr * LP + ir];
+      const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2 + v34) - K.tau * X[jr * LP + ir];
       acc_r += r * r;
     }
   }

@@ -17,13 +17,16 @@ constexpr int kTX = 64, kTY = 4;      // 2D tile: 64 x-points by 4 y-rows per bl
 constexpr int kT1 = 256;              // 1D tile
 
 struct SP {                           // stencil parameters passed by value
-  int dim, N, n, m, scheme;
+  int dim, N, n, m, scheme, taps;
   double tau, theta, h2inv;
+  double tc[5];                       // time-difference coefficients of the levels t .. t-4
   const double *ax, *ay;
 };
 
 inline SP make_sp(const Plan *p) {
-  return SP{p->dim, p->N, p->n, p->m, p->scheme, p->tau, p->theta, p->h2inv, p->ax, p->ay};
+  SP s{p->dim, p->N, p->n, p->m, p->scheme, p->taps, p->tau, p->theta, p->h2inv, {}, p->ax, p->ay};
+  for (int k = 0; k < 5; ++k) s.tc[k] = p->tcf[k];
+  return s;
 }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -71,7 +74,7 @@ __device__ __forceinline__ double Kapply(const SP &s, const double *__restrict__
 }
 
 // (T x)_k at spatial point (j, i): theta scheme x_k - x_{k-1} + tau K(theta x_k + (1-theta) x_{k-1});
-// BDF2 1.5 x_k - 2 x_{k-1} + 0.5 x_{k-2} + tau K x_k.
+// BDF-l sum_{r <= l} alpha_r x_{k-r} + tau K x_k.
 __device__ __forceinline__ double Tapply(const SP &s, const double *__restrict__ x, int k, int j, int i) {
   const int m = s.m;
   const int q = (s.dim == 1) ? i : j * s.N + i;
@@ -81,8 +84,8 @@ __device__ __forceinline__ double Tapply(const SP &s, const double *__restrict__
     double v = xk[q] - (xk1 ? xk1[q] : 0.0);
     return v + s.tau * Kapply(s, xk, s.theta, xk1, 1.0 - s.theta, j, i);
   }
-  const double *xk2 = k >= 2 ? xk1 - m : nullptr;
-  double v = 1.5 * xk[q] - (xk1 ? 2.0 * xk1[q] : 0.0) + (xk2 ? 0.5 * xk2[q] : 0.0);
+  double v = 0.0;
+  for (int r = 0; r < s.taps && r <= k; ++r) v += s.tc[r] * xk[q - (ptrdiff_t)r * m];
   return v + s.tau * Kapply(s, xk, 1.0, nullptr, 0.0, j, i);
 }
 
@@ -165,18 +168,23 @@ __global__ __launch_bounds__(256) void k_apply_YT(SP s, MarchP mp, const double 
       const double us = hs ? xl[q - N] : 0.0, un = hn ? xl[q + N] : 0.0;
       return s.h2inv * (aw * (c - uw) + ae * (c - ue) + as * (c - us) + an * (c - un));
     };
-    double x1 = 0.0, x2 = 0.0, kx1 = 0.0;           // x_{k-1}, x_{k-2}, (K x)_{k-1}
-    if (k0 >= 1) {
-      if (s.scheme == SMR_THETA) kx1 = kx(x + (size_t)(k0 - 1) * m, x1);
-      else x1 = x[(size_t)(k0 - 1) * m + q];
-    }
-    if (k0 >= 2 && s.scheme != SMR_THETA) x2 = x[(size_t)(k0 - 2) * m + q];
+    double xp[4] = {0.0, 0.0, 0.0, 0.0};           // x_{k-1} .. x_{k-4}
+    double kx1 = 0.0;                              // (K x)_{k-1} (theta method)
+    if (k0 >= 1 && s.scheme == SMR_THETA) kx1 = kx(x + (size_t)(k0 - 1) * m, xp[0]);
+    if (s.scheme != SMR_THETA)
+      for (int r = 1; r < s.taps; ++r)
+        if (k0 >= r) xp[r - 1] = x[(size_t)(k0 - r) * m + q];
     for (int k = k0; k < k1; ++k) {
       double x0;
       const double kx0 = kx(x + (size_t)k * m, x0);
       double tv;
-      if (s.scheme == SMR_THETA) tv = x0 - x1 + s.tau * (s.theta * kx0 + (1.0 - s.theta) * kx1);
-      else tv = 1.5 * x0 - 2.0 * x1 + 0.5 * x2 + s.tau * kx0;
+      if (s.scheme == SMR_THETA) {
+        tv = x0 - xp[0] + s.tau * (s.theta * kx0 + (1.0 - s.theta) * kx1);
+      } else {
+        tv = s.tc[0] * x0 + s.tau * kx0;
+#pragma unroll
+        for (int r = 1; r < 5; ++r) tv += s.tc[r] * xp[r - 1];   // zero past the scheme's taps
+      }
       const size_t o = (size_t)(s.n - 1 - k) * m + q;   // Y: time level k lands at n-1-k
       if (MODE == 0) {
         const double val = xs * tv;
@@ -189,8 +197,10 @@ __global__ __launch_bounds__(256) void k_apply_YT(SP s, MarchP mp, const double 
         acc0 += r * r;
         acc1 += bk * bk;
       }
-      x2 = x1;
-      x1 = x0;
+      xp[3] = xp[2];
+      xp[2] = xp[1];
+      xp[1] = xp[0];
+      xp[0] = x0;
       kx1 = kx0;
     }
   }

@@ -172,8 +172,9 @@ smr_status validate(const smr_desc *d) {
   if (d->dim != 1 && d->dim != 2) return fail(SMR_EINVAL, "dim must be 1 or 2 (got %d)", d->dim);
   if (d->N < 1 || d->N > kMaxN || !is_pow2(d->N + 1))
     return fail(SMR_EINVAL, "N + 1 must be a power of two in [2, %d] (got N = %d)", kMaxN + 1, d->N);
-  if (d->scheme != SMR_THETA && d->scheme != SMR_BDF2) return fail(SMR_EINVAL, "unknown scheme %d", d->scheme);
-  const int nmin = d->scheme == SMR_BDF2 ? 2 : 1;
+  if (d->scheme != SMR_THETA && d->scheme != SMR_BDF2 && d->scheme != SMR_BDF3 && d->scheme != SMR_BDF4)
+    return fail(SMR_EINVAL, "unknown scheme %d", d->scheme);
+  const int nmin = d->scheme == SMR_THETA ? 1 : d->scheme;   // BDF-l: n >= l
   if (d->n < nmin || d->n > kMaxn) return fail(SMR_EINVAL, "n must be in [%d, %d] (got %d)", nmin, kMaxn, d->n);
   if (!(d->T > 0.0) || !std::isfinite(d->T)) return fail(SMR_EINVAL, "T must be finite and > 0");
   if (d->scheme == SMR_THETA && !(d->theta >= 0.0 && d->theta <= 1.0))
@@ -353,6 +354,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.T = d->T;
   p.tau = d->T / d->n;
   p.theta = d->scheme == SMR_THETA ? d->theta : 1.0;
+  p.taps = scheme_coefs(p.scheme, p.theta, p.tcf, p.kbf);
   p.L = d->N + 1;
   p.logL = ilog2(p.L);
   p.h = 1.0 / p.L;
@@ -440,10 +442,23 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
       tcoef[4 * t + 1] = (double)(th + (1.0L - th) * cp);
       tcoef[4 * t + 2] = (double)(-sp);
       tcoef[4 * t + 3] = (double)((1.0L - th) * sp);
-    } else {
+    } else if (p.scheme == SMR_BDF2) {
       tcoef[4 * t + 0] = (double)(4.0L * s2h * s2h);
       tcoef[4 * t + 1] = 1.0;
       tcoef[4 * t + 2] = (double)(-sp * (2.0L - cp));
+      tcoef[4 * t + 3] = 0.0;
+    } else {
+      // ghat(phi) at tau mu = (alpha_0 + tau mu) + sum_{k >= 1} alpha_k e^{i k phi}; since the
+      // alpha_k sum to zero its real part is tau mu - 2 sum_k alpha_k sin^2(k phi / 2)
+      long double re = 0.0L, im = 0.0L;
+      for (int k = 1; k < p.taps; ++k) {
+        const long double hk = sinpi_ratio((long long)k * (t + 1), 2LL * (n + 1));
+        re += -2.0L * p.tcf[k] * hk * hk;
+        im += p.tcf[k] * sinpi_ratio((long long)k * (t + 1), n + 1);
+      }
+      tcoef[4 * t + 0] = (double)re;
+      tcoef[4 * t + 1] = 1.0;
+      tcoef[4 * t + 2] = (double)im;
       tcoef[4 * t + 3] = 0.0;
     }
     ez[t] = (double)(2.0L * sh);
@@ -1172,19 +1187,23 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       cols[i] = forced(p) ? p.spec_c : !spec_cols_ok(p.hp, 32) ? 16 : group(p) >= cus ? 32 : 16;
     }
   }
+  // kernel instantiation of an instance's fused launch: 3 time taps (theta, BDF2) or 5
+  auto taps_of = [](const Plan &p) { return p.taps <= 3 ? 3 : 5; };
   std::stable_sort(spec_ids.begin(), spec_ids.end(), [&](int a, int c) {
     const Plan &pa = plans[a]->p, &pc = plans[c]->p;
     if (pa.hp != pc.hp) return pa.hp < pc.hp;
+    if (taps_of(pa) != taps_of(pc)) return taps_of(pa) < taps_of(pc);
     return cols[a] != cols[c] ? cols[a] < cols[c] : pa.pprec < pc.pprec;
   });
-  struct Class { int first, count, blocks, hp, cols, pprec; };
+  struct Class { int first, count, blocks, hp, cols, pprec, taps; };
   std::vector<Class> classes;
   std::vector<SpecP> table(spec_ids.size());
   for (size_t k = 0; k < spec_ids.size(); ++k) {
     const Plan &p = plans[spec_ids[k]]->p;
     const int c = cols[spec_ids[k]];
-    if (classes.empty() || classes.back().hp != p.hp || classes.back().cols != c || classes.back().pprec != p.pprec)
-      classes.push_back(Class{(int)k, 0, 0, p.hp, c, p.pprec});
+    if (classes.empty() || classes.back().hp != p.hp || classes.back().cols != c || classes.back().pprec != p.pprec ||
+        classes.back().taps != taps_of(p))
+      classes.push_back(Class{(int)k, 0, 0, p.hp, c, p.pprec, taps_of(p)});
     Class &cl = classes.back();
     table[k] = spec_desc(&p, p.T2, p.T1, c);
     table[k].tile0 = cl.blocks;
@@ -1240,7 +1259,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       for (const KClass &cl : kclasses)
         LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
     for (const Class &cl : classes)
-      LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, 0, 0));
+      LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps, 0, 0));
     // one iteration j: the per-level matvec of every N class, then the fused launch of every
     // time-size class
     // One captured iteration j: the per-level matvec of every N class, then the fused launch of
@@ -1293,7 +1312,8 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       if (e == hipSuccess)
         e = phase(cs, (int)classes.size(), [&](hipStream_t st, int c) {
           const Class &cl = classes[c];
-          return launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, j == 1 ? 1 : 2, j);
+          return launch_spec_multi(st, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps,
+                                   j == 1 ? 1 : 2, j);
         });
       return e;
     };
@@ -1303,7 +1323,8 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     if (!g_prof.on) {
       std::vector<long> key{(long)(uintptr_t)d_ws};
       for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
-      for (const Class &cl : classes) key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec});
+      for (const Class &cl : classes)
+        key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps});
       g6 = batch_graph(bst, key, [&](hipStream_t cs) {
         hipError_t e = hipSuccess;
         for (int j = 6; j < 12 && e == hipSuccess; ++j) e = iteration_par(cs, j);
@@ -1328,7 +1349,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
           for (const KClass &cl : kclasses)
             LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
           for (const Class &cl : classes)
-            LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec,
+            LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps,
                                                 j == 1 ? 1 : 2, j));
         }
         issued += todo;

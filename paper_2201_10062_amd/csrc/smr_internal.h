@@ -35,10 +35,31 @@ struct Scal {
   int nres, pad;                        // true residuals evaluated so far
 };
 
+// Time coefficients of one block row of T (Sec. 1 and Sec. 4): (T x)_t = sum_k c_k x_{t-k} +
+// tau K (b_0 x_t + b_1 x_{t-1}).  Theta method: c = (1, -1), b = (theta, 1 - theta); BDF-l: c
+// the l-step backward difference formula (sum_{j=1}^{l} nabla^j / j), b = (1, 0).  Returns the
+// number of levels (2, or l + 1); c is zero past it.  Shared by the host set-up and the kernels,
+// which take the scheme and theta from their descriptors rather than a coefficient array.
+__host__ __device__ inline int scheme_coefs(int scheme, double theta, double (&c)[5], double (&b)[2]) {
+  for (int k = 0; k < 5; ++k) c[k] = 0.0;
+  b[0] = 1.0;
+  b[1] = 0.0;
+  switch (scheme) {
+    case SMR_BDF2: c[0] = 1.5; c[1] = -2.0; c[2] = 0.5; return 3;
+    case SMR_BDF3: c[0] = 11.0 / 6.0; c[1] = -3.0; c[2] = 1.5; c[3] = -1.0 / 3.0; return 4;
+    case SMR_BDF4: c[0] = 25.0 / 12.0; c[1] = -4.0; c[2] = 3.0; c[3] = -4.0 / 3.0; c[4] = 0.25; return 5;
+    default: c[0] = 1.0; c[1] = -1.0; b[0] = theta; b[1] = 1.0 - theta; return 2;
+  }
+}
+
 // Host-side plan: parameters plus device pointers into the caller's workspace.
 struct Plan {
   // parameters
   int dim, N, n, m, scheme, precond, pprec, cheb_k, flags;
+  int taps;                   // time levels one block row of T couples: 2 (theta), l + 1 (BDF-l)
+  double tcf[5];              // time-difference coefficients of those levels (theta: 1, -1;
+                              // BDF-l: alpha_0 .. alpha_l), zero past taps
+  double kbf[2];              // weights of K on levels t and t-1 (theta: theta, 1 - theta; BDF: 1, 0)
   size_t len;                 // n*m
   int ld;                     // row stride of the sine-basis vectors: m rounded up to 32
   size_t vlen;                // n*ld: elements of every work vector
@@ -186,7 +207,7 @@ hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool
 // cols: column-tile width of the launch (0: the plan's own)
 SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols = 0);
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
-                             int mode, int j);
+                             int taps, int mode, int j);
 hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int slot, Scal *out);
 // Column-tile width (spatial modes per workgroup) of the fused kernel: 16 or 32, the latter
 // for hp <= 128 only (two 32-column LDS blocks of 256 rows do not fit).

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsmr.so")
 SMR_OK, SMR_EINVAL, SMR_EWORKSPACE, SMR_EDEVICE, SMR_ENOTSPD, SMR_EBREAKDOWN, SMR_ENOTCONV, SMR_EUNSUPPORTED = range(8)
 STATUS_NAMES = {0: "ok", 1: "einval", 2: "eworkspace", 3: "edevice", 4: "enotspd", 5: "ebreakdown",
                 6: "enotconv", 7: "eunsupported"}
-SCHEMES = {"theta": 0, "bdf2": 2}
+SCHEMES = {"theta": 0, "bdf2": 2, "bdf3": 3, "bdf4": 4}
 PRECONDS = {"PH": 0, "PTHETA_CHEB": 2, "NONE": 3}
 PPRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
 

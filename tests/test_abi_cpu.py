@@ -38,6 +38,8 @@ def test_library_exports_every_declared_symbol():
     (dict(dim=2, N=1023, n=4), smr.SMR_EINVAL),        # N too large
     (dict(dim=2, N=7, n=0), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=1, scheme="bdf2"), smr.SMR_EINVAL),
+    (dict(dim=2, N=7, n=3, scheme="bdf4"), smr.SMR_EINVAL),         # BDF-l needs n >= l
+    (dict(dim=2, N=7, n=8, scheme="bdf3", precond="PTHETA_CHEB"), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=4, theta=1.5), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=4, T=-1.0), smr.SMR_EINVAL),
     (dict(dim=2, N=7, n=4, precond="PTHETA_CHEB", cheb_k=0), smr.SMR_EINVAL),
