@@ -150,6 +150,14 @@ def ptheta_eigs(n: int, theta: float):
     return eta, zeta
 
 
+def sigma_ptheta(mu: np.ndarray, n: int, tau: float, theta: float) -> np.ndarray:
+    """Eigenvalues eta_j + tau zeta_j mu_k of P_theta when K = U diag(mu) U^T (constant a):
+    then every per-mode block of Sec. 3.1.4 is diagonal in the spatial sine basis and
+    P_theta^{-1} takes the same three steps as P_H with these values.  Shape (n, len(mu))."""
+    eta, zeta = ptheta_eigs(n, theta)
+    return eta[:, None] + tau * zeta[:, None] * np.asarray(mu, dtype=np.float64)[None, :]
+
+
 def ptheta_dense(K, n: int, tau: float, theta: float) -> np.ndarray:
     """P_theta = H (x) I + H_theta (x) tau K assembled with dense matrix square roots."""
     T2 = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
@@ -212,8 +220,8 @@ def cheb_params(a_min: float, a_max: float):
 def pinv_ptheta_cheb(v: np.ndarray, K, N: int, dim: int, n: int, tau: float, theta: float,
                      k: int, a_min: float, a_max: float) -> np.ndarray:
     """P_theta^{-1} v with each per-mode solve replaced by k Chebyshev steps whose
-    inner preconditioner eta_j I + tau zeta_j abar K_lap is applied by 2D (or 1D)
-    sine transforms."""
+    inner preconditioner eta_j I + tau zeta_j abar K_lap is applied by the spatial
+    sine transforms (1D, 2D or 3D)."""
     from .spatial import mu_const
     m = K.shape[0]
     eta, zeta = ptheta_eigs(n, theta)

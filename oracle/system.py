@@ -22,19 +22,23 @@ from .minres import minres
 class System:
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0,
                  ax=None, ay=None, a_nodal=None, T: float = 1.0, precond: str = "PH",
-                 cheb_k: int = 3):
+                 cheb_k: int = 3, az=None):
         self.dim, self.N, self.n, self.scheme, self.theta = dim, N, n, scheme, float(theta)
         self.T = float(T)
         self.tau = self.T / n
         self.h = 1.0 / (N + 1)
         self.m = N ** dim
         if a_nodal is not None:
+            if dim == 3:
+                raise ValueError("3D coefficients are given as face values")
             ax, ay = spatial.faces_from_nodal(a_nodal, dim)
         self.const = ax is None
         if ax is None:
-            ax, ay = spatial.const_faces(N, dim)
-        self.ax, self.ay = ax, ay
-        self.K = spatial.stiffness(N, dim, ax, ay)
+            faces = spatial.const_faces(N, dim)
+            ax, ay = faces[0], faces[1]
+            az = faces[2] if dim == 3 else None
+        self.ax, self.ay, self.az = ax, ay, az
+        self.K = spatial.stiffness(N, dim, ax, ay, az)
         if scheme == "theta":
             self.blocks = aao.theta_blocks(self.K, self.tau, self.theta)
         elif scheme == "bdf2":
@@ -46,10 +50,10 @@ class System:
             raise ValueError(scheme)
         self.precond = precond
         self.cheb_k = cheb_k
-        self.a_min, self.a_max = spatial.coef_bounds(N, dim, ax, ay)
+        self.a_min, self.a_max = spatial.coef_bounds(N, dim, ax, ay, az)
         # eigenvalues used by P_H / Phat: those of K itself when a is constant, of the
         # averaged Kbar otherwise (the two coincide for constant face values)
-        self.mu = spatial.mu_kbar(N, dim, ax, ay)
+        self.mu = spatial.mu_kbar(N, dim, ax, ay, az)
         if scheme == "theta":
             self.sigma = pc.sigma_theta(self.mu, n, self.tau, self.theta)
         elif scheme == "bdf2":

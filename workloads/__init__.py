@@ -28,7 +28,7 @@ __all__ = [
     "Problem", "interior", "sample_faces", "sample_nodal", "sample_grid_fn",
     "manufactured_1d", "crank_nicolson_2d_noisy", "variable_coef_2d",
     "bdf2_batch", "inverse_problem_2d", "example1", "example2", "example2_exact",
-    "bdf2_batch_spec", "bump_centres",
+    "bdf2_batch_spec", "bump_centres", "example3",
 ]
 
 
@@ -40,7 +40,7 @@ class Problem:
     f: (n+1, N^dim) source samples at t_0..t_n (theta scheme), or None.
     b: (n, N^dim) right-hand side given directly (BDF2 batch), or None.
     u0: (N^dim,) initial value at interior nodes.
-    ax, ay: face coefficients (None means a == 1 everywhere).
+    ax, ay, az: face coefficients (None means a == 1 everywhere; az in 3D only).
     a_nodal: nodal coefficient on the (N+2)^dim grid, or None.
     """
     dim: int
@@ -56,6 +56,7 @@ class Problem:
     ay: Optional[np.ndarray] = None
     a_nodal: Optional[np.ndarray] = None
     name: str = ""
+    az: Optional[np.ndarray] = None
 
     @property
     def m(self) -> int:
@@ -235,6 +236,17 @@ def example2(N: int, n: int, theta: float) -> Problem:
     u0 = (X * (1 - X) * Y * (1 - Y)).reshape(-1)
     return Problem(dim=2, N=N, n=n, theta=theta, f=f, u0=u0, ax=ax, ay=ay,
                    name=f"example2_N{N}_n{n}_theta{theta}")
+
+
+def example3(N: int, n: int, theta: float) -> Problem:
+    """Example 3: 3D, a = 1e-3, u0 = x(x-1)y(y-1)z(z-1), f = g = 0, T = 1."""
+    xi = interior(N)
+    Z, Y, X = np.meshgrid(xi, xi, xi, indexing="ij")      # [k, j, i], x fastest
+    u0 = (X * (X - 1) * Y * (Y - 1) * Z * (Z - 1)).reshape(-1)
+    a = 1e-3
+    return Problem(dim=3, N=N, n=n, theta=theta, f=np.zeros((n + 1, N ** 3)), u0=u0,
+                   ax=np.full((N, N, N + 1), a), ay=np.full((N, N + 1, N), a), az=np.full((N + 1, N, N), a),
+                   name=f"example3_N{N}_n{n}_theta{theta}")
 
 
 def example2_exact(N: int, n: int) -> np.ndarray:
