@@ -44,8 +44,9 @@ TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_k_spec_multi_bdf2_b
 CSRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc")
 
 
-def kernel_hash(files=("k_spec.hip", "mfma_tiles.h")) -> str:
-    """Hash of a kernel's sources (the fused kernel's file and its matrix-core tile header)."""
+def kernel_hash(files=("k_spec.hip", "k_spec_impl.h", "mfma_tiles.h")) -> str:
+    """Hash of the fused kernel's sources (its launch file, the kernel templates and the
+    matrix-core tile header)."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(CSRC, f), "rb") as fh:

@@ -10,8 +10,8 @@
  *   - the theta-method (eq. theta): T_H has A0 = I + theta tau K on the block
  *     diagonal and A1 = -I + (1-theta) tau K below it;
  *   - BDF-l, l = 2, 3, 4 (eqn:matrix_gen): A0 = alpha_0 I + tau K, A_k = alpha_k I.
- * K = K(a) is the 3-point (1D) or 5-point (2D) stencil of eqn:matrix_Km_va built from
- * face values of a.  The library solves Y T u = Y f_H (eqn:main_system, Y the time
+ * K = K(a) is the 3-point (1D), 5-point (2D) or 7-point (3D, the setting of Sec. 5's
+ * Example 3) stencil of eqn:matrix_Km_va built from face values of a.  The library solves Y T u = Y f_H (eqn:main_system, Y the time
  * flip) by preconditioned MINRES with
  *   - SMR_P_H: P_H (def:matrix_P) or, for BDF-l, Phat (def:matrix_P_gen); for
  *     variable a the averaged Toeplitz Kbar of Sec. 3.1.1 replaces K inside P only.
@@ -20,11 +20,12 @@
  *   - SMR_P_THETA_CHEB: P_theta (def:matrix_mod_P) whose per-time-mode SPD solves
  *     (eta_j I + tau zeta_j K(a)) are replaced by k steps of Chebyshev iteration
  *     preconditioned by eta_j I + tau zeta_j abar K_lap (the paper leaves the inner
- *     solver open);
+ *     solver open).  For constant a that inner preconditioner is exact, and P_theta^{-1}
+ *     is the sine-basis division by eta_j + tau zeta_j mu_k (one step solves each mode);
  *   - SMR_P_NONE: identity.
  *
  * Conventions shared by every entry point
- *   Layout: every vector is float64, C-ordered (time, y, x), x fastest; a solution /
+ *   Layout: every vector is float64, C-ordered (time, [z,] y, x), x fastest; a solution /
  *     right-hand side has n*m entries, a source f has (n+1)*m (levels t_0..t_n).
  *   Pointers: arguments named d_* or documented "device" are device pointers on the
  *     current HIP device; "host" pointers are ordinary host memory.  The caller owns
@@ -43,8 +44,8 @@
  *   Errors: every call returns an smr_status; no exception crosses the ABI.  On any
  *     status other than SMR_OK a human-readable reason is available from
  *     smr_last_error() (thread-local, valid until the next call on the thread).
- *   Limits: dim in {1, 2}; N + 1 a power of two with 2 <= N + 1 <= 512; 1 <= n <= 1024
- *     (n >= l for BDF-l); 0 <= theta <= 1; every face value finite and > 0.
+ *   Limits: dim in {1, 2, 3}; N + 1 a power of two with 2 <= N + 1 <= 512 (<= 128 in 3D);
+ *     1 <= n <= 1024 (n >= l for BDF-l); 0 <= theta <= 1; every face value finite and > 0.
  */
 #ifndef SMR_H
 #define SMR_H
@@ -86,11 +87,13 @@ typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 /* P_H / Phat solves run in the spatial sine basis (b and x0 transformed on entry, x on exit;
  * the same iterates in exact arithmetic): for constant a, Y T and P^{-1} act per spatial mode
- * and one fused kernel does a MINRES iteration; for a variable a in 2D with N + 1 in
+ * and one fused kernel does a MINRES iteration (so do P_theta solves of a constant a, whose
+ * per-mode blocks are then diagonal in that basis); for a variable a in 2D with N + 1 in
  * {32, 64, 128} (Kbar inside P, Sec. 3.1.1), a per-time-level kernel first applies
  * U K(a) U (sine transforms held in LDS) and the fused kernel takes that matvec.  Other
- * variable-coefficient cases, P_theta and P = I run the general physical-basis iteration
- * (stencil matvec and 3D transforms), which this flag forces for every plan. */
+ * variable-coefficient cases, P_theta of a variable a and P = I run the general
+ * physical-basis iteration (stencil matvec and space-time transforms), which this flag
+ * forces for every plan. */
 #define SMR_FLAG_GENERAL_PATH 1
 /* Column-tile width of the fused sine-basis kernel: each workgroup owns that many spatial
  * modes of all n time levels (the folded time blocks of Sec. 3.1.1 are contracted per tile
@@ -103,7 +106,7 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 #define SMR_FLAG_TILE32 4
 
 typedef struct {
-  int32_t dim;             /* spatial dimension, 1 or 2                                   */
+  int32_t dim;             /* spatial dimension, 1, 2 or 3                                */
   int32_t N;               /* interior points per axis                                    */
   int32_t n;               /* time steps                                                  */
   int32_t scheme;          /* smr_scheme                                                  */
@@ -119,12 +122,16 @@ typedef struct {
    *   face values: dim 1: ax[N+1], ax[i] = a((i+1/2)h);
    *                dim 2: ax[N][N+1], ax[j][i] = a((i+1/2)h, (j+1)h) and
    *                       ay[N+1][N], ay[j][i] = a((i+1)h, (j+1/2)h);
-   *   nodal values: a_nodal[(N+2)^dim] on the grid including the boundary; each face
-   *                 takes the mean of its two end nodes;
+   *                dim 3: ax[N][N][N+1], ax[k][j][i] = a((i+1/2)h, (j+1)h, (k+1)h),
+   *                       ay[N][N+1][N], ay[k][j][i] = a((i+1)h, (j+1/2)h, (k+1)h) and
+   *                       az[N+1][N][N], az[k][j][i] = a((i+1)h, (j+1)h, (k+1/2)h);
+   *   nodal values (dim 1, 2): a_nodal[(N+2)^dim] on the grid including the boundary; each
+   *                 face takes the mean of its two end nodes;
    *   all NULL: a = 1. */
   const double *ax_host;
   const double *ay_host;
   const double *a_nodal_host;
+  const double *az_host;   /* dim 3 face values along z (with ax_host, ay_host); else NULL */
 } smr_desc;
 
 typedef struct {
@@ -233,8 +240,9 @@ smr_status smr_solve_adjoint_batched(int32_t count, const smr_plan *const *plans
 smr_status smr_rhs_adjoint(const smr_plan *plan, const double *d_lambda, double *d_grad_f,
                            double *d_grad_u0, void *stream);
 
-/* Gradient of a loss w.r.t. the coefficient, given the forward solution u (n*m), the
- * initial value u0 (m, NULL = 0) and the adjoint lambda (n*m):
+/* Gradient of a loss w.r.t. the coefficient (dim 1 and 2; SMR_EUNSUPPORTED in 3D), given
+ * the forward solution u (n*m), the initial value u0 (m, NULL = 0) and the adjoint
+ * lambda (n*m):
  * grad a_e = -(tau/h^2) sum_k (D_e lambda_k)(D_e utilde_k), utilde_k = theta u_k + (1-theta) u_{k-1}
  * (u_0 = u0; BDF-l: utilde_k = u_k), D_e the difference across face e.  Outputs (device,
  * each may be NULL): face gradients d_gax (shaped like ax), d_gay (dim 2) and the nodal

@@ -1,6 +1,6 @@
 // Spatial sine transforms (gfx950), general form.  The orthonormal DST-I S_N (Sec. 3.1.1, S_n of
-// eqn:matrix_tri_p with n -> N) along x (contiguous lines) or y (stride-N lines) of
-// every time slice, for N + 1 = L a power of two.
+// eqn:matrix_tri_p with n -> N) along x (contiguous lines), y (stride-N lines) or, in 3D, z
+// (stride-N^2 lines) of every time slice, for N + 1 = L a power of two.
 //
 // Method: two real lines a, b are packed as z = a + i b, extended oddly to length
 // M = 2L (z_0 = z_L = 0, z_{2L-j} = -z_j) and transformed by one complex radix-2 FFT
@@ -16,7 +16,7 @@ namespace {
 
 struct DstP {
   int N, L, M, logM, m, nslices, ppb, tpp, dim, n;
-  int rows;                   // lines per slice: N (2D) or 1 (1D)
+  int rows;                   // lines per slice: 1 (1D), N (2D) or N^2 (3D)
   long sin, sout;             // slice strides of the input and the output (>= m)
   long nlines;
   double scale;               // 1/sqrt(2L)
@@ -34,12 +34,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Offset of element j of line r inside its slice, and the slice of line r.
+// Offset of element j of line r inside its slice, and the slice of line r.  Line i of a slice:
+// x-line i (rows of N, i = z*N + y); y-line i = z*N + x; z-line i = y*N + x.
 template <int DIR>
 __device__ __forceinline__ size_t in_slice(const DstP &d, long r, int j, long &s) {
   s = r / d.rows;
   const int i = (int)(r - s * d.rows);
-  return DIR == 0 ? (size_t)i * d.N + j : (size_t)j * d.N + i;   // row i, or column i
+  const size_t N = d.N;
+  if (DIR == 0) return (size_t)i * N + j;
+  if (DIR == 1) return (size_t)(i / d.N) * N * N + (size_t)j * N + (size_t)(i % d.N);
+  return (size_t)j * N * N + (size_t)i;
 }
 
 template <int DIR>
@@ -64,7 +68,7 @@ __global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ 
   for (int e = tid; e < total; e += nthr) {
     int c, j;
     if (DIR == 0) { c = e / d.N; j = e - c * d.N; }
-    else { j = e / lpb; c = e - j * lpb; }
+    else { j = e / lpb; c = e - j * lpb; }   // neighbouring threads: neighbouring lines
     const long r = r0 + c;
     double v = 0.0;
     if (r < d.nlines) {
@@ -121,7 +125,7 @@ DstP make_dst(const Plan *p, int dir, int nslices) {
   d.n = p->n;
   d.dim = p->dim;
   d.nslices = nslices;
-  d.rows = p->dim == 1 ? 1 : p->N;
+  d.rows = p->dim == 1 ? 1 : p->dim == 2 ? p->N : p->N * p->N;
   d.nlines = (long)nslices * d.rows;
   d.sin = d.sout = p->m;
   const int half = d.M / 2;
@@ -149,6 +153,7 @@ static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nsl
                           const Scal *gate, long in_stride, long out_stride) {
   // 2D with N + 1 in {32, ..., 256}: line tiles through the register FFT
   if (dst_tile_supported(c.p)) return launch_dst_tile(c, dir, in, out, nslices, scale_mode, gate, in_stride, out_stride);
+  if (dir < 0 || dir >= c.p->dim) return hipErrorInvalidValue;
   DstP d = make_dst(c.p, dir, nslices);
   d.scale_mode = scale_mode;
   if (in_stride) d.sin = in_stride;
@@ -157,13 +162,15 @@ static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nsl
   const long nblocks = (d.nlines + lpb - 1) / lpb;
   const size_t shmem = ((size_t)d.ppb * d.M + d.M / 2) * sizeof(double2);
   if (shmem > 65536) {
-    hipError_t e = lds_limit(dir == 0 ? (const void *)k_dst<0> : (const void *)k_dst<1>, shmem);
+    hipError_t e = lds_limit(dir == 0 ? (const void *)k_dst<0> : dir == 1 ? (const void *)k_dst<1> : (const void *)k_dst<2>, shmem);
     if (e != hipSuccess) return e;
   }
   if (dir == 0)
     hipLaunchKernelGGL(k_dst<0>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
-  else
+  else if (dir == 1)
     hipLaunchKernelGGL(k_dst<1>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
+  else
+    hipLaunchKernelGGL(k_dst<2>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
   return hipGetLastError();
 }
 

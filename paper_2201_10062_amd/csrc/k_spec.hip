@@ -16,8 +16,9 @@
 //   C. z_{j+1} = S diag(1/sigma) S v_{j+1} on the FP64 matrix cores (two folded GEMMs),
 //      gamma_{j+1}^2 = <v, z> by Parseval between them;
 //   D. z_{j+1} stored, <(Y T)^ z_{j+1}, z_{j+1}> partial (gives delta_{j+1});
-//   E. block partials -> the last block to finish reduces them in a fixed order and runs
-//      the MINRES scalar recurrence (Givens rotation, convergence test).
+//   E. block partials, which every block of the next launch sums in a fixed order before
+//      running the MINRES scalar recurrence (Givens rotation, convergence test) itself; above
+//      kDirectTiles tiles a small launch between the two first sums them per tile group.
 // The iterate x_{j-1} and its residual are final one launch after v_j, z_j: the stop test
 // is the same (first iteration whose true residual is <= rtol), one launch later.
 #include "k_spec_impl.h"
@@ -75,12 +76,47 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   P.V[0] = p->V[0]; P.V[1] = p->V[1]; P.W[0] = p->W[0]; P.W[1] = p->W[1];
   P.x = x; P.bh = bh; P.part = p->part; P.sc = p->sc;
   P.x0zero = 0; P.rtol = 0.0; P.maxit = 0;
+  P.rtiles = P.tiles > kDirectTiles ? kPartGroups : 0;
   if (!p->const_coef) {
     P.qext = p->QX;
     P.kpart = p->part + kKsPartOffset;
     P.nks = p->n;
   }
   return P;
+}
+
+size_t spec_part_doubles(int m) {
+  const size_t tiles = (size_t)(m + 15) / 16;          // the narrow width has the most tiles
+  const size_t need = 8 * tiles + 8 * (size_t)kPartGroups;
+  return need > 16 * (size_t)kRedSlots ? need : 16 * (size_t)kRedSlots;
+}
+
+// Partial sums of fused launch j (slot j & 1) added per tile group: group g of kPartGroups
+// owns a fixed, contiguous range of tiles, summed by one block in a fixed order.  Skipped
+// when launch j found the solve stopped (it then wrote no partials, and the next launch does
+// not read them).
+__global__ __launch_bounds__(256) void k_part_reduce(double *__restrict__ part, int tiles, int slot,
+                                                     const Scal *__restrict__ sc) {
+  if (sc[slot].status != RUNNING) return;
+  __shared__ double red[4][4];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int per = (tiles + kPartGroups - 1) / kPartGroups;
+  const int b0 = g * per, b1 = min(tiles, b0 + per);
+  const double *pp = part + (size_t)slot * 4 * tiles;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = b0 + tid; b < b1; b += 256)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] += pp[4 * (size_t)b + q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_xor(t[q], off, 64);
+  if ((tid & 63) == 0)
+    for (int q = 0; q < 4; ++q) red[q][tid >> 6] = t[q];
+  __syncthreads();
+  if (tid < 4) {
+    double* out = part + 8 * (size_t)tiles + (size_t)slot * 4 * kPartGroups + 4 * (size_t)g;
+    out[tid] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+  }
 }
 
 // mode of launch j - 1, whose partial sums launch j reduces (an early steady launch leaves
@@ -97,7 +133,10 @@ hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool
   P.rtol = rtol;
   P.maxit = maxit;
   const int jph = j % 6, pmode = prev_mode(mode, j);
-  return run_one(c.st, P, p->pprec, p->spec_c, launch_mode(mode, j), P.tiles, p->hp, jph, pmode);
+  hipError_t e = run_one(c.st, P, p->pprec, p->spec_c, launch_mode(mode, j), P.tiles, p->hp, jph, pmode);
+  if (e != hipSuccess || !P.rtiles) return e;
+  hipLaunchKernelGGL(k_part_reduce, dim3(kPartGroups), dim3(256), 0, c.st, p->part, P.tiles, j & 1, p->sc);
+  return hipGetLastError();
 }
 
 hipError_t spec_tune(Plan *p, hipStream_t st) {
@@ -128,9 +167,11 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       p->spec_c = cand[k];
       const SpecP P = spec_desc(p, p->T1, p->T2);
-      const int npart = 4 * P.tiles, nk = P.kpart ? 4 * P.nks : 0;
+      // the partials launch 7 reads: per tile, or per tile group
+      const int npart = 4 * (P.rtiles ? P.rtiles : P.tiles), nk = P.kpart ? 4 * P.nks : 0;
+      double *tpart = P.rtiles ? p->part + 8 * (size_t)P.tiles : p->part;
       auto one = [&]() {
-        hipLaunchKernelGGL(k_tune_state, dim3((npart + 255) / 256), dim3(256), 0, st, p->sc, p->part, npart,
+        hipLaunchKernelGGL(k_tune_state, dim3((npart + 255) / 256), dim3(256), 0, st, p->sc, tpart, npart,
                            P.kpart ? p->part + kKsPartOffset : nullptr, nk, s);
         hipError_t r = hipGetLastError();
         return r == hipSuccess ? run_one(st, P, p->pprec, cand[k], MODE_STEADY, P.tiles, p->hp, 1, MODE_STEADY) : r;

@@ -233,9 +233,12 @@ __device__ __forceinline__ void spec_body(const SpecP &P, const int jph, const i
     const Scal *sprev = P.sc + ((j + 1) & 1);
     Scal *snew = P.sc + (j & 1);
     if (tid == 0) S = *sprev;      // in flight with the partial sums below
-    const double *pp = P.part + (size_t)((j + 1) & 1) * 4 * P.tiles;
+    // the previous launch's partials: one entry per tile, or per tile group once reduced
+    const int npp = P.rtiles ? P.rtiles : P.tiles;
+    const double *pp = P.rtiles ? P.part + 8 * (size_t)P.tiles + (size_t)((j + 1) & 1) * 4 * P.rtiles
+                                : P.part + (size_t)((j + 1) & 1) * 4 * P.tiles;
     double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // t[4]: residuals skipped by the per-level matvec
-    for (int b = tid; b < P.tiles; b += kThreads) {
+    for (int b = tid; b < npp; b += kThreads) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) t[q] += pp[4 * (size_t)b + q];
     }

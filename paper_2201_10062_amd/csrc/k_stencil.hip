@@ -13,18 +13,18 @@ namespace smr {
 
 namespace {
 
-constexpr int kTX = 64, kTY = 4;      // 2D tile: 64 x-points by 4 y-rows per block
+constexpr int kTX = 64, kTY = 4;      // 2D / 3D tile: 64 x-points by 4 rows (y, or z*N + y) per block
 constexpr int kT1 = 256;              // 1D tile
 
 struct SP {                           // stencil parameters passed by value
   int dim, N, n, m, scheme, taps;
   double tau, theta, h2inv;
   double tc[5];                       // time-difference coefficients of the levels t .. t-4
-  const double *ax, *ay;
+  const double *ax, *ay, *az;
 };
 
 inline SP make_sp(const Plan *p) {
-  SP s{p->dim, p->N, p->n, p->m, p->scheme, p->taps, p->tau, p->theta, p->h2inv, {}, p->ax, p->ay};
+  SP s{p->dim, p->N, p->n, p->m, p->scheme, p->taps, p->tau, p->theta, p->h2inv, {}, p->ax, p->ay, p->az};
   for (int k = 0; k < 5; ++k) s.tc[k] = p->tcf[k];
   return s;
 }
@@ -52,7 +52,8 @@ __device__ __forceinline__ double comb(const double *__restrict__ x0, double c0,
   return v;
 }
 
-// (K u)(j, i) with u = c0*x0 + c1*x1 on one slice; zero Dirichlet values outside.
+// (K u)(j, i) with u = c0*x0 + c1*x1 on one slice; zero Dirichlet values outside.  Row j is y
+// in 2D and z*N + y in 3D (the 7-point stencil adds the two z neighbours N^2 apart).
 __device__ __forceinline__ double Kapply(const SP &s, const double *__restrict__ x0, double c0,
                                          const double *__restrict__ x1, double c1, int j, int i) {
   const int N = s.N;
@@ -62,15 +63,24 @@ __device__ __forceinline__ double Kapply(const SP &s, const double *__restrict__
     const double ue = i < N - 1 ? comb(x0, c0, x1, c1, i + 1) : 0.0;
     return s.h2inv * (s.ax[i] * (uc - uw) + s.ax[i + 1] * (uc - ue));
   }
+  const int y = s.dim == 3 ? j % N : j, z = s.dim == 3 ? j / N : 0;
   const int q = j * N + i;
   const double uc = comb(x0, c0, x1, c1, q);
   const double uw = i > 0 ? comb(x0, c0, x1, c1, q - 1) : 0.0;
   const double ue = i < N - 1 ? comb(x0, c0, x1, c1, q + 1) : 0.0;
-  const double us = j > 0 ? comb(x0, c0, x1, c1, q - N) : 0.0;
-  const double un = j < N - 1 ? comb(x0, c0, x1, c1, q + N) : 0.0;
+  const double us = y > 0 ? comb(x0, c0, x1, c1, q - N) : 0.0;
+  const double un = y < N - 1 ? comb(x0, c0, x1, c1, q + N) : 0.0;
   const double aw = s.ax[j * (N + 1) + i], ae = s.ax[j * (N + 1) + i + 1];
-  const double as = s.ay[j * N + i], an = s.ay[(j + 1) * N + i];
-  return s.h2inv * (aw * (uc - uw) + ae * (uc - ue) + as * (uc - us) + an * (uc - un));
+  const int ya = (z * (N + 1) + y) * N + i;
+  const double as = s.ay[ya], an = s.ay[ya + N];
+  double v = aw * (uc - uw) + ae * (uc - ue) + as * (uc - us) + an * (uc - un);
+  if (s.dim == 3) {
+    const int NN = N * N;
+    const double ud = z > 0 ? comb(x0, c0, x1, c1, q - NN) : 0.0;
+    const double uu = z < N - 1 ? comb(x0, c0, x1, c1, q + NN) : 0.0;
+    v += s.az[q] * (uc - ud) + s.az[q + NN] * (uc - uu);
+  }
+  return s.h2inv * v;
 }
 
 // (T x)_k at spatial point (j, i): theta scheme x_k - x_{k-1} + tau K(theta x_k + (1-theta) x_{k-1});
@@ -93,6 +103,9 @@ struct TileInfo {
   int ni, nj, ntiles;
 };
 
+// rows of one slice: y (2D) or z*N + y (3D)
+__host__ __device__ inline int rows_of(int dim, int N) { return dim == 1 ? 1 : dim == 2 ? N : N * N; }
+
 inline TileInfo tiles_of(const Plan *p, int nslices) {
   TileInfo t;
   if (p->dim == 1) {
@@ -100,7 +113,7 @@ inline TileInfo tiles_of(const Plan *p, int nslices) {
     t.nj = 1;
   } else {
     t.ni = (p->N + kTX - 1) / kTX;
-    t.nj = (p->N + kTY - 1) / kTY;
+    t.nj = (rows_of(p->dim, p->N) + kTY - 1) / kTY;
   }
   t.ntiles = t.ni * t.nj * nslices;
   return t;
@@ -120,7 +133,7 @@ __device__ __forceinline__ bool tile_point(int t, int ni, int nj, int N, int dim
     i = it * kTX + threadIdx.x;
     j = jt * kTY + threadIdx.y;
   }
-  return i < N && j < (dim == 1 ? 1 : N);
+  return i < N && j < rows_of(dim, N);
 }
 
 // MODE 0: y = Y T (xs x), partial <y, xs x>.   MODE 1: r = Y rhs - Y T x (written to y
@@ -145,28 +158,37 @@ __global__ __launch_bounds__(256) void k_apply_YT(SP s, MarchP mp, const double 
   const int it = b % mp.ni, jt = (b / mp.ni) % mp.nj, kc = b / (mp.ni * mp.nj);
   const int i = s.dim == 1 ? it * kT1 + threadIdx.x : it * kTX + threadIdx.x;
   const int j = s.dim == 1 ? 0 : jt * kTY + threadIdx.y;
-  const bool ok = i < N && j < (s.dim == 1 ? 1 : N);
+  const bool ok = i < N && j < rows_of(s.dim, N);
   const int k0 = kc * mp.kr, k1 = min(s.n, k0 + mp.kr);
   double acc0 = 0.0, acc1 = 0.0;
   if (ok) {
     const int q = s.dim == 1 ? i : j * N + i;
+    const int jy = s.dim == 3 ? j % N : j, jz = s.dim == 3 ? j / N : 0;
+    const int NN = N * N;
     // neighbour offsets (0 = outside: the Dirichlet value 0) and face coefficients
-    const bool hw = i > 0, he = i < N - 1, hs = s.dim == 2 && j > 0, hn = s.dim == 2 && j < N - 1;
-    double aw, ae, as = 0.0, an = 0.0;
+    const bool hw = i > 0, he = i < N - 1, hs = s.dim >= 2 && jy > 0, hn = s.dim >= 2 && jy < N - 1;
+    const bool hd = s.dim == 3 && jz > 0, hu = s.dim == 3 && jz < N - 1;
+    double aw, ae, as = 0.0, an = 0.0, ad = 0.0, au = 0.0;
     if (s.dim == 1) {
       aw = s.ax[i];
       ae = s.ax[i + 1];
     } else {
       aw = s.ax[j * (N + 1) + i];
       ae = s.ax[j * (N + 1) + i + 1];
-      as = s.ay[j * N + i];
-      an = s.ay[(j + 1) * N + i];
+      const int ya = (jz * (N + 1) + jy) * N + i;
+      as = s.ay[ya];
+      an = s.ay[ya + N];
+      if (s.dim == 3) {
+        ad = s.az[q];
+        au = s.az[q + NN];
+      }
     }
     auto kx = [&](const double *xl, double &c) {   // c = x_l at q, returns (K x_l) at q
       c = xl[q];
       const double uw = hw ? xl[q - 1] : 0.0, ue = he ? xl[q + 1] : 0.0;
       const double us = hs ? xl[q - N] : 0.0, un = hn ? xl[q + N] : 0.0;
-      return s.h2inv * (aw * (c - uw) + ae * (c - ue) + as * (c - us) + an * (c - un));
+      const double ud = hd ? xl[q - NN] : 0.0, uu = hu ? xl[q + NN] : 0.0;
+      return s.h2inv * (aw * (c - uw) + ae * (c - ue) + as * (c - us) + an * (c - un) + ad * (c - ud) + au * (c - uu));
     };
     double xp[4] = {0.0, 0.0, 0.0, 0.0};           // x_{k-1} .. x_{k-4}
     double kx1 = 0.0;                              // (K x)_{k-1} (theta method)

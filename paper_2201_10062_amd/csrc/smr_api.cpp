@@ -169,9 +169,10 @@ int hp_of(int h1) {
 
 smr_status validate(const smr_desc *d) {
   if (!d) return fail(SMR_EINVAL, "desc is NULL");
-  if (d->dim != 1 && d->dim != 2) return fail(SMR_EINVAL, "dim must be 1 or 2 (got %d)", d->dim);
-  if (d->N < 1 || d->N > kMaxN || !is_pow2(d->N + 1))
-    return fail(SMR_EINVAL, "N + 1 must be a power of two in [2, %d] (got N = %d)", kMaxN + 1, d->N);
+  if (d->dim < 1 || d->dim > 3) return fail(SMR_EINVAL, "dim must be 1, 2 or 3 (got %d)", d->dim);
+  const int maxN = d->dim == 3 ? kMaxN3 : kMaxN;
+  if (d->N < 1 || d->N > maxN || !is_pow2(d->N + 1))
+    return fail(SMR_EINVAL, "N + 1 must be a power of two in [2, %d] in %dD (got N = %d)", maxN + 1, d->dim, d->N);
   if (d->scheme != SMR_THETA && d->scheme != SMR_BDF2 && d->scheme != SMR_BDF3 && d->scheme != SMR_BDF4)
     return fail(SMR_EINVAL, "unknown scheme %d", d->scheme);
   const int nmin = d->scheme == SMR_THETA ? 1 : d->scheme;   // BDF-l: n >= l
@@ -197,8 +198,11 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EUNSUPPORTED, "32-column tiles need ceil(n/2) <= 128 (got n = %d)", d->n);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
-  if (d->ax_host && d->dim == 2 && !d->ay_host) return fail(SMR_EINVAL, "dim 2 face values need ay");
+  if (d->ax_host && d->dim >= 2 && !d->ay_host) return fail(SMR_EINVAL, "dim %d face values need ay", d->dim);
+  if (d->ax_host && d->dim == 3 && !d->az_host) return fail(SMR_EINVAL, "dim 3 face values need az");
   if (!d->ax_host && d->ay_host) return fail(SMR_EINVAL, "ay given without ax");
+  if (d->az_host && (d->dim != 3 || !d->ax_host)) return fail(SMR_EINVAL, "az is for dim 3 face values (with ax, ay)");
+  if (d->a_nodal_host && d->dim == 3) return fail(SMR_EINVAL, "3D coefficients are given as face values");
   return SMR_OK;
 }
 
@@ -210,15 +214,19 @@ bool var_sine_basis(const smr_desc *d) {
          !(d->flags & SMR_FLAG_GENERAL_PATH) && (d->ax_host || d->a_nodal_host);
 }
 
+// interior points and face values per axis array: m = N^dim; faces along one axis (N+1) N^(dim-1)
+size_t m_of(int dim, int N) { return dim == 1 ? (size_t)N : dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
+size_t faces_of(int dim, int N) { return m_of(dim, N) / N * (N + 1); }
+
 struct Layout {
-  size_t ax, ay, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, vec0;
+  size_t ax, ay, az, tmu, tmu_lap, tcoef, ez, So, SoT, Se, SeT, Sof, SoTf, Sef, SeTf, zf, tw, gface, part, sc, vec0;
   int nvec;
   size_t total;
 };
 
 Layout layout_of(const smr_desc *d) {
   const int N = d->N, n = d->n, dim = d->dim;
-  const size_t m = dim == 1 ? (size_t)N : (size_t)N * N;
+  const size_t m = m_of(dim, N);
   const size_t len = (size_t)ld_of(m) * n;   // every work vector holds n rows of ld
   const int hp = hp_of((n + 1) / 2);
   const int L = N + 1;
@@ -229,8 +237,9 @@ Layout layout_of(const smr_desc *d) {
     off = align256(off + (bytes ? bytes : 8));
     return at;
   };
-  l.ax = take(sizeof(double) * (dim == 1 ? (size_t)(N + 1) : (size_t)N * (N + 1)));
-  l.ay = take(sizeof(double) * (dim == 1 ? 1 : (size_t)(N + 1) * N));
+  l.ax = take(sizeof(double) * faces_of(dim, N));
+  l.ay = take(sizeof(double) * (dim == 1 ? 1 : faces_of(dim, N)));
+  l.az = take(sizeof(double) * (dim == 3 ? faces_of(dim, N) : 1));
   l.tmu = take(sizeof(double) * m);
   l.tmu_lap = take(sizeof(double) * m);
   l.tcoef = take(sizeof(double) * 4 * (size_t)n);
@@ -247,7 +256,7 @@ Layout layout_of(const smr_desc *d) {
   l.zf = take(f32 ? 3 * align256(sizeof(float) * len) : 0);
   l.tw = take(sizeof(double) * 2 * (size_t)L);
   l.gface = take(sizeof(double) * 2 * (size_t)(N + 1) * (N + 1));
-  l.part = take(sizeof(double) * 16 * (size_t)kRedSlots);
+  l.part = take(sizeof(double) * spec_part_doubles((int)m));
   l.sc = take(2 * sizeof(Scal));
   // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve, + QX for the
   // variable-coefficient sine-basis solve)
@@ -270,28 +279,39 @@ long double cospi_ratio(long long k, long long q) {
   return cosl((long double)r * 3.14159265358979323846264338327950288L / (long double)q);
 }
 
-void mean_faces(const Plan &p, const std::vector<double> &ax, const std::vector<double> &ay, double &d, double &cx,
-                double &cy) {
-  const int N = p.N;
-  long double sd = 0, sx = 0, sy = 0;
+// The averaged Toeplitz Kbar of Sec. 3.1.1: d = mean of h^2 diag(K), c_axis = mean of the
+// interior face values along each axis (long double sums, fixed order).
+void mean_faces(const Plan &p, const std::vector<double> &ax, const std::vector<double> &ay,
+                const std::vector<double> &az, double &d, double &cx, double &cy, double &cz) {
+  const long long N = p.N;
+  long double sd = 0, sx = 0, sy = 0, sz = 0;
+  cx = cy = cz = 0.0;
   if (p.dim == 1) {
     for (int i = 0; i < N; ++i) sd += (long double)ax[i] + ax[i + 1];
     for (int i = 1; i < N; ++i) sx += ax[i];
     d = (double)(sd / N);
-    cx = N > 1 ? (double)(sx / (N - 1)) : 0.0;
-    cy = 0.0;
+    if (N > 1) cx = (double)(sx / (N - 1));
     return;
   }
-  for (int j = 0; j < N; ++j)
-    for (int i = 0; i < N; ++i)
-      sd += (long double)ax[j * (N + 1) + i] + ax[j * (N + 1) + i + 1] + ay[j * N + i] + ay[(j + 1) * N + i];
-  for (int j = 0; j < N; ++j)
-    for (int i = 1; i < N; ++i) sx += ax[j * (N + 1) + i];
-  for (int j = 1; j < N; ++j)
-    for (int i = 0; i < N; ++i) sy += ay[j * N + i];
-  d = (double)(sd / ((long double)N * N));
-  cx = N > 1 ? (double)(sx / ((long double)N * (N - 1))) : 0.0;
-  cy = N > 1 ? (double)(sy / ((long double)N * (N - 1))) : 0.0;
+  // planes (one in 2D): ax[k][j][i] (N+1 per row), ay[k][j][i] (N+1 rows per plane), az[k][j][i]
+  const long long P = p.dim == 3 ? N : 1;
+  for (long long k = 0; k < P; ++k)
+    for (long long j = 0; j < N; ++j)
+      for (long long i = 0; i < N; ++i) {
+        const size_t xa = (size_t)((k * N + j) * (N + 1) + i), ya = (size_t)((k * (N + 1) + j) * N + i);
+        sd += (long double)ax[xa] + ax[xa + 1] + ay[ya] + ay[ya + N];
+        if (p.dim == 3) sd += (long double)az[(size_t)((k * N + j) * N + i)] + az[(size_t)(((k + 1) * N + j) * N + i)];
+        if (i >= 1) sx += ax[xa];
+        if (j >= 1) sy += ay[ya];
+        if (p.dim == 3 && k >= 1) sz += az[(size_t)((k * N + j) * N + i)];
+      }
+  const long double cnt = (long double)P * N * N, inner = (long double)P * N * (N - 1);
+  d = (double)(sd / cnt);
+  if (N > 1) {
+    cx = (double)(sx / inner);
+    cy = (double)(sy / inner);
+    if (p.dim == 3) cz = (double)(sz / inner);
+  }
 }
 
 // compute units of the current device (256 on MI355X)
@@ -302,8 +322,12 @@ int cu_count() {
   return cus > 0 ? cus : 256;
 }
 
+// P_H / Phat (any a the sine-basis path takes), and P_theta of a constant a (its per-mode
+// blocks are diagonal in the spatial sine basis)
 bool use_spectral(const Plan &p) {
-  return p.precond == SMR_P_H && !(p.flags & SMR_FLAG_GENERAL_PATH) && (p.const_coef || p.QX != nullptr);
+  if (p.flags & SMR_FLAG_GENERAL_PATH) return false;
+  if (p.precond == SMR_P_H) return p.const_coef || p.QX != nullptr;
+  return p.precond == SMR_P_THETA_CHEB && p.const_coef;
 }
 
 }  // namespace
@@ -342,7 +366,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.dim = d->dim;
   p.N = d->N;
   p.n = d->n;
-  p.m = d->dim == 1 ? d->N : d->N * d->N;
+  p.m = (int)m_of(d->dim, d->N);
   p.len = (size_t)p.m * p.n;
   p.ld = ld_of((size_t)p.m);
   p.vlen = (size_t)p.ld * p.n;
@@ -367,12 +391,14 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
 
   const int N = p.N, n = p.n, m = p.m, dim = p.dim;
   // ---- face values
-  const size_t nax = dim == 1 ? (size_t)N + 1 : (size_t)N * (N + 1);
-  const size_t nay = dim == 1 ? 0 : (size_t)(N + 1) * N;
-  std::vector<double> ax(nax, 1.0), ay(std::max<size_t>(nay, 1), 1.0);
+  const size_t nax = faces_of(dim, N);
+  const size_t nay = dim == 1 ? 0 : faces_of(dim, N);
+  const size_t naz = dim == 3 ? faces_of(dim, N) : 0;
+  std::vector<double> ax(nax, 1.0), ay(std::max<size_t>(nay, 1), 1.0), az(std::max<size_t>(naz, 1), 1.0);
   if (d->ax_host) {
     std::copy(d->ax_host, d->ax_host + nax, ax.begin());
-    if (dim == 2) std::copy(d->ay_host, d->ay_host + nay, ay.begin());
+    if (dim >= 2) std::copy(d->ay_host, d->ay_host + nay, ay.begin());
+    if (dim == 3) std::copy(d->az_host, d->az_host + naz, az.begin());
   } else if (d->a_nodal_host) {
     const double *a = d->a_nodal_host;
     const int G = N + 2;
@@ -402,13 +428,21 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     amin = std::min(amin, ay[i]);
     amax = std::max(amax, ay[i]);
   }
+  for (size_t i = 0; i < naz; ++i) {
+    if (!(az[i] > 0.0) || !std::isfinite(az[i])) {
+      delete pl;
+      return fail(SMR_EINVAL, "face value az[%zu] = %g is not finite and positive", i, az[i]);
+    }
+    amin = std::min(amin, az[i]);
+    amax = std::max(amax, az[i]);
+  }
   p.a_min = amin;
   p.a_max = amax;
   p.const_coef = (amin == amax);
   p.abar = 0.5 * (amin + amax);
   p.cheb_lo = std::min(1.0, amin / p.abar);
   p.cheb_hi = std::max(1.0, amax / p.abar);
-  mean_faces(p, ax, ay, p.kbar_d, p.kbar_cx, p.kbar_cy);
+  mean_faces(p, ax, ay, az, p.kbar_d, p.kbar_cx, p.kbar_cy, p.kbar_cz);
 
   // ---- spatial eigenvalues (sine-basis order, x fastest), tau included
   std::vector<double> s2(N);
@@ -417,14 +451,18 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     s2[k] = (double)(sv * sv);
   }
   std::vector<double> tmu(m), tmul(m);
-  const double base = dim == 1 ? p.kbar_d - 2.0 * p.kbar_cx : p.kbar_d - 2.0 * p.kbar_cx - 2.0 * p.kbar_cy;
+  const double base = p.kbar_d - 2.0 * (p.kbar_cx + p.kbar_cy + p.kbar_cz);   // cy = 0 in 1D, cz = 0 below 3D
   for (int q = 0; q < m; ++q) {
-    const int kx = dim == 1 ? q : q % N, ly = dim == 1 ? 0 : q / N;
+    const int kx = q % N, ly = (q / N) % N, lz = q / (N * N);
     double mu = base + 4.0 * p.kbar_cx * s2[kx];
     double ml = 4.0 * s2[kx];
-    if (dim == 2) {
+    if (dim >= 2) {
       mu += 4.0 * p.kbar_cy * s2[ly];
       ml += 4.0 * s2[ly];
+    }
+    if (dim == 3) {
+      mu += 4.0 * p.kbar_cz * s2[lz];
+      ml += 4.0 * s2[lz];
     }
     tmu[q] = p.tau * (mu * p.h2inv);
     tmul[q] = p.tau * (ml * p.h2inv);
@@ -437,7 +475,13 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     const long double cp = cospi_ratio(t + 1, n + 1);           // cos(phi)
     const long double sh = sinpi_ratio(t + 1, 2LL * (n + 1));   // sin(phi/2)
     const long double s2h = sh * sh;
-    if (p.scheme == SMR_THETA) {
+    if (p.precond == SMR_P_THETA_CHEB) {
+      // P_theta of a constant a: eta_j + tau zeta_j mu (used by the sine-basis path only)
+      tcoef[4 * t + 0] = (double)(2.0L * sh);
+      tcoef[4 * t + 1] = (double)sqrtl(th * th + (1.0L - th) * (1.0L - th) + 2.0L * th * (1.0L - th) * cp);
+      tcoef[4 * t + 2] = 0.0;
+      tcoef[4 * t + 3] = 0.0;
+    } else if (p.scheme == SMR_THETA) {
       tcoef[4 * t + 0] = (double)(2.0L * s2h);
       tcoef[4 * t + 1] = (double)(th + (1.0L - th) * cp);
       tcoef[4 * t + 2] = (double)(-sp);
@@ -511,6 +555,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   char *base_ptr = (char *)d_ws;
   p.ax = (double *)(base_ptr + lay.ax);
   p.ay = (double *)(base_ptr + lay.ay);
+  p.az = (double *)(base_ptr + lay.az);
   p.tmu = (double *)(base_ptr + lay.tmu);
   p.tmu_lap = (double *)(base_ptr + lay.tmu_lap);
   p.tcoef = (double *)(base_ptr + lay.tcoef);
@@ -545,6 +590,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up(p.ax, ax.data(), nax * sizeof(double));
   if (e == hipSuccess && nay) e = up(p.ay, ay.data(), nay * sizeof(double));
+  if (e == hipSuccess && naz) e = up(p.az, az.data(), naz * sizeof(double));
   if (e == hipSuccess) e = up(p.tmu, tmu.data(), m * sizeof(double));
   if (e == hipSuccess) e = up(p.tmu_lap, tmul.data(), m * sizeof(double));
   if (e == hipSuccess) e = up(p.tcoef, tcoef.data(), tcoef.size() * sizeof(double));
@@ -617,25 +663,22 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   }
   if (p.precond == SMR_P_H) {
     LAUNCH(PROF_DST, launch_dst(c, 0, v, tb.t1, p.n, 0, gate));
-    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, tb.t1, tb.t1, p.n, 0, gate));
+    for (int ax = 1; ax < p.dim; ++ax) LAUNCH(PROF_DST, launch_dst(c, ax, tb.t1, tb.t1, p.n, 0, gate));
     LAUNCH(PROF_TIME, launch_time(c, tb.t1, tb.t2, 1, part2, nb2, gate, f32));
-    if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, tb.t2, tb.t2, p.n, 0, gate));
+    for (int ax = p.dim - 1; ax >= 1; --ax) LAUNCH(PROF_DST, launch_dst(c, ax, tb.t2, tb.t2, p.n, 0, gate));
     LAUNCH(PROF_DST, launch_dst(c, 0, tb.t2, z, p.n, 0, gate));
     return SMR_OK;
   }
   // P_theta with k-step Chebyshev per time mode: res = T1, x = T2, dvec = T3, tmp = T4
   LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
+  // inner preconditioner: the spatial transform along every axis (the last pass divides by
+  // the diagonal), then back
   auto binv = [&](const double *in, double *out) -> smr_status {
-    if (p.dim == 1) {
-      LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 1, gate));
-      LAUNCH(PROF_DST, launch_dst(c, 0, out, out, p.n, 0, gate));
-    } else {
-      LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, gate));
-      LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 1, gate));
-      LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, gate));
-      LAUNCH(PROF_DST, launch_dst(c, 0, out, out, p.n, 0, gate));
-    }
+    const int last = p.dim - 1;
+    LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, last == 0 ? 1 : 0, gate));
+    for (int ax = 1; ax <= last; ++ax) LAUNCH(PROF_DST, launch_dst(c, ax, out, out, p.n, ax == last ? 1 : 0, gate));
+    for (int ax = last; ax >= 0; --ax) LAUNCH(PROF_DST, launch_dst(c, ax, out, out, p.n, 0, gate));
     return SMR_OK;
   };
   smr_status st = binv(tb.t1, tb.t4);
@@ -667,7 +710,7 @@ smr_status spatial_dst(const Plan &p, hipStream_t s, const double *in, double *o
     return SMR_OK;
   }
   LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, 0, nullptr, in_ld, out_ld));
-  if (p.dim == 2) LAUNCH(PROF_DST, launch_dst(c, 1, out, out, p.n, 0, nullptr, out_ld, out_ld));
+  for (int ax = 1; ax < p.dim; ++ax) LAUNCH(PROF_DST, launch_dst(c, ax, out, out, p.n, 0, nullptr, out_ld, out_ld));
   return SMR_OK;
 }
 smr_status to_sine_basis(const Plan &p, hipStream_t s, const double *in, double *out) {
@@ -1206,6 +1249,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
       classes.push_back(Class{(int)k, 0, 0, p.hp, c, p.pprec, taps_of(p)});
     Class &cl = classes.back();
     table[k] = spec_desc(&p, p.T2, p.T1, c);
+    table[k].rtiles = 0;   // batched launches read every tile's partials (no grouped reduction)
     table[k].tile0 = cl.blocks;
     cl.blocks += table[k].tiles;
     cl.count += 1;
@@ -1498,6 +1542,7 @@ smr_status smr_grad_a(const smr_plan *pl, const double *u, const double *u0, con
   if (st != SMR_OK) return st;
   if (!u || !lam) return fail(SMR_EINVAL, "u and lambda must be non-NULL");
   const Plan &p = pl->p;
+  if (p.dim == 3) return fail(SMR_EUNSUPPORTED, "the coefficient gradient is implemented for dim 1 and 2");
   double *fx = gax ? gax : p.gface;
   double *fy = p.dim == 1 ? nullptr : (gay ? gay : p.gface + (size_t)p.N * (p.N + 1));
   Ctx c{&p, (hipStream_t)stream};

@@ -12,9 +12,15 @@
 namespace smr {
 
 constexpr int kMaxN = 511;       // N + 1 <= 512
+constexpr int kMaxN3 = 127;      // N + 1 <= 128 in 3D (the stencil's spatial tiles fit the partial slots)
 constexpr int kMaxn = 1024;
 constexpr int kRedSlots = 8192;  // partial sums per reduction (grid-stride kernels use <= this many blocks)
 constexpr size_t kKsPartOffset = 8 * (size_t)kRedSlots;   // per-level partials of the sine-basis matvec
+// Above this many column tiles, a fused launch's partial sums are first reduced by kPartGroups
+// blocks (one fixed group of tiles each) instead of being re-read in full by every block of
+// the next launch.
+constexpr int kDirectTiles = 1024;
+constexpr int kPartGroups = 64;
 
 // MINRES status codes kept on the device.
 enum DevStatus : int { RUNNING = 0, DONE_CONV = 1, DONE_MAXIT = 2, DONE_NOTSPD = 3, DONE_BREAKDOWN = 4 };
@@ -66,13 +72,13 @@ struct Plan {
   double T, tau, theta, h, h2inv;
   bool const_coef;            // every face value equal
   double a_min, a_max, abar, cheb_lo, cheb_hi;
-  double kbar_d, kbar_cx, kbar_cy;
+  double kbar_d, kbar_cx, kbar_cy, kbar_cz;
   double sqsigmin;            // sqrt of the smallest eigenvalue of P (P_H / Phat)
   int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
   int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
   int spec_c;                 // column-tile width of the fused sine-basis kernel (16 or 32)
   // tables (device)
-  double *ax, *ay;            // face values (filled with 1 for a = 1)
+  double *ax, *ay, *az;       // face values (filled with 1 for a = 1; az in 3D only)
   double *tmu;                // m: tau * eigenvalue of K (a const) or Kbar, sine-basis order
   double *tmu_lap;            // m: tau * eigenvalue of the a = 1 Laplacian
   double *tcoef;              // 4*hp*2: per time mode (A, B, C, D) of sigma, grouped by parity
@@ -85,7 +91,8 @@ struct Plan {
   double *QX;                 // (T z)^ of the variable-coefficient sine-basis solve (or null)
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
-  double *part;               // 16 * kRedSlots partial sums
+  double *part;               // >= 16 * kRedSlots partial sums (more when the fused kernel's
+                              // column tiles need them)
   Scal *sc;                   // device scalars (2 slots; the physical-basis path uses slot 0)
   // host-side resources of the sine-basis solve, made on first use, released by smr_destroy
   mutable hipGraphExec_t steady6 = nullptr;          // six captured steady iterations
@@ -117,7 +124,7 @@ hipError_t launch_rhs_adjoint(Ctx c, const double *lam, double *gf, double *gu0)
 hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const double *lam,
                              double *gax, double *gay, double *gnodal);
 
-// Spatial sine transform (orthonormal DST-I) along x (dir 0) or y (dir 1) of nslices
+// Spatial sine transform (orthonormal DST-I) along x (dir 0), y (dir 1) or z (dir 2, 3D) of nslices
 // slices; in-place allowed when the strides agree.  Slice strides of in and out default
 // (0) to m.  scale_mode 1 divides the result by the Chebyshev inner diagonal
 // eta_s + zeta_s * abar * tau * mu_lap.
@@ -160,7 +167,8 @@ struct SpecP {
   double *V[2], *W[2];
   double *x;             // x (INIT: x0, read only)
   const double *bh;      // transformed right-hand side b^ (unpermuted)
-  double *part;          // 2 slots (launch parity) of 4 partial sums per column tile
+  double *part;          // 2 slots (launch parity) of 4 partial sums per column tile; with
+                         // rtiles > 0 two further slots of 4 per tile group follow them
   Scal *sc;              // 2 scalar states: sc[j & 1] is the state after launch j
   // variable coefficient: (T z)^ comes from the per-level kernel, with its partial sums
   // [residual^2, residual skipped, 0, delta] per time level (null / 0 for constant a)
@@ -169,7 +177,9 @@ struct SpecP {
   int nks;
   int x0zero;            // INIT: the solve starts from x0 = 0 (x is written, not read)
   double rtol;           // INIT: the starting scalar state (sc[0]) it writes
-  int maxit, pad3;
+  int maxit;
+  int rtiles;            // 0: a launch reads every tile's partials; else the number of tile
+                         // groups whose sums a reduction launch left at part + 8 tiles
 };
 
 // One instance of the per-level sine-basis matvec (also the element of its batched table).
@@ -206,6 +216,9 @@ hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool
                        double rtol = 0.0, int maxit = 0);
 // cols: column-tile width of the launch (0: the plan's own)
 SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols = 0);
+// Doubles of partial-sum storage the fused kernel needs for a plan of m spatial modes
+// (either tile width, with the grouped reduction above kDirectTiles tiles).
+size_t spec_part_doubles(int m);
 hipError_t launch_spec_multi(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
                              int taps, int mode, int j);
 hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int slot, Scal *out);

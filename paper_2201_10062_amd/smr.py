@@ -40,6 +40,7 @@ class SmrDesc(ctypes.Structure):
         ("precond", ctypes.c_int32), ("pprec", ctypes.c_int32), ("cheb_k", ctypes.c_int32),
         ("flags", ctypes.c_int32), ("T", ctypes.c_double), ("theta", ctypes.c_double),
         ("ax_host", ctypes.c_void_p), ("ay_host", ctypes.c_void_p), ("a_nodal_host", ctypes.c_void_p),
+        ("az_host", ctypes.c_void_p),
     ]
 
 
@@ -113,7 +114,7 @@ FLAG_TILE32 = 4
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
-              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None):
+              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
     tile_cols: None (timed at setup), 16 or 32."""
     if tile_cols not in (None, 16, 32):
@@ -130,7 +131,7 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
                 cheb_k=cheb_k, flags=(FLAG_GENERAL_PATH if general_path else 0)
                 | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32}[tile_cols], T=T, theta=theta,
-                ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal))
+                ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal), az_host=host(az))
     return d, keep
 
 
@@ -169,8 +170,9 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None):
-        """workspace: a uint8 device tensor to build the plan in (e.g. the ``raw_workspace``
+                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None, az=None):
+        """ax, ay, az: face values (az with dim 3 only); a_nodal: nodal values (dim 1, 2).
+        workspace: a uint8 device tensor to build the plan in (e.g. the ``raw_workspace``
         of a plan that is no longer used); a new one is allocated when it is None or too small."""
         import torch
         self.lib = load()
@@ -180,7 +182,7 @@ class Plan:
         self.precond, self.pprec = precond, pprec
         self.device = torch.device(device)
         d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path,
-                            tile_cols)
+                            tile_cols, az)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2201_10062_amd as pkg
@@ -33,7 +34,12 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(dim=3, N=7, n=4), smr.SMR_EINVAL),
+    (dict(dim=4, N=7, n=4), smr.SMR_EINVAL),
+    (dict(dim=0, N=7, n=4), smr.SMR_EINVAL),
+    (dict(dim=3, N=255, n=4), smr.SMR_EINVAL),          # 3D: N + 1 <= 128
+    (dict(dim=3, N=7, n=4, ax=np.ones((7, 7, 8)), ay=np.ones((7, 8, 7))), smr.SMR_EINVAL),   # az missing
+    (dict(dim=2, N=7, n=4, ax=np.ones((7, 8)), ay=np.ones((8, 7)), az=np.ones(1)), smr.SMR_EINVAL),
+    (dict(dim=3, N=7, n=4, a_nodal=np.ones((9, 9, 9))), smr.SMR_EINVAL),   # 3D takes face values
     (dict(dim=2, N=6, n=4), smr.SMR_EINVAL),           # N + 1 not a power of two
     (dict(dim=2, N=1023, n=4), smr.SMR_EINVAL),        # N too large
     (dict(dim=2, N=7, n=0), smr.SMR_EINVAL),
@@ -85,6 +91,23 @@ def test_null_plan_rejected():
     lib = pkg.load()
     assert lib.smr_apply_A(None, None, None, None) == smr.SMR_EINVAL
     assert lib.smr_minres_solve(None, None, None, None, 1e-8, 10, None, None) == smr.SMR_EINVAL
+
+
+def test_desc_fields_match_header():
+    """The binding's smr_desc mirrors the C struct field by field (names and order)."""
+    text = open(os.path.join(ROOT, "include", "smr.h")).read()
+    body = re.search(r"typedef struct \{(.*?)\} smr_desc;", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)\s*;", body)
+    assert names == [f[0] for f in smr.SmrDesc._fields_]
+
+
+def test_3d_workspace_sizes():
+    a = smr.workspace_size(dim=3, N=63, n=64)
+    assert a > 10 * 8 * 63 ** 3 * 64          # the ten work vectors alone
+    assert smr.workspace_size(dim=3, N=127, n=8) > a / 2
+    faces = dict(ax=np.ones((7, 7, 8)), ay=np.ones((7, 8, 7)), az=np.ones((8, 7, 7)))
+    assert smr.workspace_size(dim=3, N=7, n=4, **faces) == smr.workspace_size(dim=3, N=7, n=4)
 
 
 def test_workspace_size_grows_with_problem():
