@@ -355,37 +355,69 @@ def manufactured_1d_leg(dev, rtol: float, reps: int = 20):
             "iters": info["iters"], "rtol": rtol, "max_err_vs_exact": err}
 
 
+def spec_fp64_bytes(infos, dof):
+    """Algorithmic bytes of the float64 fused launches of the given solves (see cn2d_leg)."""
+    def steady(k):
+        return sum(88 - (16 if j == 2 else 8 if j == 3 else 0) for j in range(2, k + 2))
+    return sum((32 + 32 + steady(i["iters"]) + 8 * (i["res_evals"] - 1)) * dof for i in infos)
+
+
 def paper_tables_leg(dev, reps: int = 3):
-    """The largest row of each of the paper's Tables 1-4 (n = 256, m + 1 = 256, 16.6 M
-    unknowns, tolerance 1e-6, P_H) solved here, beside the iteration counts and MATLAB CPU
-    seconds the paper prints for them (dual 16-core Xeon Gold 6246R, 3.4 GHz, Sec. 5)."""
+    """The largest row of each of the paper's tables solved here with P_H and P_theta (3
+    Chebyshev steps per mode), tolerance 1e-6, x0 = 0, beside the iteration counts and MATLAB
+    CPU seconds the paper prints (dual 16-core Xeon Gold 6246R, 3.4 GHz, Sec. 5): Tables 1-4
+    (2D, n = 256, m + 1 = 256, 16.6 M unknowns) and Tables 6-7 (3D Example 3, n = 64,
+    m + 1 = 64, 16.0 M unknowns).  For the 3D rows the fused sine-basis kernel (with the
+    grouped reduction of its partial sums) is also priced against the HBM roofline."""
     import torch
     import workloads as W
-    from paper_2201_10062_amd import Plan
+    from paper_2201_10062_amd import Plan, smr
     rows = []
-    path = os.path.join(ROOT, "tests", "golden", "paper_tables_full.txt")
-    with open(path) as fh:
-        for line in fh:
-            r = line.split()
-            if r and not line.startswith("#") and r[3] == "256" and r[4] == "256":
-                rows.append(r)
+    for name, dim in (("paper_tables_full.txt", 2), ("paper_tables_3d.txt", 3)):
+        with open(os.path.join(ROOT, "tests", "golden", name)) as fh:
+            for line in fh:
+                r = line.split()
+                if not r or line.startswith("#"):
+                    continue
+                if dim == 2 and r[3] == "256" and r[4] == "256":
+                    rows.append(dict(dim=2, table=r[0], ex=r[1], theta=float(r[2]), n=int(r[3]), mp1=int(r[4]),
+                                     printed={"PH": (int(r[6]), float(r[7])), "PTHETA_CHEB": (int(r[8]), float(r[9]))}))
+                if dim == 3 and r[2] == "64" and r[3] == "64":
+                    rows.append(dict(dim=3, table=r[0], ex="3", theta=float(r[1]), n=int(r[2]), mp1=int(r[3]),
+                                     printed={"PH": (int(r[6]), float(r[7])), "PTHETA_CHEB": (int(r[8]), float(r[9]))}))
     out = []
     for r in rows:
-        tab, ex, theta, n, mp1 = r[0], r[1], float(r[2]), int(r[3]), int(r[4])
-        N = mp1 - 1
-        p = W.example1(N, n, theta) if ex == "1" else W.example2(N, n, theta)
-        g = Plan(2, N, n, theta=theta, ax=p.ax, ay=p.ay, device=dev)
-        b = g.build_rhs(torch.from_numpy(p.f.reshape(-1)).to(dev), torch.from_numpy(p.u0).to(dev))
-        g.solve(b, rtol=1e-6, maxit=200)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            x, info = g.solve(b, rtol=1e-6, maxit=200)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / reps * 1e3
-        out.append({"table": tab, "n": n, "m_plus_1": mp1, "dof": n * N * N, "iters": info["iters"],
-                    "paper_iters": int(r[6]), "gpu_ms": ms, "paper_cpu_s": float(r[7])})
-        del g, b, x
+        N, n, theta, dim = r["mp1"] - 1, r["n"], r["theta"], r["dim"]
+        p = {"1": W.example1, "2": W.example2, "3": W.example3}[r["ex"]](N, n, theta)
+        dof = n * N ** dim
+        f, u0 = torch.from_numpy(p.f.reshape(-1)).to(dev), torch.from_numpy(p.u0).to(dev)
+        for pre in ("PH", "PTHETA_CHEB"):
+            g = Plan(dim, N, n, theta=theta, ax=p.ax, ay=p.ay, az=p.az, precond=pre, cheb_k=3, device=dev)
+            b = g.build_rhs(f, u0)
+            g.solve(b, rtol=1e-6, maxit=200)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x, info = g.solve(b, rtol=1e-6, maxit=200)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            e = {"table": r["table"], "dim": dim, "precond": pre, "n": n, "m_plus_1": r["mp1"], "dof": dof,
+                 "path": "sine basis" if g.tile_cols else "physical basis", "iters": info["iters"],
+                 "paper_iters": r["printed"][pre][0], "gpu_ms": ms, "paper_cpu_s": r["printed"][pre][1]}
+            if dim == 3 and g.tile_cols:
+                smr.profile_enable(True)
+                _, pinfo = g.solve(b, rtol=1e-6, maxit=200)
+                smr.profile_enable(False)
+                nl, msl = smr.profile_read("spec")
+                bpl = spec_fp64_bytes([pinfo], dof) / max(nl, 1)
+                gbs = bpl / (msl / max(nl, 1) * 1e-3) / 1e9
+                e["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                                 "kernel": "k_spec + grouped partial reduction (3D, 4D sine basis)",
+                                 "launches": nl, "avg_launch_us": msl / max(nl, 1) * 1e3, "bytes_per_launch": bpl,
+                                 "tile_cols": g.tile_cols}
+            out.append(e)
+            del g, b, x
     return out
 
 
@@ -505,6 +537,8 @@ def main() -> int:
                     help="only the headline's profiled pass (warm-up + the timed steps with per-launch events)")
     ap.add_argument("--only-cn2d", action="store_true",
                     help="only the 2D Crank-Nicolson leg (for profiling its fused kernel)")
+    ap.add_argument("--only-tables", action="store_true",
+                    help="only the paper-table leg (largest row of Tables 1-4 and 6-7, P_H and P_theta)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -529,6 +563,9 @@ def main() -> int:
         return 0
     if args.only_cn2d:
         print(json.dumps({"cn2d": cn2d_leg(dev, args.warmup, args.steps, args.rtol)}), flush=True)
+        return 0
+    if args.only_tables:
+        print(json.dumps({"paper_tables_largest": paper_tables_leg(dev)}), flush=True)
         return 0
     if args.profiled_pass_only:
         print(json.dumps(batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=False,

@@ -1365,7 +1365,8 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     // layout; the tables it reads are re-uploaded above on every call), except while profiling
     hipGraphExec_t g6 = nullptr;
     if (!g_prof.on) {
-      std::vector<long> key{(long)(uintptr_t)d_ws};
+      // the descriptor tables' places in the workspace depend on the instance count as well
+      std::vector<long> key{(long)(uintptr_t)d_ws, (long)count};
       for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
       for (const Class &cl : classes)
         key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps});
