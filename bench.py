@@ -537,6 +537,8 @@ def main() -> int:
                     help="only the headline's profiled pass (warm-up + the timed steps with per-launch events)")
     ap.add_argument("--only-cn2d", action="store_true",
                     help="only the 2D Crank-Nicolson leg (for profiling its fused kernel)")
+    ap.add_argument("--only-varcoef", action="store_true",
+                    help="only the N = 255 / n = 512 variable-coefficient leg (no CPU oracle)")
     ap.add_argument("--only-tables", action="store_true",
                     help="only the paper-table leg (largest row of Tables 1-4 and 6-7, P_H and P_theta)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -563,6 +565,9 @@ def main() -> int:
         return 0
     if args.only_cn2d:
         print(json.dumps({"cn2d": cn2d_leg(dev, args.warmup, args.steps, args.rtol)}), flush=True)
+        return 0
+    if args.only_varcoef:
+        print(json.dumps({"variable_coefficient": variable_coef_leg(dev, args.rtol, oracle=False)}), flush=True)
         return 0
     if args.only_tables:
         print(json.dumps({"paper_tables_largest": paper_tables_leg(dev)}), flush=True)

@@ -81,9 +81,10 @@ typedef enum { SMR_P_H = 0, SMR_P_THETA_CHEB = 2, SMR_P_NONE = 3 } smr_precond;
  * MINRES scalars and the true residual are always float64.  SMR_FP32 runs the time-axis sine
  * transforms of P^{-1} on the float32 matrix cores with float32 accumulation: in the sine
  * basis (see SMR_FLAG_GENERAL_PATH) z is also stored in float32; on the physical-basis path
- * (P_H, Phat, P_theta) the vectors, spatial transforms, 1/sigma scaling and Chebyshev steps
- * stay float64.  SMR_EINVAL with SMR_P_NONE.  smr_apply_P_inv always applies P^{-1} in
- * float64. */
+ * (P_H, Phat, P_theta) every intermediate vector of P^{-1} (after each spatial transform pass
+ * and each per-mode Chebyshev step) is stored in float32, while the spatial transforms, the
+ * 1/sigma scaling and the Chebyshev updates compute in float64.  SMR_EINVAL with SMR_P_NONE.
+ * smr_apply_P_inv always applies P^{-1} in float64. */
 typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 /* P_H / Phat solves run in the spatial sine basis (b and x0 transformed on entry, x on exit;
  * the same iterates in exact arithmetic): for constant a, Y T and P^{-1} act per spatial mode
@@ -99,11 +100,22 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
  * modes of all n time levels (the folded time blocks of Sec. 3.1.1 are contracted per tile
  * on the matrix cores).  With neither bit set, smr_setup times one steady iteration at each
  * width on the plan's own workspace and keeps 32 unless 16 is at least 5% faster (narrow
- * tiles pay off when the spatial grid is small); 32 needs ceil(n/2) <= 128 (SMR_EUNSUPPORTED
- * otherwise) and ceil(n/2) > 128 always takes 16.  The width changes only the summation
- * order of the reductions.  Setting both bits is SMR_EINVAL. */
+ * tiles pay off when the spatial grid is small); the choice is cached per device and shape
+ * (see smr_tune_stats).  32 needs ceil(n/2) <= 128 (SMR_EUNSUPPORTED otherwise) and
+ * ceil(n/2) > 128 always takes 16.  The width changes only the summation order of the
+ * reductions.  Setting both bits is SMR_EINVAL. */
 #define SMR_FLAG_TILE16 2
 #define SMR_FLAG_TILE32 4
+/* Intermediates of the physical-basis P^{-1} of an SMR_FP32 plan (no effect on the sine-basis
+ * path): float64 vectors with float32 time-transform GEMMs (PINV_F64), float32 vectors
+ * (PINV_F32), or float32 vectors with 16-line tiles in the spatial transform's column passes
+ * (PINV_F32_COL16; 2D with N + 1 in {32, ..., 256}, else as PINV_F32).  With none set,
+ * smr_setup times one P^{-1} application of each on the plan's workspace and keeps the
+ * fastest (float64 unless another is 3% faster), cached per device and shape;
+ * smr_pinv_variant reports the choice.  At most one; SMR_EINVAL on a float64 plan. */
+#define SMR_FLAG_PINV_F64 8
+#define SMR_FLAG_PINV_F32 16
+#define SMR_FLAG_PINV_F32_COL16 32
 
 typedef struct {
   int32_t dim;             /* spatial dimension, 1, 2 or 3                                */
@@ -158,6 +170,17 @@ smr_status smr_setup(const smr_desc *desc, void *d_ws, size_t ws_bytes, void *st
 /* Column-tile width the plan's sine-basis solves launch with (16 or 32; see
  * SMR_FLAG_TILE16), 0 when its solves run in the physical basis.  Host only. */
 smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols);
+
+/* The physical-basis P^{-1} variant of an SMR_FP32 plan (see SMR_FLAG_PINV_F64): 0 float64
+ * intermediates, 1 float32, 2 float32 with 16-line column tiles; -1 for float64 plans and
+ * plans whose solves run in the sine basis.  Host only. */
+smr_status smr_pinv_variant(const smr_plan *plan, int32_t *variant);
+
+/* The autotuner's cache (host, process-wide): shapes timed so far (entries), and how many
+ * set-ups and batched calls found their choice cached (hits) or timed it (misses).
+ * smr_tune_reset clears it (the next plans and batches time their choices again). */
+smr_status smr_tune_stats(int64_t *entries, int64_t *hits, int64_t *misses);
+smr_status smr_tune_reset(void);
 
 /* Free the host-side plan (the workspace stays with the caller).  NULL is accepted. */
 smr_status smr_destroy(smr_plan *plan);

@@ -46,8 +46,10 @@ __device__ __forceinline__ size_t in_slice(const DstP &d, long r, int j, long &s
   return (size_t)j * N * N + (size_t)i;
 }
 
-template <int DIR>
-__global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ in, double *__restrict__ out,
+// TI, TO: element types of the input and output vectors (float32 intermediates of a
+// mixed-precision P^{-1}); the FFT itself runs in float64.
+template <int DIR, typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_dst(DstP d, const TI *__restrict__ in, TO *__restrict__ out,
                                              const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   extern __shared__ double2 X[];          // ppb * M complex values, then M/2 twiddles
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ 
     if (r < d.nlines) {
       long s;
       const size_t q = in_slice<DIR>(d, r, j, s);
-      v = in[(size_t)s * d.sin + q];
+      v = (double)in[(size_t)s * d.sin + q];
     }
     double2 *Xp = X + (size_t)(c >> 1) * d.M;
     const int i1 = bitrev(j + 1, d.logM), i2 = bitrev(d.M - (j + 1), d.logM);
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void k_dst(DstP d, const double *__restrict__ 
     long s;
     const size_t q = in_slice<DIR>(d, r, j, s);
     if (d.scale_mode == 1) v /= d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q];
-    out[(size_t)s * d.sout + q] = v;
+    out[(size_t)s * d.sout + q] = (TO)v;
   }
 }
 
@@ -147,12 +149,9 @@ DstP make_dst(const Plan *p, int dir, int nslices) {
   return d;
 }
 
-}  // namespace
-
-static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                          const Scal *gate, long in_stride, long out_stride) {
-  // 2D with N + 1 in {32, ..., 256}: line tiles through the register FFT
-  if (dst_tile_supported(c.p)) return launch_dst_tile(c, dir, in, out, nslices, scale_mode, gate, in_stride, out_stride);
+template <typename TI, typename TO>
+hipError_t run_dst_t(Ctx c, int dir, const TI *in, TO *out, int nslices, int scale_mode, const Scal *gate,
+                     long in_stride, long out_stride) {
   if (dir < 0 || dir >= c.p->dim) return hipErrorInvalidValue;
   DstP d = make_dst(c.p, dir, nslices);
   d.scale_mode = scale_mode;
@@ -161,22 +160,40 @@ static hipError_t run_dst(Ctx c, int dir, const double *in, double *out, int nsl
   const long lpb = 2L * d.ppb;
   const long nblocks = (d.nlines + lpb - 1) / lpb;
   const size_t shmem = ((size_t)d.ppb * d.M + d.M / 2) * sizeof(double2);
+  const void *f = dir == 0 ? (const void *)k_dst<0, TI, TO> : dir == 1 ? (const void *)k_dst<1, TI, TO>
+                                                                       : (const void *)k_dst<2, TI, TO>;
   if (shmem > 65536) {
-    hipError_t e = lds_limit(dir == 0 ? (const void *)k_dst<0> : dir == 1 ? (const void *)k_dst<1> : (const void *)k_dst<2>, shmem);
+    hipError_t e = lds_limit(f, shmem);
     if (e != hipSuccess) return e;
   }
   if (dir == 0)
-    hipLaunchKernelGGL(k_dst<0>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
+    hipLaunchKernelGGL((k_dst<0, TI, TO>), dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
   else if (dir == 1)
-    hipLaunchKernelGGL(k_dst<1>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
+    hipLaunchKernelGGL((k_dst<1, TI, TO>), dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
   else
-    hipLaunchKernelGGL(k_dst<2>, dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
+    hipLaunchKernelGGL((k_dst<2, TI, TO>), dim3((unsigned)nblocks), dim3(256), shmem, c.st, d, in, out, gate);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dst_v(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices,
+                        int scale_mode, const Scal *gate, long in_stride, long out_stride, bool col16) {
+  // 2D with N + 1 in {32, ..., 256}: line tiles through the register FFT
+  if (dst_tile_supported(c.p))
+    return launch_dst_tile(c, dir, in, in32, out, out32, nslices, scale_mode, gate, in_stride, out_stride, col16);
+  if (!in32 && !out32)
+    return run_dst_t(c, dir, (const double *)in, (double *)out, nslices, scale_mode, gate, in_stride, out_stride);
+  if (!in32 && out32)
+    return run_dst_t(c, dir, (const double *)in, (float *)out, nslices, scale_mode, gate, in_stride, out_stride);
+  if (in32 && out32)
+    return run_dst_t(c, dir, (const float *)in, (float *)out, nslices, scale_mode, gate, in_stride, out_stride);
+  return run_dst_t(c, dir, (const float *)in, (double *)out, nslices, scale_mode, gate, in_stride, out_stride);
 }
 
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
                       const Scal *gate, long in_stride, long out_stride) {
-  return run_dst(c, dir, in, out, nslices, scale_mode, gate, in_stride, out_stride);
+  return launch_dst_v(c, dir, in, false, out, false, nslices, scale_mode, gate, in_stride, out_stride);
 }
 
 }  // namespace smr

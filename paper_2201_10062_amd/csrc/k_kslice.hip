@@ -532,30 +532,34 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
   return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
-template <int R, int DIR>
-__global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restrict__ in, double *__restrict__ out,
+// TI, TO: element types of the vectors in memory (float32 intermediates of a mixed-precision
+// P^{-1}); the tile in LDS and the FFT stay float64.
+// TL: lines per tile (16 for float32 column passes, so that a tile's row piece is a whole
+// 64-byte segment).
+template <int R, int DIR, typename TI, typename TO, int TL>
+__global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const TI *__restrict__ in, TO *__restrict__ out,
                                                   const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   extern __shared__ double X[];
   constexpr int N = 32 * R - 1;
-  constexpr int LP = DIR == 0 ? N + 2 : kTL + 1;   // LDS pitch of a line (DIR 0) or a position (DIR 1)
+  constexpr int LP = DIR == 0 ? N + 2 : TL + 1;    // LDS pitch of a line (DIR 0) or a position (DIR 1)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
-  const int s = bid / d.tiles, i0 = (bid - s * d.tiles) * kTL;
-  const int nl = min(kTL, N - i0);
-  const double *src = in + (size_t)s * d.sin;
-  double *dst = out + (size_t)s * d.sout;
+  const int s = bid / d.tiles, i0 = (bid - s * d.tiles) * TL;
+  const int nl = min(TL, N - i0);
+  const TI *src = in + (size_t)s * d.sin;
+  TO *dst = out + (size_t)s * d.sout;
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(d.tw), lane);
   if (DIR == 0) {
     for (int e = tid; e < nl * N; e += kTT) {           // rows i0.. are contiguous
       const int c = e / N, j = e - c * N;
-      X[c * LP + j] = src[(size_t)i0 * N + e];
+      X[c * LP + j] = (double)src[(size_t)i0 * N + e];
     }
   } else {
-    for (int e = tid; e < kTL * N; e += kTT) {
-      const int j = e / kTL, c = e - j * kTL;
-      if (c < nl) X[j * LP + c] = src[(size_t)j * N + i0 + c];
+    for (int e = tid; e < TL * N; e += kTT) {
+      const int j = e / TL, c = e - j * TL;
+      if (c < nl) X[j * LP + c] = (double)src[(size_t)j * N + i0 + c];
     }
   }
   __syncthreads();
@@ -568,14 +572,14 @@ __global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const double *__restr
     for (int e = tid; e < nl * N; e += kTT) {
       const int c = e / N, j = e - c * N;
       const size_t q = (size_t)i0 * N + e;
-      dst[q] = fin(X[c * LP + j], q);
+      dst[q] = (TO)fin(X[c * LP + j], q);
     }
   } else {
-    for (int e = tid; e < kTL * N; e += kTT) {
-      const int j = e / kTL, c = e - j * kTL;
+    for (int e = tid; e < TL * N; e += kTT) {
+      const int j = e / TL, c = e - j * TL;
       if (c < nl) {
         const size_t q = (size_t)j * N + i0 + c;
-        dst[q] = fin(X[j * LP + c], q);
+        dst[q] = (TO)fin(X[j * LP + c], q);
       }
     }
   }
@@ -629,17 +633,19 @@ __device__ __forceinline__ void pair_dft512(double2 (&v)[8], int lane, const dou
 // range, holding the next tile's loads in registers while the current tile is transformed
 // (loads of one tile and stores of another touch different lines, so in == out is allowed);
 // the regrouping buffers alias the tile once the line pairs are in registers.
-constexpr int kLds512 = 4 * 8 * kTP;   // doubles: >= one tile in either direction (2056, 2295)
-template <int DIR>
-__global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__restrict__ in,
-                                                     double *__restrict__ out, const Scal *__restrict__ gate,
-                                                     int total) {
+// NWV waves, one line pair each: tiles of 2 NWV lines (8 lines, or 16 for float32 column
+// passes so that a tile's row piece is a whole 64-byte segment).
+template <int DIR, typename TI, typename TO, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_dst_tile512(TileP d, const TI *__restrict__ in,
+                                                          TO *__restrict__ out, const Scal *__restrict__ gate,
+                                                          int total) {
   if (gate && gate->status != RUNNING) return;
+  constexpr int kTT = 64 * NWV;
+  constexpr int kLds512 = NWV * 8 * kTP;   // doubles: >= one tile in either direction
   __shared__ double X[kLds512];
-  constexpr int N = 255, M = 512, L = 256, TL = kTL, TILES = (N + TL - 1) / TL;
+  constexpr int N = 255, M = 512, L = 256, TL = 2 * NWV, TILES = (N + TL - 1) / TL;
   constexpr int LP = DIR == 0 ? N + 2 : TL + 1;
   constexpr int PF = (TL * N + kTT - 1) / kTT;
-  static_assert(TL == 2 * (kTT / 64), "one line pair per wave");
   static_assert((DIR == 0 ? TL * LP : N * LP) <= kLds512, "the tile fits");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *T = X + wave * 8 * kTP;
@@ -656,15 +662,15 @@ __global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__re
   double pre[PF];
   auto load = [&](int t) {
     const int s = t / TILES, i0 = (t - s * TILES) * TL, nl = min(TL, N - i0);
-    const double *src = in + (size_t)s * d.sin;
+    const TI *src = in + (size_t)s * d.sin;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int e = tid + k * kTT;
       if (DIR == 0) {
-        pre[k] = e < nl * N ? src[(size_t)i0 * N + e] : 0.0;       // rows i0.. are contiguous
+        pre[k] = e < nl * N ? (double)src[(size_t)i0 * N + e] : 0.0;       // rows i0.. are contiguous
       } else {
         const int j = e / TL, c = e - j * TL;
-        pre[k] = (e < TL * N && c < nl) ? src[(size_t)j * N + i0 + c] : 0.0;
+        pre[k] = (e < TL * N && c < nl) ? (double)src[(size_t)j * N + i0 + c] : 0.0;
       }
     }
   };
@@ -713,7 +719,7 @@ __global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__re
       }
     }
     __syncthreads();
-    double *dst = out + (size_t)s * d.sout;
+    TO *dst = out + (size_t)s * d.sout;
     auto fin = [&](double x, size_t q) {
       return d.scale_mode == 1 ? x / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : x;
     };
@@ -721,14 +727,14 @@ __global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__re
       for (int e = tid; e < nl * N; e += kTT) {
         const int c2 = e / N, j = e - c2 * N;
         const size_t q = (size_t)i0 * N + e;
-        dst[q] = fin(X[c2 * LP + j], q);
+        dst[q] = (TO)fin(X[c2 * LP + j], q);
       }
     } else {
       for (int e = tid; e < TL * N; e += kTT) {
         const int j = e / TL, c2 = e - j * TL;
         if (c2 < nl) {
           const size_t q = (size_t)j * N + i0 + c2;
-          dst[q] = fin(X[j * LP + c2], q);
+          dst[q] = (TO)fin(X[j * LP + c2], q);
         }
       }
     }
@@ -736,28 +742,45 @@ __global__ __launch_bounds__(kTT) void k_dst_tile512(TileP d, const double *__re
   }
 }
 
-// resident blocks of the persistent pass (LDS allows 8 per CU); measured at N = 255, n = 512
+// resident blocks of the persistent pass (LDS allows 8 four-wave blocks per CU); measured at
+// N = 255, n = 512; eight-wave blocks: half as many
 constexpr int kGrid512[2] = {2048, 4096};
 
-template <int R>
-hipError_t run_dst_tile(hipStream_t st, int dir, const TileP &d, int nslices, const double *in, double *out,
-                        const Scal *gate) {
+template <int R, typename TI, typename TO>
+hipError_t run_dst_tile(hipStream_t st, int dir, TileP d, int nslices, const TI *in, TO *out, const Scal *gate,
+                        bool col16) {
+  constexpr bool F32 = std::is_same<TI, float>::value || std::is_same<TO, float>::value;
+  const int TLr = (F32 && dir == 1 && col16) ? 16 : kTL;   // lines per tile of this pass
+  d.tiles = (d.N + TLr - 1) / TLr;
   if constexpr (R == 8) {
     const long total = (long)nslices * d.tiles;
-    const int grid = (int)std::min<long>(kGrid512[dir], (total + 7) / 8 * 8);
-    if (dir == 0) hipLaunchKernelGGL(k_dst_tile512<0>, dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
-    else hipLaunchKernelGGL(k_dst_tile512<1>, dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
+    if (TLr == 16) {
+      const int grid = (int)std::min<long>(kGrid512[dir] / 2, (total + 7) / 8 * 8);
+      hipLaunchKernelGGL((k_dst_tile512<1, TI, TO, 8>), dim3(grid), dim3(512), 0, st, d, in, out, gate, (int)total);
+    } else {
+      const int grid = (int)std::min<long>(kGrid512[dir], (total + 7) / 8 * 8);
+      if (dir == 0)
+        hipLaunchKernelGGL((k_dst_tile512<0, TI, TO, 4>), dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
+      else
+        hipLaunchKernelGGL((k_dst_tile512<1, TI, TO, 4>), dim3(grid), dim3(kTT), 0, st, d, in, out, gate, (int)total);
+    }
   } else {
     constexpr int N = 32 * R - 1;
-    const size_t sh = (size_t)(dir == 0 ? kTL * (N + 2) : N * (kTL + 1)) * sizeof(double);
-    const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0> : (const void *)k_dst_tile<R, 1>;
+    const size_t sh = (size_t)(dir == 0 ? TLr * (N + 2) : N * (TLr + 1)) * sizeof(double);
+    const void *f = dir == 0 ? (const void *)k_dst_tile<R, 0, TI, TO, kTL>
+                             : TLr == 16 ? (const void *)k_dst_tile<R, 1, TI, TO, 16>
+                                         : (const void *)k_dst_tile<R, 1, TI, TO, kTL>;
     if (sh > 65536) {
       const hipError_t e = lds_limit(f, sh);
       if (e != hipSuccess) return e;
     }
     const unsigned blocks = (unsigned)((long)nslices * d.tiles);
-    if (dir == 0) hipLaunchKernelGGL((k_dst_tile<R, 0>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
-    else hipLaunchKernelGGL((k_dst_tile<R, 1>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
+    if (dir == 0)
+      hipLaunchKernelGGL((k_dst_tile<R, 0, TI, TO, kTL>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
+    else if (TLr == 16)
+      hipLaunchKernelGGL((k_dst_tile<R, 1, TI, TO, 16>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
+    else
+      hipLaunchKernelGGL((k_dst_tile<R, 1, TI, TO, kTL>), dim3(blocks), dim3(kTT), sh, st, d, in, out, gate);
   }
   return hipGetLastError();
 }
@@ -768,10 +791,21 @@ bool dst_tile_supported(const Plan *p) {
   return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128 || p->L == 256);
 }
 
-hipError_t launch_dst_tile(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                           const Scal *gate, long in_stride, long out_stride) {
+namespace {
+template <int R>
+hipError_t run_dst_tile_v(hipStream_t st, int dir, const TileP &d, int nslices, const void *in, bool in32, void *out,
+                          bool out32, const Scal *gate, bool col16) {
+  if (!in32 && !out32) return run_dst_tile<R>(st, dir, d, nslices, (const double *)in, (double *)out, gate, col16);
+  if (!in32 && out32) return run_dst_tile<R>(st, dir, d, nslices, (const double *)in, (float *)out, gate, col16);
+  if (in32 && out32) return run_dst_tile<R>(st, dir, d, nslices, (const float *)in, (float *)out, gate, col16);
+  return run_dst_tile<R>(st, dir, d, nslices, (const float *)in, (double *)out, gate, col16);
+}
+}  // namespace
+
+hipError_t launch_dst_tile(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices,
+                           int scale_mode, const Scal *gate, long in_stride, long out_stride, bool col16) {
   const Plan *p = c.p;
-  if (!dst_tile_supported(p)) return hipErrorInvalidValue;
+  if (!dst_tile_supported(p) || dir < 0 || dir > 1) return hipErrorInvalidValue;
   TileP d{};
   d.N = p->N;
   d.n = p->n;
@@ -785,10 +819,10 @@ hipError_t launch_dst_tile(Ctx c, int dir, const double *in, double *out, int ns
   d.tmu_lap = p->tmu_lap;
   d.scale_mode = scale_mode;
   switch (p->L) {
-    case 32: return run_dst_tile<1>(c.st, dir, d, nslices, in, out, gate);
-    case 64: return run_dst_tile<2>(c.st, dir, d, nslices, in, out, gate);
-    case 128: return run_dst_tile<4>(c.st, dir, d, nslices, in, out, gate);
-    case 256: return run_dst_tile<8>(c.st, dir, d, nslices, in, out, gate);
+    case 32: return run_dst_tile_v<1>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
+    case 64: return run_dst_tile_v<2>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
+    case 128: return run_dst_tile_v<4>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
+    case 256: return run_dst_tile_v<8>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
     default: break;
   }
   return hipErrorInvalidValue;

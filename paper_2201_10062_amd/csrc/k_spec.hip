@@ -139,9 +139,30 @@ hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool
   return hipGetLastError();
 }
 
+hipError_t spec_tune_state(const Plan *p, hipStream_t st, const SpecP &P) {
+  (void)p;
+  Scal s{};
+  s.status = RUNNING; s.iter = 5; s.maxit = 1 << 30;
+  s.gamma = s.gamma1 = s.gamma_new = s.zs = 1.0; s.delta = 0.5;
+  s.c = s.c_old = 1.0; s.eta = 1.0; s.bnorm = 1.0; s.rtol = 0.0;   // never converges
+  // the partials a launch with j = 7 reads (slot 0): per tile, or per tile group
+  const int npart = 4 * (P.rtiles ? P.rtiles : P.tiles), nk = P.kpart ? 4 * P.nks : 0;
+  double *tpart = P.rtiles ? P.part + 8 * (size_t)P.tiles : P.part;
+  hipLaunchKernelGGL(k_tune_state, dim3((npart + 255) / 256), dim3(256), 0, st, P.sc, tpart, npart,
+                     P.kpart ? const_cast<double *>(P.kpart) : nullptr, nk, s);
+  return hipGetLastError();
+}
+
 hipError_t spec_tune(Plan *p, hipStream_t st) {
   if (!spec_cols_ok(p->hp, 32)) {
     p->spec_c = 16;
+    return hipSuccess;
+  }
+  const std::vector<long> key{TUNE_SPEC_WIDTH, p->dim, p->hp, p->n, p->m, p->pprec, p->taps <= 3 ? 3 : 5,
+                              p->const_coef ? 0 : 1};
+  int cached = 0;
+  if (tune_get(key, &cached)) {
+    p->spec_c = cached;
     return hipSuccess;
   }
   hipError_t e = hipSuccess;
@@ -152,43 +173,28 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
   if (p->pprec == SMR_FP32)
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMemsetAsync(p->ZF[i], 0, sizeof(float) * p->vlen, st);
   if (e != hipSuccess) return e;
-  Scal s{};
-  s.status = RUNNING; s.iter = 5; s.maxit = 1 << 30;
-  s.gamma = s.gamma1 = s.gamma_new = s.zs = 1.0; s.delta = 0.5;
-  s.c = s.c_old = 1.0; s.eta = 1.0; s.bnorm = 1.0; s.rtol = 0.0;   // never converges
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  e = hipEventCreate(&ev[0]);
-  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  // a steady launch with j = 7 reads scalar and partial slot 0 and writes slot 1, so repeated
+  // launches all start from the same state
   const int cand[2] = {32, 16};
   float best[2] = {1e30f, 1e30f};
-  constexpr int kReps = 6;
-  // launch 7 of a solve: reads scalar slot 0 and partial slot 0, writes slot 1
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       p->spec_c = cand[k];
       const SpecP P = spec_desc(p, p->T1, p->T2);
-      // the partials launch 7 reads: per tile, or per tile group
-      const int npart = 4 * (P.rtiles ? P.rtiles : P.tiles), nk = P.kpart ? 4 * P.nks : 0;
-      double *tpart = P.rtiles ? p->part + 8 * (size_t)P.tiles : p->part;
-      auto one = [&]() {
-        hipLaunchKernelGGL(k_tune_state, dim3((npart + 255) / 256), dim3(256), 0, st, p->sc, tpart, npart,
-                           P.kpart ? p->part + kKsPartOffset : nullptr, nk, s);
-        hipError_t r = hipGetLastError();
-        return r == hipSuccess ? run_one(st, P, p->pprec, cand[k], MODE_STEADY, P.tiles, p->hp, 1, MODE_STEADY) : r;
-      };
-      e = one();
-      if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-      for (int r = 0; r < kReps && e == hipSuccess; ++r) e = one();
-      if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      e = spec_tune_state(p, st, P);
       float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e == hipSuccess)
+        e = tune_time(st, 6, [&]() {
+          hipError_t r = run_one(st, P, p->pprec, cand[k], MODE_STEADY, P.tiles, p->hp, 1, MODE_STEADY);
+          if (r == hipSuccess && P.rtiles)
+            hipLaunchKernelGGL(k_part_reduce, dim3(kPartGroups), dim3(256), 0, st, p->part, P.tiles, 1, p->sc);
+          return r == hipSuccess ? hipGetLastError() : r;
+        }, &ms);
       if (e == hipSuccess) best[k] = std::min(best[k], ms);
     }
-  for (hipEvent_t v : ev)
-    if (v) hipEventDestroy(v);
   // the wider tile stays unless the narrow one is clearly faster
   p->spec_c = best[1] < 0.95f * best[0] ? 16 : 32;
+  if (e == hipSuccess) tune_put(key, p->spec_c);
   return e;
 }
 

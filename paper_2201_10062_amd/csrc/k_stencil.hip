@@ -44,18 +44,20 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;   // valid in thread 0 only
 }
 
-// u = c0*x0 + c1*x1 (x1 may be null) at flat index q
-__device__ __forceinline__ double comb(const double *__restrict__ x0, double c0,
-                                       const double *__restrict__ x1, double c1, int q) {
-  double v = c0 * x0[q];
-  if (x1) v += c1 * x1[q];
+// u = c0*x0 + c1*x1 (x1 may be null) at flat index q (T: the vectors' element type)
+template <typename T>
+__device__ __forceinline__ double comb(const T *__restrict__ x0, double c0, const T *__restrict__ x1, double c1,
+                                       int q) {
+  double v = c0 * (double)x0[q];
+  if (x1) v += c1 * (double)x1[q];
   return v;
 }
 
 // (K u)(j, i) with u = c0*x0 + c1*x1 on one slice; zero Dirichlet values outside.  Row j is y
 // in 2D and z*N + y in 3D (the 7-point stencil adds the two z neighbours N^2 apart).
-__device__ __forceinline__ double Kapply(const SP &s, const double *__restrict__ x0, double c0,
-                                         const double *__restrict__ x1, double c1, int j, int i) {
+template <typename T>
+__device__ __forceinline__ double Kapply(const SP &s, const T *__restrict__ x0, double c0, const T *__restrict__ x1,
+                                         double c1, int j, int i) {
   const int N = s.N;
   if (s.dim == 1) {
     const double uc = comb(x0, c0, x1, c1, i);
@@ -92,11 +94,11 @@ __device__ __forceinline__ double Tapply(const SP &s, const double *__restrict__
   const double *xk1 = k >= 1 ? xk - m : nullptr;
   if (s.scheme == SMR_THETA) {
     double v = xk[q] - (xk1 ? xk1[q] : 0.0);
-    return v + s.tau * Kapply(s, xk, s.theta, xk1, 1.0 - s.theta, j, i);
+    return v + s.tau * Kapply<double>(s, xk, s.theta, xk1, 1.0 - s.theta, j, i);
   }
   double v = 0.0;
   for (int r = 0; r < s.taps && r <= k; ++r) v += s.tc[r] * xk[q - (ptrdiff_t)r * m];
-  return v + s.tau * Kapply(s, xk, 1.0, nullptr, 0.0, j, i);
+  return v + s.tau * Kapply<double>(s, xk, 1.0, nullptr, 0.0, j, i);
 }
 
 struct TileInfo {
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(256) void k_build_rhs(SP s, TileInfo ti, const doub
     if (!tile_point(t, ti.ni, ti.nj, s.N, s.dim, k, j, i)) continue;
     const int q = (s.dim == 1) ? i : j * s.N + i;
     double v = s.theta * s.tau * f[(size_t)(k + 1) * s.m + q] + (1.0 - s.theta) * s.tau * f[(size_t)k * s.m + q];
-    if (k == 0 && u0) v += u0[q] - (1.0 - s.theta) * s.tau * Kapply(s, u0, 1.0, nullptr, 0.0, j, i);
+    if (k == 0 && u0) v += u0[q] - (1.0 - s.theta) * s.tau * Kapply<double>(s, u0, 1.0, nullptr, 0.0, j, i);
     b[(size_t)k * s.m + q] = v;
   }
 }
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(256) void k_rhs_adjoint(SP s, TileInfo ti, const do
     if (k >= 1) v += s.theta * s.tau * lam[(size_t)(k - 1) * s.m + q];
     if (k <= s.n - 1) v += (1.0 - s.theta) * s.tau * lam[(size_t)k * s.m + q];
     gf[(size_t)k * s.m + q] = v;
-    if (k == 0 && gu0) gu0[q] = lam[q] - (1.0 - s.theta) * s.tau * Kapply(s, lam, 1.0, nullptr, 0.0, j, i);
+    if (k == 0 && gu0) gu0[q] = lam[q] - (1.0 - s.theta) * s.tau * Kapply<double>(s, lam, 1.0, nullptr, 0.0, j, i);
   }
 }
 
@@ -468,29 +470,34 @@ __global__ __launch_bounds__(256) void k_scalar_step(int stage, Scal *sc, const 
 
 // Chebyshev helpers for P_theta (per-mode solves run on all modes at once).
 // first: x = t/c scaled: dvec = a_t * tmp; x = dvec.  else x += dvec_old... see launcher.
-__global__ __launch_bounds__(256) void k_cheb_axpy(size_t len, double *__restrict__ x, double *__restrict__ dvec,
-                                                   const double *__restrict__ tmp, double a_d, double a_t,
+// T: the element type of the Chebyshev vectors (float32 in a mixed-precision P^{-1}); the
+// arithmetic is float64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb_axpy(size_t len, T *__restrict__ x, T *__restrict__ dvec,
+                                                   const T *__restrict__ tmp, double a_d, double a_t,
                                                    int first, const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-    const double d = first ? a_t * tmp[e] : a_d * dvec[e] + a_t * tmp[e];
-    dvec[e] = d;
-    x[e] = first ? d : x[e] + d;
+    const double d = first ? a_t * (double)tmp[e] : a_d * (double)dvec[e] + a_t * (double)tmp[e];
+    dvec[e] = (T)d;
+    x[e] = first ? (T)d : (T)((double)x[e] + d);
   }
 }
 
 // res -= (eta_j I + tau zeta_j K(a)) dvec on every time mode j.
+template <typename T>
 __global__ __launch_bounds__(256) void k_cheb_resid(SP s, TileInfo ti, const double *__restrict__ ez,
-                                                    double *__restrict__ res, const double *__restrict__ dvec,
+                                                    T *__restrict__ res, const T *__restrict__ dvec,
                                                     const Scal *__restrict__ gate) {
   if (gate && gate->status != RUNNING) return;
   for (int t = blockIdx.x; t < ti.ntiles; t += gridDim.x) {
     int k, j, i;
     if (!tile_point(t, ti.ni, ti.nj, s.N, s.dim, k, j, i)) continue;
     const int q = (s.dim == 1) ? i : j * s.N + i;
-    const double *dk = dvec + (size_t)k * s.m;
-    const double av = ez[k] * dk[q] + s.tau * ez[s.n + k] * Kapply(s, dk, 1.0, nullptr, 0.0, j, i);
-    res[(size_t)k * s.m + q] -= av;
+    const T *dk = dvec + (size_t)k * s.m;
+    const double av = ez[k] * (double)dk[q] + s.tau * ez[s.n + k] * Kapply<T>(s, dk, 1.0, nullptr, 0.0, j, i);
+    T *r = res + (size_t)k * s.m + q;
+    *r = (T)((double)*r - av);
   }
 }
 
@@ -600,18 +607,28 @@ hipError_t launch_scalar_step(Ctx c, int stage, const double *part, int nb, cons
   return hipGetLastError();
 }
 
-hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, double a_d, double a_t, int first,
-                            const Scal *gate) {
-  hipLaunchKernelGGL(k_cheb_axpy, dim3(grid_all(c.p->len, 1024)), dim3(256), 0, c.st, c.p->len, x, dvec, tmp, a_d,
-                     a_t, first, gate);
+hipError_t launch_cheb_axpy(Ctx c, void *x, void *dvec, const void *tmp, double a_d, double a_t, int first,
+                            const Scal *gate, bool f32) {
+  const dim3 g(grid_all(c.p->len, 1024));
+  if (f32)
+    hipLaunchKernelGGL(k_cheb_axpy<float>, g, dim3(256), 0, c.st, c.p->len, (float *)x, (float *)dvec,
+                       (const float *)tmp, a_d, a_t, first, gate);
+  else
+    hipLaunchKernelGGL(k_cheb_axpy<double>, g, dim3(256), 0, c.st, c.p->len, (double *)x, (double *)dvec,
+                       (const double *)tmp, a_d, a_t, first, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_cheb_resid(Ctx c, double *res, const double *dvec, const Scal *gate) {
+hipError_t launch_cheb_resid(Ctx c, void *res, const void *dvec, const Scal *gate, bool f32) {
   const Plan *p = c.p;
   TileInfo ti = tiles_of(p, p->n);
   const int g = grid_all(ti.ntiles, 1);
-  hipLaunchKernelGGL(k_cheb_resid, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, p->ez, res, dvec, gate);
+  if (f32)
+    hipLaunchKernelGGL(k_cheb_resid<float>, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, p->ez, (float *)res,
+                       (const float *)dvec, gate);
+  else
+    hipLaunchKernelGGL(k_cheb_resid<double>, dim3(g), block_of(p), 0, c.st, make_sp(p), ti, p->ez, (double *)res,
+                       (const double *)dvec, gate);
   return hipGetLastError();
 }
 

@@ -14,8 +14,9 @@
 // stream from L2 in MFMA-fragment order, two k-steps per load); the results go back to LDS,
 // where the 1/sigma scaling and the final butterfly read them.
 // PR 1 (mixed precision): the butterflied columns and the sine blocks are float32 and the
-// GEMMs run on the float32 matrix cores with float32 accumulation; the vectors in memory, the
-// 1/sigma scaling and the Parseval sum stay float64.
+// GEMMs run on the float32 matrix cores with float32 accumulation; the 1/sigma scaling and the
+// Parseval sum stay float64.  TI / TO: element types of the vectors in memory (float32 for the
+// intermediates of a mixed-precision P^{-1}).
 #include "smr_internal.h"
 #include "mfma_tiles.h"
 
@@ -56,8 +57,8 @@ __device__ __forceinline__ size_t frag_at(int r, int ks, int kk, int lane) {
   return (((size_t)r * (ks / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
 }
 
-template <int HP, int C, int MODE, int PR>
-__global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__restrict__ in, double *__restrict__ out,
+template <int HP, int C, int MODE, int PR, typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restrict__ in, TO *__restrict__ out,
                                               double *__restrict__ part, const Scal *__restrict__ gate) {
   typedef typename Prec<PR>::T T;
   typedef typename Prec<PR>::Acc Acc;
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
       const int e = e0 + u * 256;
       const int p = e / C, col = col0 + (e - p * C);
       const bool okc = e < HP * C && col < m;
-      a[u] = okc && p < h1 ? in[(size_t)p * m + col] : 0.0;
-      b[u] = okc && p < h2 ? in[(size_t)(n - 1 - p) * m + col] : 0.0;
+      a[u] = okc && p < h1 ? (double)in[(size_t)p * m + col] : 0.0;
+      b[u] = okc && p < h2 ? (double)in[(size_t)(n - 1 - p) * m + col] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -138,8 +139,8 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int p = 16 * r + Prec<PR>::row(i, bk);
-        if (p < h1) out[(size_t)(2 * p) * m + col] = (double)ao[t][i];
-        if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (double)ae[t][i];
+        if (p < h1) out[(size_t)(2 * p) * m + col] = (TO)ao[t][i];
+        if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (TO)ae[t][i];
       }
     }
     return;
@@ -208,10 +209,10 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
       const int p = 16 * r + Prec<PR>::row(i, bk);
       const double a = (double)ao[t][i], b = (double)ae[t][i];
       if (p < h2) {
-        out[(size_t)p * m + col] = a + b;
-        out[(size_t)(n - 1 - p) * m + col] = a - b;
+        out[(size_t)p * m + col] = (TO)(a + b);
+        out[(size_t)(n - 1 - p) * m + col] = (TO)(a - b);
       } else if (p < h1) {
-        out[(size_t)p * m + col] = a;
+        out[(size_t)p * m + col] = (TO)a;
       }
     }
   }
@@ -224,9 +225,9 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const double *__res
 // hp >= 256: one folded block per pass (fewer live accumulators), results through LDS.
 // One block: C columns, all n levels; NW waves, all on the matrix cores (eight, so that a
 // CU holding a single block of the largest tiles still runs two waves per SIMD).
-template <int HP, int C, int MODE, int PR, int NW>
-__global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__restrict__ in,
-                                                  double *__restrict__ out, double *__restrict__ part,
+template <int HP, int C, int MODE, int PR, int NW, typename TI, typename TO>
+__global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict__ in,
+                                                  TO *__restrict__ out, double *__restrict__ part,
                                                   const Scal *__restrict__ gate) {
   typedef typename Prec<PR>::T T;
   typedef typename Prec<PR>::Acc Acc;
@@ -255,8 +256,8 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__rest
       const int e = e0 + u * NT;
       const int p = e / C, col = col0 + (e - p * C);
       const bool okc = e < HP * C && col < m;
-      a[u] = okc && p < h1 ? in[(size_t)p * m + col] : 0.0;
-      b[u] = okc && p < h2 ? in[(size_t)(n - 1 - p) * m + col] : 0.0;
+      a[u] = okc && p < h1 ? (double)in[(size_t)p * m + col] : 0.0;
+      b[u] = okc && p < h2 ? (double)in[(size_t)(n - 1 - p) * m + col] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kBL; ++u) {
@@ -285,8 +286,8 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__rest
     for (int e = tid; e < HP * C; e += NT) {
       const int p = e / C, c = e - p * C, col = col0 + c;
       if (col >= m) continue;
-      if (p < h1) out[(size_t)(2 * p) * m + col] = (double)U[p * LD + c];
-      if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (double)D[p * LD + c];
+      if (p < h1) out[(size_t)(2 * p) * m + col] = (TO)U[p * LD + c];
+      if (p < h2) out[(size_t)(2 * p + 1) * m + col] = (TO)D[p * LD + c];
     }
     return;
   }
@@ -328,10 +329,10 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__rest
     if (col >= m) continue;
     const double a = (double)U[p * LD + c], b = (double)D[p * LD + c];
     if (p < h2) {
-      out[(size_t)p * m + col] = a + b;
-      out[(size_t)(n - 1 - p) * m + col] = a - b;
+      out[(size_t)p * m + col] = (TO)(a + b);
+      out[(size_t)(n - 1 - p) * m + col] = (TO)(a - b);
     } else if (p < h1) {
-      out[(size_t)p * m + col] = a;
+      out[(size_t)p * m + col] = (TO)a;
     }
   }
   if (part) {
@@ -340,8 +341,8 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const double *__rest
   }
 }
 
-template <int HP, int C, int PR>
-hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int mode, double *part, int *nb,
+template <int HP, int C, int PR, typename TI, typename TO>
+hipError_t run_time(Ctx c, const TimeP &tp, const TI *in, TO *out, int mode, double *part, int *nb,
                     const Scal *gate) {
   const int blocks = (tp.m + C - 1) / C;
   if (nb) *nb = blocks;
@@ -349,29 +350,31 @@ hipError_t run_time(Ctx c, const TimeP &tp, const double *in, double *out, int m
   if constexpr (HP >= 256) {
     constexpr int NW = 8;
     if (shmem > 65536) {
-      (void)lds_limit((const void *)k_time<HP, C, 0, PR, NW>, shmem);
-      (void)lds_limit((const void *)k_time<HP, C, 1, PR, NW>, shmem);
+      (void)lds_limit((const void *)k_time<HP, C, 0, PR, NW, TI, TO>, shmem);
+      (void)lds_limit((const void *)k_time<HP, C, 1, PR, NW, TI, TO>, shmem);
     }
     if (mode == 0)
-      hipLaunchKernelGGL((k_time<HP, C, 0, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
+      hipLaunchKernelGGL((k_time<HP, C, 0, PR, NW, TI, TO>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part,
+                         gate);
     else
-      hipLaunchKernelGGL((k_time<HP, C, 1, PR, NW>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part, gate);
+      hipLaunchKernelGGL((k_time<HP, C, 1, PR, NW, TI, TO>), dim3(blocks), dim3(64 * NW), shmem, c.st, tp, in, out, part,
+                         gate);
   } else {
     if (shmem > 65536) {
-      (void)lds_limit((const void *)k_time_pair<HP, C, 0, PR>, shmem);
-      (void)lds_limit((const void *)k_time_pair<HP, C, 1, PR>, shmem);
+      (void)lds_limit((const void *)k_time_pair<HP, C, 0, PR, TI, TO>, shmem);
+      (void)lds_limit((const void *)k_time_pair<HP, C, 1, PR, TI, TO>, shmem);
     }
     if (mode == 0)
-      hipLaunchKernelGGL((k_time_pair<HP, C, 0, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+      hipLaunchKernelGGL((k_time_pair<HP, C, 0, PR, TI, TO>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
     else
-      hipLaunchKernelGGL((k_time_pair<HP, C, 1, PR>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
+      hipLaunchKernelGGL((k_time_pair<HP, C, 1, PR, TI, TO>), dim3(blocks), dim3(256), shmem, c.st, tp, in, out, part, gate);
   }
   return hipGetLastError();
 }
 
-template <int PR>
-hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double *out, int mode, double *part,
-                       int *nb, const Scal *gate) {
+template <int PR, typename TI, typename TO>
+hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const TI *in, TO *out, int mode, double *part, int *nb,
+                       const Scal *gate) {
   switch (hp) {
     case 16: return run_time<16, 32, PR>(c, tp, in, out, mode, part, nb, gate);
     case 32: return run_time<32, 32, PR>(c, tp, in, out, mode, part, nb, gate);
@@ -384,18 +387,34 @@ hipError_t run_time_hp(Ctx c, const TimeP &tp, int hp, const double *in, double 
   return hipErrorInvalidValue;
 }
 
+TimeP time_desc(const Plan *p, bool f32) {
+  TimeP tp{p->n, p->m, p->h1, p->h2, p->So, p->SoT, p->Se, p->SeT, p->tcoef, p->tmu};
+  if (f32) {
+    tp.So = p->Sof; tp.SoT = p->SoTf; tp.Se = p->Sef; tp.SeT = p->SeTf;
+  }
+  return tp;
+}
+
 }  // namespace
 
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nb, const Scal *gate,
                        bool f32) {
   const Plan *p = c.p;
   if (f32 && p->pprec != SMR_FP32) return hipErrorInvalidValue;   // no float32 tables
-  TimeP tp{p->n, p->m, p->h1, p->h2, p->So, p->SoT, p->Se, p->SeT, p->tcoef, p->tmu};
-  if (f32) {
-    tp.So = p->Sof; tp.SoT = p->SoTf; tp.Se = p->Sef; tp.SeT = p->SeTf;
-    return run_time_hp<1>(c, tp, p->hp, in, out, mode, part, nb, gate);
-  }
+  const TimeP tp = time_desc(p, f32);
+  if (f32) return run_time_hp<1>(c, tp, p->hp, in, out, mode, part, nb, gate);
   return run_time_hp<0>(c, tp, p->hp, in, out, mode, part, nb, gate);
+}
+
+hipError_t launch_time_v(Ctx c, const void *in, bool in32, void *out, bool out32, int mode, double *part, int *nb,
+                         const Scal *gate) {
+  const Plan *p = c.p;
+  if (p->pprec != SMR_FP32) return hipErrorInvalidValue;   // no float32 tables
+  const TimeP tp = time_desc(p, true);
+  if (in32 && out32) return run_time_hp<1>(c, tp, p->hp, (const float *)in, (float *)out, mode, part, nb, gate);
+  if (!in32 && out32) return run_time_hp<1>(c, tp, p->hp, (const double *)in, (float *)out, mode, part, nb, gate);
+  if (in32 && !out32) return run_time_hp<1>(c, tp, p->hp, (const float *)in, (double *)out, mode, part, nb, gate);
+  return run_time_hp<1>(c, tp, p->hp, (const double *)in, (double *)out, mode, part, nb, gate);
 }
 
 }  // namespace smr

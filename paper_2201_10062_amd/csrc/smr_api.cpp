@@ -190,8 +190,12 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EUNSUPPORTED, "pprec %d is not implemented", d->pprec);
   if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
     return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
-  const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32;
+  const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 |
+                    SMR_FLAG_PINV_F32_COL16;
   if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
+  const int pinv_flags = d->flags & (SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16);
+  if (pinv_flags & (pinv_flags - 1)) return fail(SMR_EINVAL, "at most one SMR_FLAG_PINV_* flag");
+  if (pinv_flags && d->pprec != SMR_FP32) return fail(SMR_EINVAL, "SMR_FLAG_PINV_* flags need pprec SMR_FP32");
   if ((d->flags & SMR_FLAG_TILE16) && (d->flags & SMR_FLAG_TILE32))
     return fail(SMR_EINVAL, "SMR_FLAG_TILE16 and SMR_FLAG_TILE32 exclude each other");
   if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
@@ -321,6 +325,9 @@ int cu_count() {
     return 256;
   return cus > 0 ? cus : 256;
 }
+
+// Times the physical-basis P^{-1} variants of a float32 plan and sets p.pinv_var (defined below).
+smr_status pinv_tune(Plan &p, hipStream_t s);
 
 // P_H / Phat (any a the sine-basis path takes), and P_theta of a constant a (its per-mode
 // blocks are diagonal in the spatial sine basis)
@@ -618,6 +625,20 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
       return fail(SMR_EDEVICE, "tile-width timing failed: %s", hipGetErrorString(e));
     }
   }
+  // the physical-basis P^{-1} of a float32 plan: forced by a flag, else timed
+  p.pinv_var = -1;
+  if (p.pprec == SMR_FP32 && !use_spectral(p)) {
+    if (p.flags & SMR_FLAG_PINV_F64) p.pinv_var = 0;
+    else if (p.flags & SMR_FLAG_PINV_F32) p.pinv_var = 1;
+    else if (p.flags & SMR_FLAG_PINV_F32_COL16) p.pinv_var = dst_tile_supported(&p) ? 2 : 1;
+    else {
+      const smr_status ts = pinv_tune(p, s);
+      if (ts != SMR_OK) {
+        delete pl;
+        return ts;
+      }
+    }
+  }
   *out = pl;
   return SMR_OK;
 }
@@ -652,7 +673,10 @@ struct PinvBufs {
 PinvBufs plan_bufs(const Plan &p) { return PinvBufs{p.T1, p.T2, p.T3, p.T4}; }
 
 // z = P^{-1} v; gamma^2 partials (Parseval or an explicit dot) into part2, count in *nb2.
-// f32: the time transforms on the float32 matrix cores (the solve of an SMR_FP32 plan)
+// f32 (the solves of an SMR_FP32 plan): the time transforms on the float32 matrix cores and,
+// per the plan's tuned variant, every intermediate vector of P^{-1} (spatial passes,
+// Chebyshev steps) stored in float32 in the first half of the float64 buffers; v and z, the
+// transforms' arithmetic and the Chebyshev recurrence coefficients stay float64.
 smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, double *part2, int *nb2,
                       const Scal *gate, bool f32, const PinvBufs &tb) {
   Ctx c{&p, s};
@@ -661,43 +685,86 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
     if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
     return SMR_OK;
   }
+  const bool w = f32 && p.pinv_var >= 1;     // float32 intermediates (the plan's tuned variant)
+  const bool c16 = f32 && p.pinv_var == 2;   // with 16-line column tiles
   if (p.precond == SMR_P_H) {
-    LAUNCH(PROF_DST, launch_dst(c, 0, v, tb.t1, p.n, 0, gate));
-    for (int ax = 1; ax < p.dim; ++ax) LAUNCH(PROF_DST, launch_dst(c, ax, tb.t1, tb.t1, p.n, 0, gate));
-    LAUNCH(PROF_TIME, launch_time(c, tb.t1, tb.t2, 1, part2, nb2, gate, f32));
-    for (int ax = p.dim - 1; ax >= 1; --ax) LAUNCH(PROF_DST, launch_dst(c, ax, tb.t2, tb.t2, p.n, 0, gate));
-    LAUNCH(PROF_DST, launch_dst(c, 0, tb.t2, z, p.n, 0, gate));
+    LAUNCH(PROF_DST, launch_dst_v(c, 0, v, false, tb.t1, w, p.n, 0, gate, 0, 0, c16));
+    for (int ax = 1; ax < p.dim; ++ax)
+      LAUNCH(PROF_DST, launch_dst_v(c, ax, tb.t1, w, tb.t1, w, p.n, 0, gate, 0, 0, c16));
+    if (w) LAUNCH(PROF_TIME, launch_time_v(c, tb.t1, true, tb.t2, true, 1, part2, nb2, gate));
+    else LAUNCH(PROF_TIME, launch_time(c, tb.t1, tb.t2, 1, part2, nb2, gate, f32));
+    for (int ax = p.dim - 1; ax >= 1; --ax)
+      LAUNCH(PROF_DST, launch_dst_v(c, ax, tb.t2, w, tb.t2, w, p.n, 0, gate, 0, 0, c16));
+    LAUNCH(PROF_DST, launch_dst_v(c, 0, tb.t2, w, z, false, p.n, 0, gate, 0, 0, c16));
     return SMR_OK;
   }
   // P_theta with k-step Chebyshev per time mode: res = T1, x = T2, dvec = T3, tmp = T4
-  LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
+  if (w) LAUNCH(PROF_TIME, launch_time_v(c, v, false, tb.t1, true, 0, nullptr, nullptr, gate));
+  else LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
   // inner preconditioner: the spatial transform along every axis (the last pass divides by
   // the diagonal), then back
   auto binv = [&](const double *in, double *out) -> smr_status {
     const int last = p.dim - 1;
-    LAUNCH(PROF_DST, launch_dst(c, 0, in, out, p.n, last == 0 ? 1 : 0, gate));
-    for (int ax = 1; ax <= last; ++ax) LAUNCH(PROF_DST, launch_dst(c, ax, out, out, p.n, ax == last ? 1 : 0, gate));
-    for (int ax = last; ax >= 0; --ax) LAUNCH(PROF_DST, launch_dst(c, ax, out, out, p.n, 0, gate));
+    LAUNCH(PROF_DST, launch_dst_v(c, 0, in, w, out, w, p.n, last == 0 ? 1 : 0, gate, 0, 0, c16));
+    for (int ax = 1; ax <= last; ++ax)
+      LAUNCH(PROF_DST, launch_dst_v(c, ax, out, w, out, w, p.n, ax == last ? 1 : 0, gate, 0, 0, c16));
+    for (int ax = last; ax >= 0; --ax) LAUNCH(PROF_DST, launch_dst_v(c, ax, out, w, out, w, p.n, 0, gate, 0, 0, c16));
     return SMR_OK;
   };
   smr_status st = binv(tb.t1, tb.t4);
   if (st != SMR_OK) return st;
-  LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, 0.0, 1.0 / cc, 1, gate));
+  LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, 0.0, 1.0 / cc, 1, gate, w));
   if (dd > 0.0) {
     const double s1 = cc / dd;
     double rho = 1.0 / s1;
     for (int i = 1; i < p.cheb_k; ++i) {
-      LAUNCH(PROF_STENCIL, launch_cheb_resid(c, tb.t1, tb.t3, gate));
+      LAUNCH(PROF_STENCIL, launch_cheb_resid(c, tb.t1, tb.t3, gate, w));
       st = binv(tb.t1, tb.t4);
       if (st != SMR_OK) return st;
       const double rn = 1.0 / (2.0 * s1 - rho);
-      LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, rn * rho, 2.0 * rn / dd, 0, gate));
+      LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, rn * rho, 2.0 * rn / dd, 0, gate, w));
       rho = rn;
     }
   }
-  LAUNCH(PROF_TIME, launch_time(c, tb.t2, z, 0, nullptr, nullptr, gate, f32));
+  if (w) LAUNCH(PROF_TIME, launch_time_v(c, tb.t2, true, z, false, 0, nullptr, nullptr, gate));
+  else LAUNCH(PROF_TIME, launch_time(c, tb.t2, z, 0, nullptr, nullptr, gate, f32));
   if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
+  return SMR_OK;
+}
+
+// The intermediates of a float32 plan's physical-basis P^{-1}: float64 vectors (float32 only
+// inside the time transform's GEMMs), float32 vectors, or float32 vectors with 16-line column
+// tiles in the spatial transform.  Which is fastest depends on the shape (the spatial passes
+// are bound by memory-instruction issue as much as by bytes), so one application of each is
+// timed on the plan's workspace and the fastest kept (float64 unless another is 3% faster).
+smr_status pinv_tune(Plan &p, hipStream_t s) {
+  const int nvar = dst_tile_supported(&p) ? 3 : 2;
+  const std::vector<long> key{TUNE_PINV, p.dim, p.N, p.n, p.precond, p.cheb_k, p.scheme};
+  int cached = 0;
+  if (tune_get(key, &cached)) {
+    p.pinv_var = cached;
+    return SMR_OK;
+  }
+  HIP_TRY(hipMemsetAsync(p.V[0], 0, p.len * sizeof(double), s));
+  float best = 1e30f;
+  int arg = 0;
+  for (int v = 0; v < nvar; ++v) {
+    p.pinv_var = v;
+    float ms = 0.0f;
+    const hipError_t e = tune_time(s, 3, [&]() -> hipError_t {
+      int nb2 = 0;
+      const smr_status st = apply_pinv(p, s, p.V[0], p.Z[0], p.part + 2 * kRedSlots, &nb2, nullptr, true, plan_bufs(p));
+      return st == SMR_OK ? hipSuccess : hipErrorLaunchFailure;
+    }, &ms);
+    if (e != hipSuccess) return fail(SMR_EDEVICE, "timing the P^-1 variants failed: %s", hipGetErrorString(e));
+    if (v == 0 || ms < 0.97f * best) {
+      best = v == 0 ? ms : std::min(best, ms);
+      arg = v;
+    }
+  }
+  p.pinv_var = arg;
+  tune_put(key, arg);
   return SMR_OK;
 }
 
@@ -1077,6 +1144,27 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
 
 extern "C" {
 
+smr_status smr_pinv_variant(const smr_plan *plan, int32_t *variant) {
+  if (!plan || !variant) return fail(SMR_EINVAL, "plan and variant must be non-NULL");
+  *variant = plan->p.pinv_var;
+  return SMR_OK;
+}
+
+smr_status smr_tune_stats(int64_t *entries, int64_t *hits, int64_t *misses) {
+  if (!entries || !hits || !misses) return fail(SMR_EINVAL, "NULL argument");
+  long e = 0, h = 0, m = 0;
+  tune_stats(&e, &h, &m);
+  *entries = e;
+  *hits = h;
+  *misses = m;
+  return SMR_OK;
+}
+
+smr_status smr_tune_reset(void) {
+  tune_clear();
+  return SMR_OK;
+}
+
 smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols) {
   if (check_plan(plan) != SMR_OK) return SMR_EINVAL;
   if (!cols) return fail(SMR_EINVAL, "cols is NULL");
@@ -1196,6 +1284,34 @@ smr_status check_distinct_plans(int count, const smr_plan *const *plans) {
   return SMR_OK;
 }
 
+// Times one steady fused launch of a group of batch instances at each column-tile width (on
+// their own workspaces, from a running state that never converges, through the batch's
+// descriptor table) and returns the faster: 32 unless 16 is at least 5% faster.
+smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const std::vector<int> &ids, int hp,
+                            int pprec, int taps, SpecP *d_table, int *width) {
+  const int cand[2] = {32, 16};
+  float best[2] = {1e30f, 1e30f};
+  std::vector<SpecP> t(ids.size());
+  for (int k = 0; k < 2; ++k) {
+    int blocks = 0;
+    for (size_t q = 0; q < ids.size(); ++q) {
+      const Plan &p = plans[ids[q]]->p;
+      t[q] = spec_desc(&p, p.T2, p.T1, cand[k]);
+      t[q].rtiles = 0;
+      t[q].tile0 = blocks;
+      blocks += t[q].tiles;
+      HIP_TRY(spec_tune_state(&p, s, t[q]));
+    }
+    HIP_TRY(hipMemcpyAsync(d_table, t.data(), sizeof(SpecP) * t.size(), hipMemcpyHostToDevice, s));
+    // a steady launch with j = 7 reads slot 0 and writes slot 1: repeated launches start alike
+    HIP_TRY(tune_time(s, 4, [&]() {
+      return launch_spec_multi(s, d_table, (int)ids.size(), blocks, hp, cand[k], pprec, taps, 2, 7);
+    }, &best[k]));
+  }
+  *width = best[1] < 0.95f * best[0] ? 16 : 32;
+  return SMR_OK;
+}
+
 smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *const *plans, const double *const *b,
                                 const double *const *x0, double *const *x, double rtol, int32_t maxit, void *d_ws,
                                 smr_info *infos, void *stream) {
@@ -1207,31 +1323,49 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
   // sine-basis instances, grouped by (time-size class, transform precision)
   std::vector<int> spec_ids, general_ids;
   for (int i = 0; i < count; ++i) (use_spectral(plans[i]->p) ? spec_ids : general_ids).push_back(i);
-  // Column-tile width per instance: a width forced on the plan stays; otherwise every
-  // instance of a (time-size class, precision) group takes 32 once the group's 32-column
-  // workgroups cover the compute units (narrow tiles only pay off on an underfilled chip,
-  // which is what the per-plan timing at setup measures).
-  std::vector<int> cols(count, 0);
-  {
-    std::vector<std::pair<long, long>> wide;   // (hp * 2 + pprec, 32-column workgroups)
-    auto forced = [](const Plan &p) { return (p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32)) != 0; };
-    auto group = [&](const Plan &p) -> long & {
-      const long key = (long)p.hp * 2 + p.pprec;
-      for (auto &w : wide)
-        if (w.first == key) return w.second;
-      wide.push_back({key, 0});
-      return wide.back().second;
-    };
-    const long cus = cu_count();
-    for (int i : spec_ids)
-      if (!forced(plans[i]->p)) group(plans[i]->p) += (plans[i]->p.m + 31) / 32;
-    for (int i : spec_ids) {
-      const Plan &p = plans[i]->p;
-      cols[i] = forced(p) ? p.spec_c : !spec_cols_ok(p.hp, 32) ? 16 : group(p) >= cus ? 32 : 16;
-    }
-  }
   // kernel instantiation of an instance's fused launch: 3 time taps (theta, BDF2) or 5
   auto taps_of = [](const Plan &p) { return p.taps <= 3 ? 3 : 5; };
+  // Column-tile width per instance: a width forced on the plan stays; the other instances of
+  // a (time-size class, precision, time taps) group share one width, timed on the group's own
+  // workspaces the first time the group's shape is seen on the device (then cached), before
+  // any of this call's data enters them.
+  std::vector<int> cols(count, 0);
+  {
+    auto forced = [](const Plan &p) { return (p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32)) != 0; };
+    struct Group {
+      int hp, pprec, taps;
+      std::vector<int> ids;
+    };
+    std::vector<Group> groups;
+    for (int i : spec_ids) {
+      const Plan &p = plans[i]->p;
+      if (forced(p)) { cols[i] = p.spec_c; continue; }
+      if (!spec_cols_ok(p.hp, 32)) { cols[i] = 16; continue; }
+      Group *g = nullptr;
+      for (Group &h : groups)
+        if (h.hp == p.hp && h.pprec == p.pprec && h.taps == taps_of(p)) g = &h;
+      if (!g) {
+        groups.push_back(Group{p.hp, p.pprec, taps_of(p), {}});
+        g = &groups.back();
+      }
+      g->ids.push_back(i);
+    }
+    for (const Group &g : groups) {
+      long tiles16 = 0, nvar = 0;
+      for (int i : g.ids) {
+        tiles16 += (plans[i]->p.m + 15) / 16;
+        nvar += plans[i]->p.const_coef ? 0 : 1;
+      }
+      const std::vector<long> key{TUNE_BATCH_WIDTH, g.hp, g.pprec, g.taps, (long)g.ids.size(), tiles16, nvar};
+      int w = 0;
+      if (!tune_get(key, &w)) {
+        const smr_status st = batch_width_tune(s, plans, g.ids, g.hp, g.pprec, g.taps, d_table, &w);
+        if (st != SMR_OK) return st;
+        tune_put(key, w);
+      }
+      for (int i : g.ids) cols[i] = w;
+    }
+  }
   std::stable_sort(spec_ids.begin(), spec_ids.end(), [&](int a, int c) {
     const Plan &pa = plans[a]->p, &pc = plans[c]->p;
     if (pa.hp != pc.hp) return pa.hp < pc.hp;

@@ -5,7 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "smr.h"
 
@@ -77,6 +79,8 @@ struct Plan {
   int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
   int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
   int spec_c;                 // column-tile width of the fused sine-basis kernel (16 or 32)
+  int pinv_var;               // physical-basis P^{-1} of a float32 plan: 0 float64 intermediates,
+                              // 1 float32, 2 float32 with 16-line column tiles; -1 otherwise
   // tables (device)
   double *ax, *ay, *az;       // face values (filled with 1 for a = 1; az in 3D only)
   double *tmu;                // m: tau * eigenvalue of K (a const) or Kbar, sine-basis order
@@ -130,11 +134,20 @@ hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const dou
 // eta_s + zeta_s * abar * tau * mu_lap.
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
                       const Scal *gate, long in_stride = 0, long out_stride = 0);
+// The same pass with float32 (in32 / out32) or float64 input and output vectors; the
+// transform itself runs in float64 (float32 intermediates of a mixed-precision P^{-1}).
+// col16: 16-line tiles in float32 column passes of the line-tile kernels (else 8).
+hipError_t launch_dst_v(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices,
+                        int scale_mode, const Scal *gate, long in_stride = 0, long out_stride = 0,
+                        bool col16 = false);
 // Time transform: mode 0: out = (S_n (x) I) in; mode 1: out = (S_n (x) I) diag(1/sigma) (S_n (x) I) in
 // with partial sums of <D vhat, vhat> into part when part != null.  f32: the GEMMs on the
 // float32 matrix cores with the plan's float32 sine tables (pprec SMR_FP32 plans only).
 hipError_t launch_time(Ctx c, const double *in, double *out, int mode, double *part, int *nblocks_out,
                        const Scal *gate, bool f32 = false);
+// Float32 GEMMs (SMR_FP32 plans) with float32 (in32 / out32) or float64 vectors in memory.
+hipError_t launch_time_v(Ctx c, const void *in, bool in32, void *out, bool out32, int mode, double *part,
+                         int *nblocks_out, const Scal *gate);
 
 // Elementwise / reductions / scalar steps.
 hipError_t launch_vupdate(Ctx c, const double *q, const double *v, double *vold_inout, const Scal *gate);
@@ -202,8 +215,8 @@ hipError_t launch_dst2d(Ctx c, const double *in, double *out, long in_stride, lo
 // One DST-I pass (the arguments of launch_dst) as line tiles through the register FFT, for 2D
 // plans with N + 1 in {32, 64, 128, 256}; launch_dst takes it where it applies.
 bool dst_tile_supported(const Plan *p);
-hipError_t launch_dst_tile(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
-                           const Scal *gate, long in_stride, long out_stride);
+hipError_t launch_dst_tile(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices, int scale_mode,
+                           const Scal *gate, long in_stride, long out_stride, bool col16 = false);
 KsP kslice_desc(const Plan *p, double *x, const double *bh);
 // mode 0: q = (T x)^ before the initialising launch; mode 1: q = (T z_j)^ with its partials
 // before fused launch j
@@ -232,9 +245,24 @@ bool spec_cols_ok(int hp, int cols);
 hipError_t spec_tune(Plan *p, hipStream_t st);
 hipError_t launch_zero_int(Ctx c, int *x, int count);
 
+// ---------------------------------------------------------------- autotuner (tune.cpp)
+// Process-wide cache of timed launch choices per device, keyed by the shape they depend on.
+bool tune_get(const std::vector<long> &key, int *choice);
+void tune_put(const std::vector<long> &key, int choice);
+void tune_stats(long *entries, long *hits, long *misses);
+void tune_clear();
+// One warm call of run, then reps timed calls on st (HIP events); ms per call.  Synchronises st.
+hipError_t tune_time(hipStream_t st, int reps, const std::function<hipError_t()> &run, float *ms_per_call);
+// Cache keys (first element) of the tuned choices.
+enum TuneKind : long { TUNE_SPEC_WIDTH = 1, TUNE_PINV = 2, TUNE_BATCH_WIDTH = 3 };
+// The scalar state and partial sums of a running steady iteration that never converges, for
+// timing fused launches on a plan's workspace (k_spec.hip).
+hipError_t spec_tune_state(const Plan *p, hipStream_t st, const SpecP &P);
+
 // Chebyshev per-mode solve pieces (P_theta).
-hipError_t launch_cheb_axpy(Ctx c, double *x, double *dvec, const double *tmp, double a_d, double a_t,
-                            int first, const Scal *gate);
-hipError_t launch_cheb_resid(Ctx c, double *res, const double *dvec, const Scal *gate);
+// f32: the vectors are float32 (mixed-precision P^{-1}); the arithmetic is float64 either way.
+hipError_t launch_cheb_axpy(Ctx c, void *x, void *dvec, const void *tmp, double a_d, double a_t,
+                            int first, const Scal *gate, bool f32 = false);
+hipError_t launch_cheb_resid(Ctx c, void *res, const void *dvec, const Scal *gate, bool f32 = false);
 
 }  // namespace smr

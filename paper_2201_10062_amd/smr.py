@@ -28,7 +28,7 @@ EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
     "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_solve_adjoint_batched", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error", "smr_tile_cols",
-    "smr_apply_P_inv_static",
+    "smr_apply_P_inv_static", "smr_pinv_variant", "smr_tune_stats", "smr_tune_reset",
 )
 STATIC_SCRATCH_BYTES = 64 << 20   # SMR_STATIC_SCRATCH_BYTES
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5, "kslice": 6}
@@ -77,6 +77,9 @@ def load() -> ctypes.CDLL:
     lib.smr_setup.argtypes = [ctypes.POINTER(SmrDesc), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     lib.smr_destroy.argtypes = [P]
     lib.smr_tile_cols.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.smr_pinv_variant.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.smr_tune_stats.argtypes = [ctypes.POINTER(ctypes.c_int64)] * 3
+    lib.smr_tune_reset.argtypes = []
     lib.smr_build_rhs.argtypes = [P, P, P, P, P]
     lib.smr_apply_A.argtypes = [P, P, P, P]
     lib.smr_apply_P_inv.argtypes = [P, P, P, P]
@@ -111,14 +114,18 @@ def _check(st: int):
 FLAG_GENERAL_PATH = 1
 FLAG_TILE16 = 2
 FLAG_TILE32 = 4
+PINV_FLAGS = {None: 0, "f64": 8, "f32": 16, "f32c16": 32}
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
-              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None):
+              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
-    tile_cols: None (timed at setup), 16 or 32."""
+    tile_cols: None (timed at setup), 16 or 32.  pinv: None (timed at setup), "f64", "f32" or
+    "f32c16" (the physical-basis P^{-1} variant of a float32 plan)."""
     if tile_cols not in (None, 16, 32):
         raise ValueError(f"tile_cols must be None, 16 or 32 (got {tile_cols})")
+    if pinv not in PINV_FLAGS:
+        raise ValueError(f"pinv must be one of {list(PINV_FLAGS)} (got {pinv})")
     keep = []
 
     def host(a):
@@ -130,7 +137,7 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
 
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
                 cheb_k=cheb_k, flags=(FLAG_GENERAL_PATH if general_path else 0)
-                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32}[tile_cols], T=T, theta=theta,
+                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32}[tile_cols] | PINV_FLAGS[pinv], T=T, theta=theta,
                 ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal), az_host=host(az))
     return d, keep
 
@@ -146,6 +153,18 @@ def profile_read(cls: str):
     ms = ctypes.c_double(0.0)
     _check(load().smr_profile_read(PROFILE_CLASSES[cls], ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def tune_stats():
+    """(entries, hits, misses) of the autotuner's process-wide cache."""
+    v = [ctypes.c_int64(0) for _ in range(3)]
+    _check(load().smr_tune_stats(*[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def tune_reset():
+    """Clear the autotuner's cache: the next plans and batches time their choices again."""
+    _check(load().smr_tune_reset())
 
 
 def workspace_size(**kw) -> int:
@@ -170,7 +189,7 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None, az=None):
+                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None, az=None, pinv=None):
         """ax, ay, az: face values (az with dim 3 only); a_nodal: nodal values (dim 1, 2).
         workspace: a uint8 device tensor to build the plan in (e.g. the ``raw_workspace``
         of a plan that is no longer used); a new one is allocated when it is None or too small."""
@@ -182,7 +201,7 @@ class Plan:
         self.precond, self.pprec = precond, pprec
         self.device = torch.device(device)
         d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path,
-                            tile_cols, az)
+                            tile_cols, az, pinv)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -205,6 +224,14 @@ class Plan:
         c = ctypes.c_int32(0)
         _check(self.lib.smr_tile_cols(self.handle, ctypes.byref(c)))
         return c.value
+
+    @property
+    def pinv_variant(self) -> str:
+        """The physical-basis P^{-1} variant of a float32 plan ("f64", "f32", "f32c16"), or None
+        (float64 plans and sine-basis solves)."""
+        c = ctypes.c_int32(0)
+        _check(self.lib.smr_pinv_variant(self.handle, ctypes.byref(c)))
+        return {0: "f64", 1: "f32", 2: "f32c16"}.get(c.value)
 
     @property
     def raw_workspace(self):

@@ -139,6 +139,28 @@ def test_fp32_3d_sine_basis():
     assert rel(xr, ref.x) < 1e-6
 
 
+@pytest.mark.parametrize("precond", ["PH", "PTHETA_CHEB"])
+def test_fp32_3d_physical_basis(precond):
+    """Variable a in 3D with float32 time transforms and float32 intermediates of P^{-1}
+    (parity unpinned by rounding): float64 true residual at the tolerance, iterations within
+    10% (+1) of the float64 oracle's, error reported."""
+    _dev()
+    N, n = 15, 16
+    g, o = _pair(N, n, "theta", 1.0, "var", precond, pprec="fp32")
+    assert g.tile_cols == 0
+    rng = np.random.default_rng(23)
+    b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m))
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    x, info = g.solve(_t(b), rtol=1e-8, maxit=400)
+    xr = _n(x)
+    r = np.linalg.norm(b - o.apply_T(xr)) / np.linalg.norm(b)
+    print(f"3D fp32 physical {precond}: iters {info['iters']} (fp64 oracle {ref.iters}) relres {r:.2e} "
+          f"err {rel(xr, ref.x):.2e}")
+    assert info["status"] == "ok" and r <= 1e-8
+    assert info["iters"] <= int(1.1 * ref.iters) + 1
+    assert rel(xr, ref.x) < 1e-6
+
+
 def test_grad_a_rejects_3d():
     from paper_2201_10062_amd import smr
     _dev()

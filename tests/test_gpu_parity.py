@@ -306,19 +306,27 @@ def test_mixed_fp32_solve(dim, N, n, scheme, theta):
     assert rel(x, _n(x64)) > 1e-13
 
 
-@pytest.mark.parametrize("case", ["var-N15", "ptheta", "general-const", "1d-var", "hp256-var"])
+@pytest.mark.parametrize("case", ["var-N15", "ptheta", "general-const", "1d-var", "hp256-var", "ptheta-N255",
+                                  "ph-N255-var", "ptheta-N127", "ptheta-N63-general"])
 def test_mixed_fp32_physical_basis(case):
-    """Float32 time transforms on the physical-basis path (variable a with N + 1 outside
-    {32, 64, 128}, P_theta, the forced general path, 1D variable a): the float64 true residual
-    reaches the tolerance, iterations within 10% (+1) of the float64 oracle's, error vs the
-    oracle small and reported, and the float32 transform really ran."""
+    """Mixed precision on the physical-basis path (variable a with N + 1 outside {32, 64, 128},
+    P_theta, the forced general path, 1D variable a; every spatial-transform kernel: the
+    radix-2 LDS FFT, the register-FFT line tiles and the regrouped 512-point pass): float32
+    time transforms and float32 intermediates of P^{-1} (each spatial pass and Chebyshev step).
+    Parity unpinned by rounding; checked: the float64 true residual reaches the tolerance,
+    iterations within 10% (+1) of the float64 oracle's, error vs the oracle small and reported,
+    and the float32 path really ran."""
     from paper_2201_10062_amd import Plan
     dim, N, n, theta, precond, kind, general = {
         "var-N15": (2, 15, 24, 1.0, "PH", "var", False),
         "ptheta": (2, 15, 24, 1.0, "PTHETA_CHEB", "smooth", False),
         "general-const": (2, 31, 32, 0.5, "PH", "const", True),
         "1d-var": (1, 63, 64, 1.0, "PH", "var", False),
-    "hp256-var": (2, 15, 300, 1.0, "PH", "var", False),
+        "hp256-var": (2, 15, 300, 1.0, "PH", "var", False),
+        "ptheta-N255": (2, 255, 16, 1.0, "PTHETA_CHEB", "smooth", False),
+        "ph-N255-var": (2, 255, 12, 1.0, "PH", "smooth", False),
+        "ptheta-N127": (2, 127, 20, 0.5, "PTHETA_CHEB", "var", False),
+        "ptheta-N63-general": (2, 63, 24, 1.0, "PTHETA_CHEB", "const", True),
     }[case]
     ax, ay = _faces(kind, N, dim)
     kw = dict(scheme="theta", theta=theta, precond=precond, cheb_k=3, ax=ax, ay=ay, general_path=general)

@@ -1,0 +1,124 @@
+"""The autotuner: choices timed on the device the first time a shape is seen, cached per device.
+
+  * the physical-basis P^{-1} variants of a float32 plan (float64 intermediates, float32
+    intermediates, float32 with 16-line column tiles), each forced by a flag: the float64 true
+    residual reaches the tolerance, iterations within 10% (+1) of the float64 oracle's (parity
+    unpinned by rounding), error against the oracle reported;
+  * the tuned choice is one of them, and a second plan of the same shape takes it from the
+    cache without timing again;
+  * the fused kernel's width of single plans and of batch classes is cached the same way, and
+    batched solves after tuning still equal the oracle per instance.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.system import System
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64)).reshape(-1)).to(_dev())
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _smooth(N):
+    return W.sample_faces(lambda x, y: 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y), N, 2)
+
+
+CASES = {"ptheta-N255": (255, 16, "PTHETA_CHEB"), "ph-N127": (127, 24, "PH"), "ptheta-N63": (63, 32, "PTHETA_CHEB"),
+         "ph-N15": (15, 24, "PH")}
+
+
+@pytest.mark.parametrize("pinv", ["f64", "f32", "f32c16"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_forced_pinv_variants(case, pinv):
+    from paper_2201_10062_amd import Plan
+    _dev()
+    N, n, precond = CASES[case]
+    ax, ay = _smooth(N)
+    kw = dict(theta=1.0, precond=precond, cheb_k=3, ax=ax, ay=ay)
+    g = Plan(2, N, n, pprec="fp32", pinv=pinv, general_path=True, **kw)
+    assert g.tile_cols == 0
+    expect = "f32" if (pinv == "f32c16" and N + 1 < 32) else pinv
+    assert g.pinv_variant == expect
+    o = System(2, N, n, **kw)
+    rng = np.random.default_rng(31)
+    b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m))
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    x, info = g.solve(_t(b), rtol=1e-8, maxit=400)
+    xr = _n(x)
+    r = np.linalg.norm(b - o.apply_T(xr)) / np.linalg.norm(b)
+    print(f"{case} pinv={pinv}: iters {info['iters']} (fp64 oracle {ref.iters}) relres {r:.2e} err {rel(xr, ref.x):.2e}")
+    assert info["status"] == "ok" and r <= 1e-8
+    assert info["iters"] <= int(1.1 * ref.iters) + 1
+    assert rel(xr, ref.x) < 1e-6
+
+
+def test_tuned_pinv_variant_is_cached():
+    from paper_2201_10062_amd import Plan, smr
+    _dev()
+    smr.tune_reset()
+    N, n = 63, 20
+    ax, ay = _smooth(N)
+    g1 = Plan(2, N, n, theta=1.0, precond="PTHETA_CHEB", ax=ax, ay=ay, pprec="fp32")
+    e1, h1, m1 = smr.tune_stats()
+    assert g1.pinv_variant in ("f64", "f32", "f32c16") and m1 >= 1
+    g2 = Plan(2, N, n, theta=1.0, precond="PTHETA_CHEB", ax=ax, ay=ay, pprec="fp32")
+    e2, h2, m2 = smr.tune_stats()
+    assert g2.pinv_variant == g1.pinv_variant
+    assert h2 == h1 + 1 and m2 == m1 and e2 == e1
+    # a float64 plan has no variant
+    assert Plan(2, N, n, theta=1.0, precond="PTHETA_CHEB", ax=ax, ay=ay).pinv_variant is None
+
+
+def test_fused_width_is_cached():
+    from paper_2201_10062_amd import Plan, smr
+    _dev()
+    smr.tune_reset()
+    g1 = Plan(2, 63, 64, theta=0.5)
+    _, h1, m1 = smr.tune_stats()
+    g2 = Plan(2, 63, 64, theta=0.5)
+    _, h2, m2 = smr.tune_stats()
+    assert g2.tile_cols == g1.tile_cols in (16, 32)
+    assert h2 == h1 + 1 and m2 == m1
+
+
+def test_batch_width_tuned_cached_and_exact():
+    """A batch whose classes have no forced width: the first call times each class, the
+    second finds them cached; both equal the oracle per instance."""
+    from paper_2201_10062_amd import Batch, Plan, smr
+    _dev()
+    probs = W.bdf2_batch(count=9, Ns=(15, 31), ns=(64, 128))
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay) for p in probs]
+    smr.tune_reset()
+    refs = [System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay).solve(p.b.reshape(-1), rtol=1e-8, maxit=500)
+            for p in probs]
+    batch = Batch(plans)
+    stats = []
+    for rep in range(2):
+        xs, infos = batch.solve([_t(p.b) for p in probs], rtol=1e-8)
+        stats.append(smr.tune_stats())
+        for p, x, info, ref in zip(probs, xs, infos, refs):
+            assert info["status"] == "ok" and info["iters"] == ref.iters, (rep, p.name)
+            assert rel(_n(x), ref.x) < 1e-10, (rep, p.name)
+    (e1, h1, m1), (e2, h2, m2) = stats
+    assert m1 >= 1 and e1 >= 1          # timed on the first call
+    assert m2 == m1 and h2 > h1         # cached on the second
