@@ -41,6 +41,7 @@ PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X dense FP64 vector peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_spec_cn2d_N127_n256.json")
 TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_k_spec_multi_bdf2_batch64.json")
+TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "traffic_k_spec_3d_ex3_N63_n64.json")
 CSRC = os.path.join(ROOT, "paper_2201_10062_amd", "csrc")
 
 
@@ -412,7 +413,7 @@ def paper_tables_leg(dev, reps: int = 3):
                 bpl = spec_fp64_bytes([pinfo], dof) / max(nl, 1)
                 gbs = bpl / (msl / max(nl, 1) * 1e-3) / 1e9
                 e["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                 "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                                 "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_entry(TRAFFIC_FILE_3D),
                                  "kernel": "k_spec + grouped partial reduction (3D, 4D sine basis)",
                                  "launches": nl, "avg_launch_us": msl / max(nl, 1) * 1e3, "bytes_per_launch": bpl,
                                  "tile_cols": g.tile_cols}
