@@ -106,16 +106,19 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
  * reductions.  Setting both bits is SMR_EINVAL. */
 #define SMR_FLAG_TILE16 2
 #define SMR_FLAG_TILE32 4
-/* Intermediates of the physical-basis P^{-1} of an SMR_FP32 plan (no effect on the sine-basis
- * path): float64 vectors with float32 time-transform GEMMs (PINV_F64), float32 vectors
- * (PINV_F32), or float32 vectors with 16-line tiles in the spatial transform's column passes
- * (PINV_F32_COL16; 2D with N + 1 in {32, ..., 256}, else as PINV_F32).  With none set,
- * smr_setup times one P^{-1} application of each on the plan's workspace and keeps the
- * fastest (float64 unless another is 3% faster), cached per device and shape;
- * smr_pinv_variant reports the choice.  At most one; SMR_EINVAL on a float64 plan. */
+/* Variant of the physical-basis P^{-1} (no effect on the sine-basis path): 8-line (PINV_F64)
+ * or 16-line (PINV_F64_COL16) tiles in the spatial transform's column passes with float64
+ * intermediate vectors, and for SMR_FP32 plans float32 intermediate vectors with 8-line
+ * (PINV_F32) or 16-line (PINV_F32_COL16) column tiles (float64 intermediates of an SMR_FP32
+ * plan keep float32 GEMMs in the time transform).  16-line tiles apply to 2D plans with
+ * N + 1 in {32, ..., 256} (others take the 8-line form).  With none set, smr_setup times a
+ * few P^{-1} applications of each candidate on the plan's workspace and keeps the fastest
+ * (PINV_F64 unless another is 3% faster), cached per device and shape; smr_pinv_variant
+ * reports the choice.  At most one; the float32 ones need SMR_FP32 (else SMR_EINVAL). */
 #define SMR_FLAG_PINV_F64 8
 #define SMR_FLAG_PINV_F32 16
 #define SMR_FLAG_PINV_F32_COL16 32
+#define SMR_FLAG_PINV_F64_COL16 64
 
 typedef struct {
   int32_t dim;             /* spatial dimension, 1, 2 or 3                                */
@@ -171,9 +174,10 @@ smr_status smr_setup(const smr_desc *desc, void *d_ws, size_t ws_bytes, void *st
  * SMR_FLAG_TILE16), 0 when its solves run in the physical basis.  Host only. */
 smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols);
 
-/* The physical-basis P^{-1} variant of an SMR_FP32 plan (see SMR_FLAG_PINV_F64): 0 float64
- * intermediates, 1 float32, 2 float32 with 16-line column tiles; -1 for float64 plans and
- * plans whose solves run in the sine basis.  Host only. */
+/* The physical-basis P^{-1} variant of a plan (see SMR_FLAG_PINV_F64): 0 float64
+ * intermediates, 1 float32, 2 float32 with 16-line column tiles, 3 float64 with 16-line
+ * column tiles; -1 for plans whose solves run in the sine basis or without a preconditioner.
+ * Host only. */
 smr_status smr_pinv_variant(const smr_plan *plan, int32_t *variant);
 
 /* The autotuner's cache (host, process-wide): shapes timed so far (entries), and how many

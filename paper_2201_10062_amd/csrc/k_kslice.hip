@@ -534,8 +534,8 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
 
 // TI, TO: element types of the vectors in memory (float32 intermediates of a mixed-precision
 // P^{-1}); the tile in LDS and the FFT stay float64.
-// TL: lines per tile (16 for float32 column passes, so that a tile's row piece is a whole
-// 64-byte segment).
+// TL: lines per tile (8, or 16 in column passes when tuned: a tile's row piece is then 128
+// bytes of float64 or 64 of float32).
 template <int R, int DIR, typename TI, typename TO, int TL>
 __global__ __launch_bounds__(kTT) void k_dst_tile(TileP d, const TI *__restrict__ in, TO *__restrict__ out,
                                                   const Scal *__restrict__ gate) {
@@ -633,8 +633,8 @@ __device__ __forceinline__ void pair_dft512(double2 (&v)[8], int lane, const dou
 // range, holding the next tile's loads in registers while the current tile is transformed
 // (loads of one tile and stores of another touch different lines, so in == out is allowed);
 // the regrouping buffers alias the tile once the line pairs are in registers.
-// NWV waves, one line pair each: tiles of 2 NWV lines (8 lines, or 16 for float32 column
-// passes so that a tile's row piece is a whole 64-byte segment).
+// NWV waves, one line pair each: tiles of 2 NWV lines (8 lines, or 16 in column passes when
+// tuned, for longer row pieces).
 template <int DIR, typename TI, typename TO, int NWV>
 __global__ __launch_bounds__(64 * NWV) void k_dst_tile512(TileP d, const TI *__restrict__ in,
                                                           TO *__restrict__ out, const Scal *__restrict__ gate,
@@ -749,8 +749,7 @@ constexpr int kGrid512[2] = {2048, 4096};
 template <int R, typename TI, typename TO>
 hipError_t run_dst_tile(hipStream_t st, int dir, TileP d, int nslices, const TI *in, TO *out, const Scal *gate,
                         bool col16) {
-  constexpr bool F32 = std::is_same<TI, float>::value || std::is_same<TO, float>::value;
-  const int TLr = (F32 && dir == 1 && col16) ? 16 : kTL;   // lines per tile of this pass
+  const int TLr = (dir == 1 && col16) ? 16 : kTL;   // lines per tile of this pass
   d.tiles = (d.N + TLr - 1) / TLr;
   if constexpr (R == 8) {
     const long total = (long)nslices * d.tiles;

@@ -191,11 +191,13 @@ smr_status validate(const smr_desc *d) {
   if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
     return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
   const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 |
-                    SMR_FLAG_PINV_F32_COL16;
+                    SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16;
   if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
-  const int pinv_flags = d->flags & (SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16);
+  const int pinv_flags =
+      d->flags & (SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16);
   if (pinv_flags & (pinv_flags - 1)) return fail(SMR_EINVAL, "at most one SMR_FLAG_PINV_* flag");
-  if (pinv_flags && d->pprec != SMR_FP32) return fail(SMR_EINVAL, "SMR_FLAG_PINV_* flags need pprec SMR_FP32");
+  if ((pinv_flags & (SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16)) && d->pprec != SMR_FP32)
+    return fail(SMR_EINVAL, "float32 P^-1 intermediates need pprec SMR_FP32");
   if ((d->flags & SMR_FLAG_TILE16) && (d->flags & SMR_FLAG_TILE32))
     return fail(SMR_EINVAL, "SMR_FLAG_TILE16 and SMR_FLAG_TILE32 exclude each other");
   if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
@@ -625,12 +627,14 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
       return fail(SMR_EDEVICE, "tile-width timing failed: %s", hipGetErrorString(e));
     }
   }
-  // the physical-basis P^{-1} of a float32 plan: forced by a flag, else timed
+  // the physical-basis P^{-1} variant: forced by a flag, else timed
   p.pinv_var = -1;
-  if (p.pprec == SMR_FP32 && !use_spectral(p)) {
+  if (!use_spectral(p) && p.precond != SMR_P_NONE) {
+    const bool tiles = dst_tile_supported(&p);
     if (p.flags & SMR_FLAG_PINV_F64) p.pinv_var = 0;
     else if (p.flags & SMR_FLAG_PINV_F32) p.pinv_var = 1;
-    else if (p.flags & SMR_FLAG_PINV_F32_COL16) p.pinv_var = dst_tile_supported(&p) ? 2 : 1;
+    else if (p.flags & SMR_FLAG_PINV_F32_COL16) p.pinv_var = tiles ? 2 : 1;
+    else if (p.flags & SMR_FLAG_PINV_F64_COL16) p.pinv_var = tiles ? 3 : 0;
     else {
       const smr_status ts = pinv_tune(p, s);
       if (ts != SMR_OK) {
@@ -685,8 +689,9 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
     if (part2) LAUNCH(PROF_VEC, launch_dot(c, z, v, part2, nb2, gate));
     return SMR_OK;
   }
-  const bool w = f32 && p.pinv_var >= 1;     // float32 intermediates (the plan's tuned variant)
-  const bool c16 = f32 && p.pinv_var == 2;   // with 16-line column tiles
+  // the plan's tuned variant: float32 intermediates (float32 solves only), 16-line column tiles
+  const bool w = f32 && (p.pinv_var == 1 || p.pinv_var == 2);
+  const bool c16 = p.pinv_var == 2 || p.pinv_var == 3;
   if (p.precond == SMR_P_H) {
     LAUNCH(PROF_DST, launch_dst_v(c, 0, v, false, tb.t1, w, p.n, 0, gate, 0, 0, c16));
     for (int ax = 1; ax < p.dim; ++ax)
@@ -733,14 +738,24 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   return SMR_OK;
 }
 
-// The intermediates of a float32 plan's physical-basis P^{-1}: float64 vectors (float32 only
-// inside the time transform's GEMMs), float32 vectors, or float32 vectors with 16-line column
-// tiles in the spatial transform.  Which is fastest depends on the shape (the spatial passes
-// are bound by memory-instruction issue as much as by bytes), so one application of each is
-// timed on the plan's workspace and the fastest kept (float64 unless another is 3% faster).
+// The physical-basis P^{-1} variant: the spatial transform's column passes with 8- or 16-line
+// tiles, and for a float32 plan float64 or float32 intermediate vectors (float32 only inside
+// the time transform's GEMMs, or everywhere).  Which is fastest depends on the shape (the
+// spatial passes are bound by memory-instruction issue as much as by bytes), so a few
+// applications of each are timed on the plan's workspace and the fastest kept (variant 0
+// unless another is 3% faster).
 smr_status pinv_tune(Plan &p, hipStream_t s) {
-  const int nvar = dst_tile_supported(&p) ? 3 : 2;
-  const std::vector<long> key{TUNE_PINV, p.dim, p.N, p.n, p.precond, p.cheb_k, p.scheme};
+  std::vector<int> cand{0};
+  if (dst_tile_supported(&p)) cand.push_back(3);
+  if (p.pprec == SMR_FP32) {
+    cand.push_back(1);
+    if (dst_tile_supported(&p)) cand.push_back(2);
+  }
+  if (cand.size() == 1) {
+    p.pinv_var = 0;
+    return SMR_OK;
+  }
+  const std::vector<long> key{TUNE_PINV, p.dim, p.N, p.n, p.precond, p.cheb_k, p.scheme, p.pprec};
   int cached = 0;
   if (tune_get(key, &cached)) {
     p.pinv_var = cached;
@@ -749,12 +764,13 @@ smr_status pinv_tune(Plan &p, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(p.V[0], 0, p.len * sizeof(double), s));
   float best = 1e30f;
   int arg = 0;
-  for (int v = 0; v < nvar; ++v) {
+  for (int v : cand) {
     p.pinv_var = v;
     float ms = 0.0f;
     const hipError_t e = tune_time(s, 3, [&]() -> hipError_t {
       int nb2 = 0;
-      const smr_status st = apply_pinv(p, s, p.V[0], p.Z[0], p.part + 2 * kRedSlots, &nb2, nullptr, true, plan_bufs(p));
+      const smr_status st =
+          apply_pinv(p, s, p.V[0], p.Z[0], p.part + 2 * kRedSlots, &nb2, nullptr, p.pprec == SMR_FP32, plan_bufs(p));
       return st == SMR_OK ? hipSuccess : hipErrorLaunchFailure;
     }, &ms);
     if (e != hipSuccess) return fail(SMR_EDEVICE, "timing the P^-1 variants failed: %s", hipGetErrorString(e));

@@ -79,8 +79,9 @@ struct Plan {
   int L, logL;                // L = N + 1 = 2^logL (spatial sine transform length)
   int h1, h2, hp;             // folded time halves: ceil(n/2), floor(n/2), padded to 16
   int spec_c;                 // column-tile width of the fused sine-basis kernel (16 or 32)
-  int pinv_var;               // physical-basis P^{-1} of a float32 plan: 0 float64 intermediates,
-                              // 1 float32, 2 float32 with 16-line column tiles; -1 otherwise
+  int pinv_var;               // physical-basis P^{-1}: 0 float64 intermediates, 1 float32, 2 float32
+                              // with 16-line column tiles, 3 float64 with 16-line column tiles
+                              // (float32 only in SMR_FP32 solves); -1 on the sine-basis path
   // tables (device)
   double *ax, *ay, *az;       // face values (filled with 1 for a = 1; az in 3D only)
   double *tmu;                // m: tau * eigenvalue of K (a const) or Kbar, sine-basis order
@@ -136,7 +137,7 @@ hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices
                       const Scal *gate, long in_stride = 0, long out_stride = 0);
 // The same pass with float32 (in32 / out32) or float64 input and output vectors; the
 // transform itself runs in float64 (float32 intermediates of a mixed-precision P^{-1}).
-// col16: 16-line tiles in float32 column passes of the line-tile kernels (else 8).
+// col16: 16-line tiles in the column passes of the line-tile kernels (else 8).
 hipError_t launch_dst_v(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices,
                         int scale_mode, const Scal *gate, long in_stride = 0, long out_stride = 0,
                         bool col16 = false);

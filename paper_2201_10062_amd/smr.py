@@ -114,14 +114,14 @@ def _check(st: int):
 FLAG_GENERAL_PATH = 1
 FLAG_TILE16 = 2
 FLAG_TILE32 = 4
-PINV_FLAGS = {None: 0, "f64": 8, "f32": 16, "f32c16": 32}
+PINV_FLAGS = {None: 0, "f64": 8, "f32": 16, "f32c16": 32, "f64c16": 64}
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
               ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
-    tile_cols: None (timed at setup), 16 or 32.  pinv: None (timed at setup), "f64", "f32" or
-    "f32c16" (the physical-basis P^{-1} variant of a float32 plan)."""
+    tile_cols: None (timed at setup), 16 or 32.  pinv: None (timed at setup), "f64", "f64c16",
+    "f32" or "f32c16" (the physical-basis P^{-1} variant; the float32 ones for float32 plans)."""
     if tile_cols not in (None, 16, 32):
         raise ValueError(f"tile_cols must be None, 16 or 32 (got {tile_cols})")
     if pinv not in PINV_FLAGS:
@@ -227,11 +227,11 @@ class Plan:
 
     @property
     def pinv_variant(self) -> str:
-        """The physical-basis P^{-1} variant of a float32 plan ("f64", "f32", "f32c16"), or None
-        (float64 plans and sine-basis solves)."""
+        """The physical-basis P^{-1} variant ("f64", "f64c16", "f32", "f32c16"), or None
+        (sine-basis solves, P = I)."""
         c = ctypes.c_int32(0)
         _check(self.lib.smr_pinv_variant(self.handle, ctypes.byref(c)))
-        return {0: "f64", 1: "f32", 2: "f32c16"}.get(c.value)
+        return {0: "f64", 1: "f32", 2: "f32c16", 3: "f64c16"}.get(c.value)
 
     @property
     def raw_workspace(self):

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
     (dict(dim=3, N=7, n=4, ax=np.ones((7, 7, 8)), ay=np.ones((7, 8, 7))), smr.SMR_EINVAL),   # az missing
     (dict(dim=2, N=7, n=4, ax=np.ones((7, 8)), ay=np.ones((8, 7)), az=np.ones(1)), smr.SMR_EINVAL),
     (dict(dim=3, N=7, n=4, a_nodal=np.ones((9, 9, 9))), smr.SMR_EINVAL),   # 3D takes face values
-    (dict(dim=2, N=7, n=4, pinv="f32"), smr.SMR_EINVAL),               # P^-1 variants: float32 plans only
+    (dict(dim=2, N=7, n=4, pinv="f32"), smr.SMR_EINVAL),               # float32 intermediates: float32 plans only
     (dict(dim=2, N=6, n=4), smr.SMR_EINVAL),           # N + 1 not a power of two
     (dict(dim=2, N=1023, n=4), smr.SMR_EINVAL),        # N too large
     (dict(dim=2, N=7, n=0), smr.SMR_EINVAL),
@@ -68,7 +68,7 @@ def test_tile_width_flags_checked_on_host():
     out = ctypes.c_size_t(0)
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     assert b"exclude" in lib.smr_last_error()
-    d.flags = 8
+    d.flags = 128                     # no such flag
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     with pytest.raises(ValueError):
         smr.make_desc(2, 7, 4, tile_cols=24)
@@ -96,6 +96,7 @@ def test_null_plan_rejected():
 
 def test_pinv_flags_checked_on_host():
     assert smr.workspace_size(dim=2, N=7, n=4, pprec="fp32", pinv="f32c16") > 0
+    assert smr.workspace_size(dim=2, N=7, n=4, pinv="f64c16") > 0
     d, keep = smr.make_desc(2, 7, 4, pprec="fp32")
     d.flags = smr.PINV_FLAGS["f32"] | smr.PINV_FLAGS["f64"]
     out = ctypes.c_size_t(0)

@@ -1,9 +1,10 @@
 """The autotuner: choices timed on the device the first time a shape is seen, cached per device.
 
-  * the physical-basis P^{-1} variants of a float32 plan (float64 intermediates, float32
-    intermediates, float32 with 16-line column tiles), each forced by a flag: the float64 true
-    residual reaches the tolerance, iterations within 10% (+1) of the float64 oracle's (parity
-    unpinned by rounding), error against the oracle reported;
+  * the physical-basis P^{-1} variants (8- or 16-line column tiles in the spatial transform;
+    for float32 plans float64 or float32 intermediates), each forced by a flag: float64 plans
+    equal the oracle's iterate to 1e-10; float32 plans reach the tolerance with the float64
+    true residual, iterations within 10% (+1) of the float64 oracle's (parity unpinned by
+    rounding), error against the oracle reported;
   * the tuned choice is one of them, and a second plan of the same shape takes it from the
     cache without timing again;
   * the fused kernel's width of single plans and of batch classes is cached the same way, and
@@ -47,7 +48,7 @@ CASES = {"ptheta-N255": (255, 16, "PTHETA_CHEB"), "ph-N127": (127, 24, "PH"), "p
          "ph-N15": (15, 24, "PH")}
 
 
-@pytest.mark.parametrize("pinv", ["f64", "f32", "f32c16"])
+@pytest.mark.parametrize("pinv", ["f64", "f64c16", "f32", "f32c16"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_forced_pinv_variants(case, pinv):
     from paper_2201_10062_amd import Plan
@@ -57,7 +58,7 @@ def test_forced_pinv_variants(case, pinv):
     kw = dict(theta=1.0, precond=precond, cheb_k=3, ax=ax, ay=ay)
     g = Plan(2, N, n, pprec="fp32", pinv=pinv, general_path=True, **kw)
     assert g.tile_cols == 0
-    expect = "f32" if (pinv == "f32c16" and N + 1 < 32) else pinv
+    expect = pinv.replace("c16", "") if N + 1 < 32 else pinv     # no 16-line tiles below N + 1 = 32
     assert g.pinv_variant == expect
     o = System(2, N, n, **kw)
     rng = np.random.default_rng(31)
@@ -70,6 +71,29 @@ def test_forced_pinv_variants(case, pinv):
     assert info["status"] == "ok" and r <= 1e-8
     assert info["iters"] <= int(1.1 * ref.iters) + 1
     assert rel(xr, ref.x) < 1e-6
+
+
+@pytest.mark.parametrize("pinv", ["f64", "f64c16"])
+@pytest.mark.parametrize("case", ["ptheta-N255", "ph-N127"])
+def test_float64_column_tiles_exact(case, pinv):
+    """Float64 plans with 8- or 16-line column tiles: the oracle's iterate to 1e-10 at its
+    stopping iteration, and P^{-1} to 1e-12."""
+    from paper_2201_10062_amd import Plan
+    _dev()
+    N, n, precond = CASES[case]
+    ax, ay = _smooth(N)
+    kw = dict(theta=1.0, precond=precond, cheb_k=3, ax=ax, ay=ay)
+    g = Plan(2, N, n, pinv=pinv, general_path=True, **kw)
+    assert g.tile_cols == 0 and g.pinv_variant == pinv
+    o = System(2, N, n, **kw)
+    rng = np.random.default_rng(32)
+    v = rng.standard_normal(n * g.m)
+    assert rel(_n(g.apply_P_inv(_t(v))), o.apply_Pinv(v)) < 1e-12
+    b = o.rhs(rng.standard_normal((n + 1, g.m)), rng.standard_normal(g.m))
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    x, info = g.solve(_t(b), rtol=1e-8, maxit=400)
+    assert info["status"] == "ok" and info["iters"] == ref.iters
+    assert rel(_n(x), ref.x) < 1e-10
 
 
 def test_tuned_pinv_variant_is_cached():
@@ -85,8 +109,9 @@ def test_tuned_pinv_variant_is_cached():
     e2, h2, m2 = smr.tune_stats()
     assert g2.pinv_variant == g1.pinv_variant
     assert h2 == h1 + 1 and m2 == m1 and e2 == e1
-    # a float64 plan has no variant
-    assert Plan(2, N, n, theta=1.0, precond="PTHETA_CHEB", ax=ax, ay=ay).pinv_variant is None
+    # a float64 plan chooses between the float64 variants; the sine basis has none
+    assert Plan(2, N, n, theta=1.0, precond="PTHETA_CHEB", ax=ax, ay=ay).pinv_variant in ("f64", "f64c16")
+    assert Plan(2, N, n, theta=1.0).pinv_variant is None
 
 
 def test_fused_width_is_cached():
