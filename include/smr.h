@@ -100,12 +100,15 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
  * modes of all n time levels (the folded time blocks of Sec. 3.1.1 are contracted per tile
  * on the matrix cores).  With neither bit set, smr_setup times one steady iteration at each
  * width on the plan's own workspace and keeps 32 unless 16 is at least 5% faster (narrow
- * tiles pay off when the spatial grid is small); the choice is cached per device and shape
- * (see smr_tune_stats).  32 needs ceil(n/2) <= 128 (SMR_EUNSUPPORTED otherwise) and
+ * tiles pay off when the spatial grid is small; with ceil(n/2) <= 32 a 64-mode tile is a
+ * third candidate, for large grids with few time levels); the choice is cached per device
+ * and shape (see smr_tune_stats).  32 needs ceil(n/2) <= 128 and 64 (SMR_FLAG_TILE64, single
+ * solves only: batched calls take 16 or 32) ceil(n/2) <= 32 (SMR_EUNSUPPORTED otherwise);
  * ceil(n/2) > 128 always takes 16.  The width changes only the summation order of the
- * reductions.  Setting both bits is SMR_EINVAL. */
+ * reductions.  Setting more than one of the three bits is SMR_EINVAL. */
 #define SMR_FLAG_TILE16 2
 #define SMR_FLAG_TILE32 4
+#define SMR_FLAG_TILE64 128
 /* Variant of the physical-basis P^{-1} (no effect on the sine-basis path): 8-line (PINV_F64)
  * or 16-line (PINV_F64_COL16) tiles in the spatial transform's column passes with float64
  * intermediate vectors, and for SMR_FP32 plans float32 intermediate vectors with 8-line
@@ -170,7 +173,7 @@ smr_status smr_workspace_size(const smr_desc *desc, size_t *bytes);
 smr_status smr_setup(const smr_desc *desc, void *d_ws, size_t ws_bytes, void *stream,
                      smr_plan **out);
 
-/* Column-tile width the plan's sine-basis solves launch with (16 or 32; see
+/* Column-tile width the plan's sine-basis solves launch with (16, 32 or 64; see
  * SMR_FLAG_TILE16), 0 when its solves run in the physical basis.  Host only. */
 smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols);
 

@@ -56,7 +56,7 @@ int spec_cols(const Plan *p) { return p->spec_c; }
 
 int spec_cols_default(int hp) { return hp >= 256 ? 16 : 32; }
 
-bool spec_cols_ok(int hp, int cols) { return cols == 16 || (cols == 32 && hp <= 128); }
+bool spec_cols_ok(int hp, int cols) { return cols == 16 || (cols == 32 && hp <= 128) || (cols == 64 && hp <= 32); }
 
 SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   SpecP P{};
@@ -174,11 +174,12 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMemsetAsync(p->ZF[i], 0, sizeof(float) * p->vlen, st);
   if (e != hipSuccess) return e;
   // a steady launch with j = 7 reads scalar and partial slot 0 and writes slot 1, so repeated
-  // launches all start from the same state
-  const int cand[2] = {32, 16};
-  float best[2] = {1e30f, 1e30f};
+  // launches all start from the same state; 64-column tiles are a candidate at hp <= 32
+  const int cand[3] = {32, 16, 64};
+  const int ncand = spec_cols_ok(p->hp, 64) ? 3 : 2;
+  float best[3] = {1e30f, 1e30f, 1e30f};
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    for (int k = 0; k < ncand && e == hipSuccess; ++k) {
       p->spec_c = cand[k];
       const SpecP P = spec_desc(p, p->T1, p->T2);
       e = spec_tune_state(p, st, P);
@@ -192,8 +193,11 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
         }, &ms);
       if (e == hipSuccess) best[k] = std::min(best[k], ms);
     }
-  // the wider tile stays unless the narrow one is clearly faster
-  p->spec_c = best[1] < 0.95f * best[0] ? 16 : 32;
+  // 32 stays unless another width is clearly (5%) faster; then the fastest
+  int arg = 0;
+  for (int k = 1; k < ncand; ++k)
+    if (best[k] < 0.95f * best[0] && best[k] < best[arg]) arg = k;
+  p->spec_c = cand[arg];
   if (e == hipSuccess) tune_put(key, p->spec_c);
   return e;
 }

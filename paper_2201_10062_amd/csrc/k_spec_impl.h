@@ -602,11 +602,25 @@ hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode,
   return hipErrorInvalidValue;
 }
 
+// 64-column tiles (single plans with hp <= 32, where a block's fixed costs weigh most)
+template <int PR, int TAPS>
+hipError_t run_spec_hp64(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
+  switch (hp) {
+    case 16: return run_spec<16, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
+    case 32: return run_spec<32, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
 // One launch of the fused kernel (single plan) or of its batched variant, dispatched on the
 // transform precision, the column-tile width and the time padding.
 template <int TAPS>
 hipError_t run_one_taps(hipStream_t st, const SpecP &P, int pprec, int cols, int mode, int blocks, int hp, int jph,
                         int pmode) {
+  if (cols == 64)
+    return pprec == SMR_FP32 ? run_spec_hp64<1, TAPS>(st, P, mode, blocks, hp, jph, pmode)
+                             : run_spec_hp64<0, TAPS>(st, P, mode, blocks, hp, jph, pmode);
   if (cols == 16)
     return pprec == SMR_FP32 ? run_spec_hp<1, 16, TAPS>(st, P, mode, blocks, hp, jph, pmode)
                              : run_spec_hp<0, 16, TAPS>(st, P, mode, blocks, hp, jph, pmode);

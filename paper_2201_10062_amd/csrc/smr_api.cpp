@@ -190,18 +190,20 @@ smr_status validate(const smr_desc *d) {
     return fail(SMR_EUNSUPPORTED, "pprec %d is not implemented", d->pprec);
   if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
     return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
-  const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 |
-                    SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16;
+  const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64 | SMR_FLAG_PINV_F64 |
+                    SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16;
   if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
   const int pinv_flags =
       d->flags & (SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16);
   if (pinv_flags & (pinv_flags - 1)) return fail(SMR_EINVAL, "at most one SMR_FLAG_PINV_* flag");
   if ((pinv_flags & (SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16)) && d->pprec != SMR_FP32)
     return fail(SMR_EINVAL, "float32 P^-1 intermediates need pprec SMR_FP32");
-  if ((d->flags & SMR_FLAG_TILE16) && (d->flags & SMR_FLAG_TILE32))
-    return fail(SMR_EINVAL, "SMR_FLAG_TILE16 and SMR_FLAG_TILE32 exclude each other");
+  const int tile_flags = d->flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64);
+  if (tile_flags & (tile_flags - 1)) return fail(SMR_EINVAL, "SMR_FLAG_TILE16/32/64 exclude each other");
   if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
     return fail(SMR_EUNSUPPORTED, "32-column tiles need ceil(n/2) <= 128 (got n = %d)", d->n);
+  if ((d->flags & SMR_FLAG_TILE64) && !spec_cols_ok(hp_of((d->n + 1) / 2), 64))
+    return fail(SMR_EUNSUPPORTED, "64-column tiles need ceil(n/2) <= 32 (got n = %d)", d->n);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
   if (d->ax_host && d->dim >= 2 && !d->ay_host) return fail(SMR_EINVAL, "dim %d face values need ay", d->dim);
@@ -395,7 +397,10 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.h1 = (d->n + 1) / 2;
   p.h2 = d->n / 2;
   p.hp = hp_of(p.h1);
-  p.spec_c = (d->flags & SMR_FLAG_TILE16) ? 16 : (d->flags & SMR_FLAG_TILE32) ? 32 : spec_cols_default(p.hp);
+  p.spec_c = (d->flags & SMR_FLAG_TILE16)   ? 16
+             : (d->flags & SMR_FLAG_TILE32) ? 32
+             : (d->flags & SMR_FLAG_TILE64) ? 64
+                                            : spec_cols_default(p.hp);
   p.ws_bytes = ws_bytes;
 
   const int N = p.N, n = p.n, m = p.m, dim = p.dim;
@@ -620,7 +625,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
     delete pl;
     return fail(SMR_EDEVICE, "setup upload failed: %s", hipGetErrorString(e));
   }
-  if (use_spectral(p) && !(p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32))) {
+  if (use_spectral(p) && !(p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64))) {
     e = spec_tune(&p, s);
     if (e != hipSuccess) {
       delete pl;
@@ -1355,7 +1360,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     std::vector<Group> groups;
     for (int i : spec_ids) {
       const Plan &p = plans[i]->p;
-      if (forced(p)) { cols[i] = p.spec_c; continue; }
+      if (forced(p) && p.spec_c != 64) { cols[i] = p.spec_c; continue; }
       if (!spec_cols_ok(p.hp, 32)) { cols[i] = 16; continue; }
       Group *g = nullptr;
       for (Group &h : groups)

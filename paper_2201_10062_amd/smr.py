@@ -114,16 +114,17 @@ def _check(st: int):
 FLAG_GENERAL_PATH = 1
 FLAG_TILE16 = 2
 FLAG_TILE32 = 4
+FLAG_TILE64 = 128
 PINV_FLAGS = {None: 0, "f64": 8, "f32": 16, "f32c16": 32, "f64c16": 64}
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
               ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
-    tile_cols: None (timed at setup), 16 or 32.  pinv: None (timed at setup), "f64", "f64c16",
+    tile_cols: None (timed at setup), 16, 32 or 64 (single solves, ceil(n/2) <= 32).  pinv: None (timed at setup), "f64", "f64c16",
     "f32" or "f32c16" (the physical-basis P^{-1} variant; the float32 ones for float32 plans)."""
-    if tile_cols not in (None, 16, 32):
-        raise ValueError(f"tile_cols must be None, 16 or 32 (got {tile_cols})")
+    if tile_cols not in (None, 16, 32, 64):
+        raise ValueError(f"tile_cols must be None, 16, 32 or 64 (got {tile_cols})")
     if pinv not in PINV_FLAGS:
         raise ValueError(f"pinv must be one of {list(PINV_FLAGS)} (got {pinv})")
     keep = []
@@ -137,7 +138,7 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
 
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
                 cheb_k=cheb_k, flags=(FLAG_GENERAL_PATH if general_path else 0)
-                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32}[tile_cols] | PINV_FLAGS[pinv], T=T, theta=theta,
+                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32, 64: FLAG_TILE64}[tile_cols] | PINV_FLAGS[pinv], T=T, theta=theta,
                 ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal), az_host=host(az))
     return d, keep
 
@@ -220,7 +221,7 @@ class Plan:
 
     @property
     def tile_cols(self) -> int:
-        """Column-tile width of the sine-basis solve (16 or 32), 0 on the physical-basis path."""
+        """Column-tile width of the sine-basis solve (16, 32 or 64), 0 on the physical-basis path."""
         c = ctypes.c_int32(0)
         _check(self.lib.smr_tile_cols(self.handle, ctypes.byref(c)))
         return c.value

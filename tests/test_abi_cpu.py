@@ -68,7 +68,7 @@ def test_tile_width_flags_checked_on_host():
     out = ctypes.c_size_t(0)
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     assert b"exclude" in lib.smr_last_error()
-    d.flags = 128                     # no such flag
+    d.flags = 256                     # no such flag
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     with pytest.raises(ValueError):
         smr.make_desc(2, 7, 4, tile_cols=24)

@@ -92,6 +92,8 @@ CASES = [
     (7, 40, "bdf4", 1.0, "const07", "PH", False, 32),
     (31, 16, "theta", 0.5, "const", "PH", False, 16),               # 1862 tiles: grouped partials
     (31, 16, "theta", 1.0, "const", "PTHETA_CHEB", False, 32),      # 931 tiles: direct
+    (31, 16, "theta", 0.5, "const", "PH", False, 64),               # 466 tiles of 64 modes
+    (63, 12, "bdf3", 1.0, "const07", "PH", False, 64),              # 3907 tiles of 64, 5 time taps
     (15, 12, "theta", 1.0, "var", "PH", False, None),               # physical basis, Kbar
     (15, 12, "theta", 0.5, "var", "PTHETA_CHEB", False, None),      # Chebyshev per mode
     (7, 10, "bdf3", 1.0, "var", "PH", False, None),

@@ -116,3 +116,32 @@ def test_batch_mixes_tile_widths():
         for p, x, info, ref in zip(probs, xs, infos, refs):
             assert info["status"] == "ok" and info["iters"] == ref.iters, (rep, p.name, info, ref.iters)
             assert rel(_n(x), ref.x) < 1e-9, (rep, p.name)
+
+
+@pytest.mark.parametrize("scheme,theta,N,n,pprec", [("theta", 0.5, 63, 64, "fp64"), ("bdf4", 1.0, 127, 40, "fp64"),
+                                                     ("bdf2", 1.0, 63, 64, "fp32")])
+def test_tile64_single_solves(scheme, theta, N, n, pprec):
+    """64-mode column tiles (single plans, ceil(n/2) <= 32): float64 equal to the oracle's
+    iterate to 1e-10 at its stopping iteration; float32 within the iteration bound."""
+    from paper_2201_10062_amd import Plan
+    _dev()
+    g = Plan(2, N, n, scheme=scheme, theta=theta, pprec=pprec, tile_cols=64)
+    assert g.tile_cols == 64
+    o = System(2, N, n, scheme=scheme, theta=theta)
+    b = np.random.default_rng(33).standard_normal(n * g.m)
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    x, info = g.solve(_t(b), rtol=1e-8, maxit=400)
+    assert info["status"] == "ok"
+    if pprec == "fp64":
+        assert info["iters"] == ref.iters
+        assert rel(_n(x), ref.x) < 1e-10
+    else:
+        assert info["iters"] <= int(1.1 * ref.iters) + 1
+        assert np.linalg.norm(b - o.apply_T(_n(x))) / np.linalg.norm(b) <= 1e-8
+
+
+def test_tile64_rejected_beyond_hp32():
+    from paper_2201_10062_amd import Plan, smr
+    _dev()
+    with pytest.raises(smr.SmrError, match="eunsupported"):
+        Plan(2, 15, 80, tile_cols=64)
