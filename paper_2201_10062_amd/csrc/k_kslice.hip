@@ -39,22 +39,46 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ int brev6(int l) { return (int)(__brev((unsigned)l) >> 26); }
 
-// Value of lane (lane ^ d).  Spans 1, 2, 4 and 8 stay inside a 16-lane row and use DPP moves
-// (quad_perm [1,0,3,2] and [2,3,0,1]; row_half_mirror then quad_perm [3,2,1,0], i.e. xor 7
-// then xor 3; row_ror:8); spans 16 and 32 go through the cross-lane permute.
+// Value of lane (lane ^ d) for spans 1, 2, 4 and 8, which stay inside a 16-lane row: DPP
+// moves (quad_perm [1,0,3,2] and [2,3,0,1]; row_half_mirror then quad_perm [3,2,1,0], i.e.
+// xor 7 then xor 3; row_ror:8).
 template <int D>
 __device__ __forceinline__ int xor_lane_i(int v) {
+  static_assert(D == 1 || D == 2 || D == 4 || D == 8, "spans 16 and 32 use pair_vals");
   if (D == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
   if (D == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
   if (D == 4) return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
-  if (D == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
-  return __shfl_xor(v, D, 64);
+  return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
 }
 template <int D>
 __device__ __forceinline__ double xor_lane(double x) {
   const long long u = __double_as_longlong(x);
   const int lo = xor_lane_i<D>((int)(u & 0xffffffff)), hi = xor_lane_i<D>((int)(u >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Spans 16 and 32: both values of the lane pair (l, l ^ D) on both lanes, a = the value of
+// the lower lane (l & D == 0), b = that of the upper one.  gfx950's permlane swaps do this in
+// registers: swapping a register with itself, rows 1 and 3 against rows 0 and 2 (span 16)
+// or lanes 32-63 against lanes 0-31 (span 32), leaves the lower lanes' values in the first
+// result and the upper lanes' values in the second, on every lane.
+template <int D>
+__device__ __forceinline__ void pair_vals(double x, double &a, double &b) {
+  static_assert(D == 16 || D == 32, "spans 16 and 32 only");
+  const long long u = __double_as_longlong(x);
+  const unsigned lo = (unsigned)(u & 0xffffffff), hi = (unsigned)(u >> 32);
+  unsigned alo, blo, ahi, bhi;
+  if constexpr (D == 32) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    alo = rl[0]; blo = rl[1]; ahi = rh[0]; bhi = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    alo = rl[0]; blo = rl[1]; ahi = rh[0]; bhi = rh[1];
+  }
+  a = __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo));
+  b = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
 }
 
 // W_M^t for 0 <= t < M from the half table tw[t] = exp(-2 pi i t / M), t < M/2
@@ -85,19 +109,35 @@ struct Twiddles {
   }
 };
 
-// One cross-lane stage of span D: all partner reads first, then (sg v + p) wm per value.
+// One cross-lane stage of span D: all exchanges first, then per value (sg v + p) wm with p
+// the partner's value (spans up to 8), or (a + sg b) wm with a, b the pair's lower and upper
+// values (spans 16 and 32); both are a + b on the lower lane and a - b on the upper one.
 template <int R, int D>
 __device__ __forceinline__ void dif_stage(double2 (&v)[R], double sg, double2 wm) {
   double2 p[R];
+  if constexpr (D >= 16) {
+    double2 q[R];
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) {
-    p[k1].x = xor_lane<D>(v[k1].x);
-    p[k1].y = xor_lane<D>(v[k1].y);
-  }
+    for (int k1 = 0; k1 < R; ++k1) {
+      pair_vals<D>(v[k1].x, p[k1].x, q[k1].x);
+      pair_vals<D>(v[k1].y, p[k1].y, q[k1].y);
+    }
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) {
-    const double tx = fma(sg, v[k1].x, p[k1].x), ty = fma(sg, v[k1].y, p[k1].y);
-    v[k1] = cmul(make_double2(tx, ty), wm);
+    for (int k1 = 0; k1 < R; ++k1) {
+      const double tx = fma(sg, q[k1].x, p[k1].x), ty = fma(sg, q[k1].y, p[k1].y);
+      v[k1] = cmul(make_double2(tx, ty), wm);
+    }
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      p[k1].x = xor_lane<D>(v[k1].x);
+      p[k1].y = xor_lane<D>(v[k1].y);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      const double tx = fma(sg, v[k1].x, p[k1].x), ty = fma(sg, v[k1].y, p[k1].y);
+      v[k1] = cmul(make_double2(tx, ty), wm);
+    }
   }
 }
 
