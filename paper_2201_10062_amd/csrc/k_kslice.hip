@@ -208,13 +208,37 @@ __device__ __forceinline__ void wave_dft(double2 (&v)[R], int lane, const Twiddl
   dif_stage<R, 1>(v, W.sg[5], W.wm[5]);
 }
 
-// Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS
-// (row pitch LP), in place; each wave takes pairs of lines.
-template <int R, int DIR, int NW = kKW>   // NW: waves of the block
+// A whole N x N level in LDS (N = 32 R - 1), skewed so that the transforms' scattered stores
+// spread over the banks: element (r, c) sits at r LP + (r >> 5) + c + (c >> 5), i.e. one pad
+// slot after every 32 columns and after every 32 rows, with the pitch LP = 1 mod 8.  One
+// store instruction of a wave's transform writes positions R b + k of a row or of a column
+// (fixed k, b = brev6(lane) over the 32 lanes with an output in range); with a plain pitch
+// these meet on the same banks 4 ways (R = 4) or 2 ways (R = 2) (64 banks of 4 bytes), with
+// the skew every lane has banks of its own.  R = 1 stores consecutive positions and keeps the
+// plain layout (pitch N + 2).
+template <int R>
+struct Lvl {
+  static constexpr int N = 32 * R - 1;
+  static constexpr bool SKEW = R > 1;
+  static constexpr int CP = SKEW ? (N - 1) + ((N - 1) >> 5) + 1 : N;   // slots of a row, pads included
+  static constexpr int LP = SKEW ? (CP + 6) / 8 * 8 + 1 : N + 2;       // skewed: smallest >= CP that is 1 mod 8
+  static constexpr int SIZE = SKEW ? (N - 1) * LP + ((N - 1) >> 5) + CP : N * LP;
+  __device__ static __forceinline__ int at(int r, int c) {
+    return SKEW ? r * LP + (r >> 5) + c + (c >> 5) : r * LP + c;
+  }
+};
+
+// Orthonormal DST-I of every row (DIR 0) or column (DIR 1) of the N x N level in LDS, in
+// place; each wave takes pairs of lines.  SKEW: the level layout above (LP unused); else the
+// row pitch LP.
+template <int R, int DIR, int NW = kKW, bool SKEW = false>   // NW: waves of the block
 __device__ __forceinline__ void dst_lines(double *X, int N, int nl, int LP, const Twiddles<R> &W, double scale,
                                           int wave, int lane) {
   constexpr int M = 64 * R, L = M / 2;
-  auto at = [&](int line, int pos) { return DIR == 0 ? line * LP + pos : pos * LP + line; };
+  auto at = [&](int line, int pos) {
+    if constexpr (SKEW) return DIR == 0 ? Lvl<R>::at(line, pos) : Lvl<R>::at(pos, line);
+    else return DIR == 0 ? line * LP + pos : pos * LP + line;
+  };
   const int npairs = (nl + 1) / 2;
   // odd-extension source position and sign of this lane's R values (independent of the pair)
   int srcp[R];
@@ -248,23 +272,23 @@ __device__ __forceinline__ void dst_lines(double *X, int N, int nl, int LP, cons
   }
 }
 
-// The same for all N lines of an N x N level.
+// The same for all N lines of an N x N level in the skewed layout.
 template <int R, int DIR>
-__device__ __forceinline__ void dst_level(double *X, int N, int LP, const Twiddles<R> &W, double scale, int wave,
-                                          int lane) {
-  dst_lines<R, DIR>(X, N, N, LP, W, scale, wave, lane);
+__device__ __forceinline__ void dst_level(double *X, const Twiddles<R> &W, double scale, int wave, int lane) {
+  dst_lines<R, DIR, kKW, true>(X, Lvl<R>::N, Lvl<R>::N, 0, W, scale, wave, lane);
 }
 
 // X <- U K(a) U X for the level in LDS (U applied as DST along rows, then columns).
 template <int R, int KMAX>
 __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int wave, int lane) {
-  const int N = K.N, LP = N + 2;
-  constexpr int NC = 32 * R - 1;   // = N (the launcher picks R = (N + 1) / 32): divisions by a constant
+  const int N = K.N;
+  constexpr int NC = Lvl<R>::N;   // = N (the launcher picks R = (N + 1) / 32): divisions by a constant
+  auto at = [](int r, int c) { return Lvl<R>::at(r, c); };
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(K.tw), lane);
-  dst_level<R, 0>(X, N, LP, W, K.scale, wave, lane);
+  dst_level<R, 0>(X, W, K.scale, wave, lane);
   __syncthreads();
-  dst_level<R, 1>(X, N, LP, W, K.scale, wave, lane);
+  dst_level<R, 1>(X, W, K.scale, wave, lane);
   __syncthreads();
   double kv[KMAX];
 #pragma unroll
@@ -273,11 +297,11 @@ __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int 
     kv[k] = 0.0;
     if (e < N * N) {
       const int j = e / NC, i = e - j * NC;
-      const double uc = X[j * LP + i];
-      const double uw = i > 0 ? X[j * LP + i - 1] : 0.0;
-      const double ue = i < N - 1 ? X[j * LP + i + 1] : 0.0;
-      const double us = j > 0 ? X[(j - 1) * LP + i] : 0.0;
-      const double un = j < N - 1 ? X[(j + 1) * LP + i] : 0.0;
+      const double uc = X[at(j, i)];
+      const double uw = i > 0 ? X[at(j, i - 1)] : 0.0;
+      const double ue = i < N - 1 ? X[at(j, i + 1)] : 0.0;
+      const double us = j > 0 ? X[at(j - 1, i)] : 0.0;
+      const double un = j < N - 1 ? X[at(j + 1, i)] : 0.0;
       const double aw = K.ax[j * (N + 1) + i], ae = K.ax[j * (N + 1) + i + 1];
       const double as = K.ay[j * N + i], an = K.ay[(j + 1) * N + i];
       kv[k] = K.h2inv * (aw * (uc - uw) + ae * (uc - ue) + as * (uc - us) + an * (uc - un));
@@ -289,13 +313,13 @@ __device__ __forceinline__ void uku_level(double *X, const KsP &K, int tid, int 
     const int e = tid + k * kKT;
     if (e < N * N) {
       const int j = e / NC, i = e - j * NC;
-      X[j * LP + i] = kv[k];
+      X[at(j, i)] = kv[k];
     }
   }
   __syncthreads();
-  dst_level<R, 0>(X, N, LP, W, K.scale, wave, lane);
+  dst_level<R, 0>(X, W, K.scale, wave, lane);
   __syncthreads();
-  dst_level<R, 1>(X, N, LP, W, K.scale, wave, lane);
+  dst_level<R, 1>(X, W, K.scale, wave, lane);
   __syncthreads();
 }
 
@@ -327,8 +351,9 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
   extern __shared__ double X[];
   __shared__ double red[4][kKW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int N = K.N, n = K.n, m = K.m, LP = N + 2;
-  constexpr int NC = 32 * R - 1;   // = N (the launcher picks R = (N + 1) / 32): divisions by a constant
+  const int n = K.n, m = K.m;
+  constexpr int NC = Lvl<R>::N;   // = K.N (the launcher picks R = (N + 1) / 32): divisions by a constant
+  auto at = [](int r, int c) { return Lvl<R>::at(r, c); };
   const size_t ld = (size_t)K.ld;
   const int j = jfull % 6;   // rotation phase of the z buffers
   bool do_res = false;
@@ -371,7 +396,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
         const int e = e0 + u * kKT;
         if (e >= m) break;
         const int jr = e / NC, ir = e - jr * NC;
-        X[jr * LP + ir] = b0 * a0[u] + b1 * a1[u];
+        X[at(jr, ir)] = b0 * a0[u] + b1 * a1[u];
       }
     }
     __syncthreads();
@@ -395,7 +420,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
         const int e = e0 + u * kKT;
         if (e >= m) break;
         const int jr = e / NC, ir = e - jr * NC;
-        double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[jr * LP + ir];
+        double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[at(jr, ir)];
         if (far) v += (s3 ? c3 * (double)s3[e] : 0.0) + (s4 ? c4 * (double)s4[e] : 0.0);
         q[e] = v;
         if (MODE == 1) acc_d += v * af[u];
@@ -424,7 +449,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
         const int e = e0 + u * kKT;
         if (e >= m) break;
         const int jr = e / NC, ir = e - jr * NC;
-        X[jr * LP + ir] = b0 * a0[u] + b1 * a1[u];
+        X[at(jr, ir)] = b0 * a0[u] + b1 * a1[u];
       }
     }
     __syncthreads();
@@ -435,7 +460,7 @@ __device__ __forceinline__ void ks_body(const KsP &K, int jfull, int t) {
       const double v2 = x2 ? x2[e] : 0.0;
       const double v34 = (x3 ? c3 * x3[e] : 0.0) + (x4 ? c4 * x4[e] : 0.0);
       const int jr = e / NC, ir = e - jr * NC;
-      const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2 + v34) - K.tau * X[jr * LP + ir];
+      const double r = bt[e] - (c0 * v0 + c1 * v1 + c2 * v2 + v34) - K.tau * X[at(jr, ir)];
       acc_r += r * r;
     }
   }
@@ -460,7 +485,7 @@ __global__ __launch_bounds__(kKT) void k_dst2d(const double *__restrict__ in, do
                                                const Scal *__restrict__ stop_gate) {
   if (stop_gate && stop_gate->status == RUNNING) return;
   extern __shared__ double X[];
-  constexpr int N = 32 * R - 1, LP = N + 2;
+  constexpr int N = Lvl<R>::N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double *src = in + (size_t)blockIdx.x * sin;
   for (int e0 = tid; e0 < N * N; e0 += kLB * kKT) {   // kLB elements' loads in flight
@@ -472,20 +497,20 @@ __global__ __launch_bounds__(kKT) void k_dst2d(const double *__restrict__ in, do
       const int e = e0 + u * kKT;
       if (e >= N * N) break;
       const int j = e / N, i = e - j * N;
-      X[j * LP + i] = a[u];
+      X[Lvl<R>::at(j, i)] = a[u];
     }
   }
   Twiddles<R> W;
   W.load(reinterpret_cast<const double2 *>(tw), lane);
   __syncthreads();
-  dst_level<R, 0>(X, N, LP, W, scale, wave, lane);
+  dst_level<R, 0>(X, W, scale, wave, lane);
   __syncthreads();
-  dst_level<R, 1>(X, N, LP, W, scale, wave, lane);
+  dst_level<R, 1>(X, W, scale, wave, lane);
   __syncthreads();
   double *dst = out + (size_t)blockIdx.x * sout;
   for (int e = tid; e < N * N; e += kKT) {
     const int j = e / N, i = e - j * N;
-    dst[e] = X[j * LP + i];
+    dst[e] = X[Lvl<R>::at(j, i)];
   }
 }
 
@@ -509,7 +534,7 @@ __global__ __launch_bounds__(kKT) void k_kslice_multi(const KsP *__restrict__ ta
 }
 
 template <int R, int PR>
-size_t ks_shmem() { return (size_t)(32 * R - 1) * (32 * R + 1) * sizeof(double); }
+size_t ks_shmem() { return (size_t)Lvl<R>::SIZE * sizeof(double); }
 
 template <int R, int PR>
 hipError_t run_ks(hipStream_t st, const KsP *K, const KsP *table, int ninst, int blocks, int mode, int jfull) {
@@ -872,7 +897,7 @@ bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L
 template <int R>
 static hipError_t run_dst2d(hipStream_t st, int n, const double *in, double *out, long sin, long sout,
                             const double *tw, const Scal *stop_gate) {
-  const size_t sh = (size_t)(32 * R - 1) * (32 * R + 1) * sizeof(double);
+  const size_t sh = (size_t)Lvl<R>::SIZE * sizeof(double);
   if (sh > 65536) lds_limit((const void *)k_dst2d<R>, sh);
   hipLaunchKernelGGL(k_dst2d<R>, dim3(n), dim3(kKT), sh, st, in, out, sin, sout, tw, 1.0 / sqrt(64.0 * R), stop_gate);
   return hipGetLastError();
