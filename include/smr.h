@@ -122,6 +122,18 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
 #define SMR_FLAG_PINV_F32 16
 #define SMR_FLAG_PINV_F32_COL16 32
 #define SMR_FLAG_PINV_F64_COL16 64
+/* Form of the per-level matvec U K(a) U of an N = 127 variable-coefficient 2D solve in the
+ * sine basis (Sec. 3.1.1: the spatial sine transform diagonalises the constant part; for a
+ * variable a each time level goes through U, the 5-point K(a) of eqn:matrix_Km_va, and U):
+ * MATVEC_LEVEL holds a whole level in LDS per workgroup (one workgroup per CU);
+ * MATVEC_TILES streams three passes over 16-line tiles (rows of the source, columns with the
+ * stencil, rows into (T z)^), with four level-sized intermediates in the workspace, so that
+ * several workgroups share a CU.  With neither set, smr_setup times both on the plan's
+ * workspace and keeps the tiled passes unless the level form is 3% faster, cached per device
+ * and shape; smr_matvec_tiles reports the choice.  Same arithmetic; only the grouping of the
+ * partial sums differs.  No effect on other plans.  At most one (else SMR_EINVAL). */
+#define SMR_FLAG_MATVEC_LEVEL 256
+#define SMR_FLAG_MATVEC_TILES 512
 
 typedef struct {
   int32_t dim;             /* spatial dimension, 1, 2 or 3                                */
@@ -182,6 +194,10 @@ smr_status smr_tile_cols(const smr_plan *plan, int32_t *cols);
  * column tiles; -1 for plans whose solves run in the sine basis or without a preconditioner.
  * Host only. */
 smr_status smr_pinv_variant(const smr_plan *plan, int32_t *variant);
+
+/* 1 when the plan's per-level matvec runs as tiled passes (see SMR_FLAG_MATVEC_TILES), else 0
+ * (level form, or a plan without that matvec).  Host only. */
+smr_status smr_matvec_tiles(const smr_plan *plan, int32_t *tiled);
 
 /* The autotuner's cache (host, process-wide): shapes timed so far (entries), and how many
  * set-ups and batched calls found their choice cached (hits) or timed it (misses).

@@ -39,6 +39,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ int brev6(int l) { return (int)(__brev((unsigned)l) >> 26); }
 
+// Workgroups go to the 8 XCDs round-robin in block order; give each XCD a contiguous range of
+// tiles instead, so that the tiles sharing cache lines (column tiles of one slice) meet in the
+// same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  constexpr int kXcd = 8;
+  const int x = bid % kXcd, local = bid / kXcd;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // Value of lane (lane ^ d) for spans 1, 2, 4 and 8, which stay inside a 16-lane row: DPP
 // moves (quad_perm [1,0,3,2] and [2,3,0,1]; row_half_mirror then quad_perm [3,2,1,0], i.e.
 // xor 7 then xor 3; row_ror:8).
@@ -136,7 +146,8 @@ __device__ __forceinline__ void dif_stage(double2 (&v)[R], double sg, double2 wm
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       const double tx = fma(sg, v[k1].x, p[k1].x), ty = fma(sg, v[k1].y, p[k1].y);
-      v[k1] = cmul(make_double2(tx, ty), wm);
+      // span 1: the upper lane's multiplier is W_2^0 = 1, so no lane multiplies
+      v[k1] = D == 1 ? make_double2(tx, ty) : cmul(make_double2(tx, ty), wm);
     }
   }
 }
@@ -566,6 +577,309 @@ hipError_t run_ks_r(hipStream_t st, int L, const KsP *K, const KsP *table, int n
   return hipErrorInvalidValue;
 }
 
+// ---- The per-level matvec at N = 127 as three streamed passes over line tiles.
+// U K(a) U s per level, with U = S_y S_x: (A) row transforms of the source, s = b0 z_t +
+// b1 z_{t-1}, into Y1; (B) per tile of 16 columns: the column transforms of those columns and
+// of one halo column on each side, the 5-point stencil K(a) on the 16, and their column
+// transforms back, into Y2; (C) row transforms of Y2, combined with the time stencil into
+// q_t = sum_r c_r z_{t-r} + tau (U K U s)_t, with the delta partial per tile.  A block holds
+// at most 18 lines (18.6 KB of LDS) instead of a whole level (139 KB), so several blocks
+// share a CU and one block's loads overlap another's transforms.  The true-residual chain
+// runs the same three passes on x in the same launches, through intermediates of its own,
+// when launch j-1's scalars ask for it.  Same arithmetic as
+// the level kernel; only the partial sums are grouped per tile (kKsTiles per level).
+constexpr int kKsN = 127, kKsLP = kKsN + 2;   // level size, LDS pitch of a line
+constexpr int kKsTT = 256;                     // threads per block: 4 waves
+constexpr int kKsTL = 16;                      // rows (passes A, C) or columns (pass B) per tile
+static_assert(kKsTiles * kKsTL >= kKsN && (kKsTiles - 1) * kKsTL < kKsN, "tiles cover a level");
+
+
+__device__ __forceinline__ double block_sum_tt(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kKsTT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Pass A: Y1_t = S_x (b0 s_t + b1 s_{t-1}) on rows [16 tile, 16 tile + 16) of level t; s = x
+// (MODE 0, residual chain) or z_j.
+template <int PR, int MODE, bool RES>
+__device__ __forceinline__ void ks_rows_in(const KsP &K, int jfull, int t, int tile, double *X, double *yout) {
+  typedef typename std::conditional<PR == 0 || MODE == 0 || RES, double, float>::type T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = tile * kKsTL, nl = min(kKsTL, kKsN - r0);
+  const size_t ld = (size_t)K.ld;
+  double tcs[5], kbs[2];
+  (void)scheme_coefs(K.scheme, K.theta, tcs, kbs);
+  const double b0 = kbs[0], b1 = kbs[1];
+  const T *s = MODE == 0 || RES ? reinterpret_cast<const T *>(K.x)
+                                : reinterpret_cast<const T *>(K.Z[((jfull % 6) + 2) % 3]);
+  const T *st = s + (size_t)t * ld + (size_t)r0 * kKsN;      // the tile's rows are contiguous
+  const T *s1 = t >= 1 ? st - ld : nullptr;
+  for (int e0 = tid; e0 < nl * kKsN; e0 += kLB * kKsTT) {
+    double a0[kLB], a1[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = min(e0 + u * kKsTT, nl * kKsN - 1);
+      a0[u] = (double)st[e];
+      a1[u] = s1 ? (double)s1[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kKsTT;
+      if (e >= nl * kKsN) break;
+      const int c = e / kKsN, i = e - c * kKsN;
+      X[c * kKsLP + i] = b0 * a0[u] + b1 * a1[u];
+    }
+  }
+  Twiddles<4> W;
+  W.load(reinterpret_cast<const double2 *>(K.tw), lane);
+  __syncthreads();
+  dst_lines<4, 0, kKsTT / 64>(X, kKsN, nl, kKsLP, W, K.scale, wave, lane);
+  __syncthreads();
+  double *y = yout + (size_t)t * ld + (size_t)r0 * kKsN;
+  for (int e = tid; e < nl * kKsN; e += kKsTT) {
+    const int c = e / kKsN, i = e - c * kKsN;
+    y[e] = X[c * kKsLP + i];
+  }
+}
+
+// Pass B: columns [16 tile, 16 tile + 16) of Y2_t = S_y K(a) S_y Y1_t (the halo columns
+// c0 - 1 and c1 are transformed as well, for the stencil's x neighbours).
+// X: (kKsTL + 2) lines of kKsLP (line = column, position = row).
+__device__ __forceinline__ void ks_cols(const KsP &K, int t, int tile, double *X, const double *yin, double *yout) {
+  constexpr int N = kKsN, LP = kKsLP;
+  constexpr int KV = (kKsTL * kKsN + kKsTT - 1) / kKsTT;   // stencil points per thread
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = tile * kKsTL, c1 = min(N, c0 + kKsTL), nin = c1 - c0;
+  const int cl = max(0, c0 - 1), ch = min(N, c1 + 1), nh = ch - cl;
+  const size_t ld = (size_t)K.ld;
+  const double *y1 = yin + (size_t)t * ld;
+  for (int e0 = tid; e0 < N * nh; e0 += kLB * kKsTT) {
+    double a[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = min(e0 + u * kKsTT, N * nh - 1);
+      const int r = e / nh, c = e - r * nh;
+      a[u] = y1[(size_t)r * N + cl + c];
+    }
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kKsTT;
+      if (e >= N * nh) break;
+      const int r = e / nh, c = e - r * nh;
+      X[c * LP + r] = a[u];
+    }
+  }
+  Twiddles<4> W;
+  W.load(reinterpret_cast<const double2 *>(K.tw), lane);
+  __syncthreads();
+  dst_lines<4, 0, kKsTT / 64>(X, N, nh, LP, W, K.scale, wave, lane);
+  __syncthreads();
+  // K(a) u on the tile's columns: u(r, c) = X[(c - cl) LP + r], zero beyond the boundary
+  double kv[KV];
+#pragma unroll
+  for (int k = 0; k < KV; ++k) {
+    const int e = tid + k * kKsTT;
+    kv[k] = 0.0;
+    if (e < nin * N) {
+      const int r = e / nin, c = c0 + (e - r * nin);
+      const double *xc = X + (c - cl) * LP;
+      const double uc = xc[r];
+      const double uw = c > 0 ? xc[r - LP] : 0.0;
+      const double ue = c < N - 1 ? xc[r + LP] : 0.0;
+      const double us = r > 0 ? xc[r - 1] : 0.0;
+      const double un = r < N - 1 ? xc[r + 1] : 0.0;
+      const double aw = K.ax[r * (N + 1) + c], ae = K.ax[r * (N + 1) + c + 1];
+      const double as = K.ay[r * N + c], an = K.ay[(r + 1) * N + c];
+      kv[k] = K.h2inv * (aw * (uc - uw) + ae * (uc - ue) + as * (uc - us) + an * (uc - un));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KV; ++k) {
+    const int e = tid + k * kKsTT;
+    if (e < nin * N) {
+      const int r = e / nin, c = e - r * nin;
+      X[c * LP + r] = kv[k];
+    }
+  }
+  __syncthreads();
+  dst_lines<4, 0, kKsTT / 64>(X, N, nin, LP, W, K.scale, wave, lane);
+  __syncthreads();
+  double *y2 = yout + (size_t)t * ld;
+  for (int e = tid; e < nin * N; e += kKsTT) {
+    const int r = e / nin, c = e - r * nin;
+    y2[(size_t)r * N + c0 + c] = X[c * LP + r];
+  }
+}
+
+// Pass C: rows [16 tile, 16 tile + 16) of S_x Y2_t, then q_t = sum_r c_r s_{t-r} + tau (.)
+// with the delta partial of the tile (source chain), or the tile's part of
+// ||b^ - (T x)^||^2 (residual chain).  Partials: 4 per (level, tile), [residual^2, residual
+// skipped, 0, delta]; the residual chain runs after the source chain and fills slot 0.
+template <int PR, int MODE, bool RES>
+__device__ __forceinline__ void ks_rows_out(const KsP &K, int jfull, int t, int tile, bool skipped, double *X,
+                                            double *red, const double *yin) {
+  typedef typename std::conditional<PR == 0 || MODE == 0 || RES, double, float>::type T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = tile * kKsTL, nl = min(kKsTL, kKsN - r0), ne = nl * kKsN;
+  const int n = K.n;
+  const size_t ld = (size_t)K.ld, o = (size_t)r0 * kKsN;
+  const double *y2 = yin + (size_t)t * ld + o;
+  for (int e = tid; e < ne; e += kKsTT) {
+    const int c = e / kKsN, i = e - c * kKsN;
+    X[c * kKsLP + i] = y2[e];
+  }
+  Twiddles<4> W;
+  W.load(reinterpret_cast<const double2 *>(K.tw), lane);
+  __syncthreads();
+  dst_lines<4, 0, kKsTT / 64>(X, kKsN, nl, kKsLP, W, K.scale, wave, lane);
+  __syncthreads();
+  double tcs[5], kbs[2];
+  const bool far = scheme_coefs(K.scheme, K.theta, tcs, kbs) > 3;   // levels t-3, t-4 enter (BDF3, BDF4)
+  const double c0 = tcs[0], c1 = tcs[1], c2 = tcs[2], c3 = tcs[3], c4 = tcs[4];
+  const T *s = MODE == 0 || RES ? reinterpret_cast<const T *>(K.x)
+                                : reinterpret_cast<const T *>(K.Z[((jfull % 6) + 2) % 3]);
+  const T *st = s + (size_t)t * ld + o;
+  const T *s1 = t >= 1 ? st - ld : nullptr;
+  const T *s2 = t >= 2 ? st - 2 * ld : nullptr;
+  const T *s3 = far && t >= 3 ? st - 3 * ld : nullptr;
+  const T *s4 = far && t >= 4 ? st - 4 * ld : nullptr;
+  double acc = 0.0;
+  if (!RES) {
+    double *q = K.q + (size_t)t * ld + o;
+    const T *sf = s + (size_t)(n - 1 - t) * ld + o;
+    for (int e0 = tid; e0 < ne; e0 += 4 * kKsTT) {   // four elements' loads in flight
+      double a0[4], a1[4], a2[4], af[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * kKsTT, ne - 1);
+        a0[u] = (double)st[e];
+        a1[u] = s1 ? (double)s1[e] : 0.0;
+        a2[u] = s2 ? (double)s2[e] : 0.0;
+        af[u] = MODE == 1 ? (double)sf[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kKsTT;
+        if (e >= ne) break;
+        const int c = e / kKsN, i = e - c * kKsN;
+        double v = c0 * a0[u] + c1 * a1[u] + c2 * a2[u] + K.tau * X[c * kKsLP + i];
+        if (far) v += (s3 ? c3 * (double)s3[e] : 0.0) + (s4 ? c4 * (double)s4[e] : 0.0);
+        q[e] = v;
+        if (MODE == 1) acc += v * af[u];
+      }
+    }
+  } else {
+    const double *bt = K.bh + (size_t)t * ld + o;
+    for (int e0 = tid; e0 < ne; e0 += 4 * kKsTT) {
+      double v0[4], v1[4], v2[4], v34[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * kKsTT, ne - 1);
+        v0[u] = (double)st[e];
+        v1[u] = s1 ? (double)s1[e] : 0.0;
+        v2[u] = s2 ? (double)s2[e] : 0.0;
+        v34[u] = (s3 ? c3 * (double)s3[e] : 0.0) + (s4 ? c4 * (double)s4[e] : 0.0);
+        bb[u] = bt[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kKsTT;
+        if (e >= ne) break;
+        const int c = e / kKsN, i = e - c * kKsN;
+        const double r = bb[u] - (c0 * v0[u] + c1 * v1[u] + c2 * v2[u] + v34[u]) - K.tau * X[c * kKsLP + i];
+        acc += r * r;
+      }
+    }
+  }
+  if (MODE == 0) return;
+  const double sum = block_sum_tt(acc, red);
+  if (tid == 0) {
+    double *pp = K.kpart + 4 * ((size_t)t * kKsTiles + tile);
+    if (RES) {
+      pp[0] = sum;
+    } else {
+      pp[0] = 0.0;
+      pp[1] = skipped ? 1.0 : 0.0;
+      pp[2] = 0.0;
+      pp[3] = sum;
+    }
+  }
+}
+
+// One pass on one tile: the source chain, then (MODE 1) the residual chain on x when the
+// scalars of launch j - 1 cannot exclude convergence (the level kernel's rule); MODE 0
+// (q = (T x0)^) has no residual.  Nothing runs once the solve has stopped.
+template <int PASS, int PR, int MODE>
+__device__ __forceinline__ void ks_pass(const KsP &K, int jfull, int t, int tile) {
+  __shared__ double X[(kKsTL + 2) * kKsLP];
+  __shared__ double red[kKsTT / 64];
+  bool do_res = false, skipped = false;
+  if (MODE == 1) {
+    const Scal *sprev = K.sc + (((jfull % 6) + 1) & 1);
+    if (sprev->status != RUNNING) return;
+    do_res = jfull >= 3 &&
+             (K.sqsigmin * fabs(sprev->eta) <= 2.0 * sprev->rtol * sprev->bnorm || sprev->iter >= sprev->maxit);
+    skipped = jfull >= 3 && !do_res;
+  }
+  // the source chain passes its intermediates through y[0], y[1], the residual chain through
+  // y[2], y[3] (both run in the same launches)
+  if (PASS == 0) ks_rows_in<PR, MODE, false>(K, jfull, t, tile, X, K.y[0]);
+  else if (PASS == 1) ks_cols(K, t, tile, X, K.y[0], K.y[1]);
+  else ks_rows_out<PR, MODE, false>(K, jfull, t, tile, skipped, X, red, K.y[1]);
+  if (MODE == 1 && do_res) {
+    __syncthreads();
+    if (PASS == 0) ks_rows_in<PR, MODE, true>(K, jfull, t, tile, X, K.y[2]);
+    else if (PASS == 1) ks_cols(K, t, tile, X, K.y[2], K.y[3]);
+    else ks_rows_out<PR, MODE, true>(K, jfull, t, tile, skipped, X, red, K.y[3]);
+  }
+}
+// Single plan: block (t, tile); batched: the table's instances, level blocks counted by blk0.
+template <int PASS, int PR, int MODE>
+__global__ __launch_bounds__(kKsTT) void k_ks_tiles(KsP K, int jfull) {
+  const int b = xcd_block(blockIdx.x, gridDim.x), t = b / kKsTiles;
+  ks_pass<PASS, PR, MODE>(K, jfull, t, b - t * kKsTiles);
+}
+template <int PASS, int PR, int MODE>
+__global__ __launch_bounds__(kKsTT) void k_ks_tiles_multi(const KsP *__restrict__ table, int ninst, int jfull) {
+  const int b = xcd_block(blockIdx.x, gridDim.x), g = b / kKsTiles;
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].blk0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const KsP &K = table[lo];
+  ks_pass<PASS, PR, MODE>(K, jfull, g - K.blk0, b - g * kKsTiles);
+}
+
+// The chain of one launch: passes A, B, C of the source, then (MODE 1) of the residual, whose
+// blocks exit at once unless launch j-1's scalars ask for it.  levels: grid / kKsTiles.
+// The three passes of one launch (levels: grid / kKsTiles).
+template <int PR, int MODE>
+hipError_t run_ks_chain(hipStream_t st, const KsP *K, const KsP *table, int ninst, int levels, int jfull) {
+  const dim3 g(levels * kKsTiles), blk(kKsTT);
+  if (K) {
+    hipLaunchKernelGGL((k_ks_tiles<0, PR, MODE>), g, blk, 0, st, *K, jfull);
+    hipLaunchKernelGGL((k_ks_tiles<1, PR, MODE>), g, blk, 0, st, *K, jfull);
+    hipLaunchKernelGGL((k_ks_tiles<2, PR, MODE>), g, blk, 0, st, *K, jfull);
+  } else {
+    hipLaunchKernelGGL((k_ks_tiles_multi<0, PR, MODE>), g, blk, 0, st, table, ninst, jfull);
+    hipLaunchKernelGGL((k_ks_tiles_multi<1, PR, MODE>), g, blk, 0, st, table, ninst, jfull);
+    hipLaunchKernelGGL((k_ks_tiles_multi<2, PR, MODE>), g, blk, 0, st, table, ninst, jfull);
+  }
+  return hipGetLastError();
+}
+template <int PR>
+hipError_t run_ks_split(hipStream_t st, const KsP *K, const KsP *table, int ninst, int levels, int mode, int jfull) {
+  return mode == 0 ? run_ks_chain<PR, 0>(st, K, table, ninst, levels, jfull)
+                   : run_ks_chain<PR, 1>(st, K, table, ninst, levels, jfull);
+}
+
 }  // namespace
 
 namespace {
@@ -586,16 +900,6 @@ struct TileP {
   const double *tw, *ez, *tmu_lap;
   int scale_mode;
 };
-
-// Workgroups go to the 8 XCDs round-robin in block order; give each XCD a contiguous range of
-// tiles instead, so that the tiles sharing cache lines (column tiles of one slice) meet in the
-// same L2.
-__device__ __forceinline__ int xcd_block(int bid, int nb) {
-  constexpr int kXcd = 8;
-  const int x = bid % kXcd, local = bid / kXcd;
-  const int per = nb / kXcd, rem = nb % kXcd;
-  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
-}
 
 // TI, TO: element types of the vectors in memory (float32 intermediates of a mixed-precision
 // P^{-1}); the tile in LDS and the FFT stay float64.
@@ -924,18 +1228,27 @@ KsP kslice_desc(const Plan *p, double *x, const double *bh) {
   const bool f32 = p->pprec == SMR_FP32;
   for (int i = 0; i < 3; ++i) K.Z[i] = f32 ? (const void *)p->ZF[i] : (const void *)(i == 0 ? p->Z[0] : i == 1 ? p->Z[1] : p->Q);
   K.x = x; K.bh = bh; K.q = p->QX; K.kpart = p->part + kKsPartOffset; K.sc = p->sc;
+  for (int i = 0; i < 4; ++i) K.y[i] = p->Y[i];
   return K;
 }
 
 hipError_t launch_kslice(Ctx c, int mode, int j, double *x, const double *bh) {
   const Plan *p = c.p;
   const KsP K = kslice_desc(p, x, bh);
+  if (p->ks_split)
+    return p->pprec == SMR_FP32 ? run_ks_split<1>(c.st, &K, nullptr, 1, p->n, mode, j)
+                                : run_ks_split<0>(c.st, &K, nullptr, 1, p->n, mode, j);
   return p->pprec == SMR_FP32 ? run_ks_r<1>(c.st, p->L, &K, nullptr, 1, p->n, mode, j)
                               : run_ks_r<0>(c.st, p->L, &K, nullptr, 1, p->n, mode, j);
 }
 
 hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int blocks, int L, int pprec, int mode,
-                               int j) {
+                               int j, bool split) {
+  if (split) {
+    if (L != kKsN + 1) return hipErrorInvalidValue;
+    return pprec == SMR_FP32 ? run_ks_split<1>(st, nullptr, table, ninst, blocks, mode, j)
+                             : run_ks_split<0>(st, nullptr, table, ninst, blocks, mode, j);
+  }
   return pprec == SMR_FP32 ? run_ks_r<1>(st, L, nullptr, table, ninst, blocks, mode, j)
                            : run_ks_r<0>(st, L, nullptr, table, ninst, blocks, mode, j);
 }

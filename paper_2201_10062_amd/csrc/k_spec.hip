@@ -80,7 +80,7 @@ SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   if (!p->const_coef) {
     P.qext = p->QX;
     P.kpart = p->part + kKsPartOffset;
-    P.nks = p->n;
+    P.nks = p->ks_split ? p->n * kKsTiles : p->n;
   }
   return P;
 }

@@ -191,8 +191,11 @@ smr_status validate(const smr_desc *d) {
   if (d->pprec == SMR_FP32 && d->precond == SMR_P_NONE)
     return fail(SMR_EINVAL, "float32 preconditioning needs a preconditioner (P = I has none)");
   const int known = SMR_FLAG_GENERAL_PATH | SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64 | SMR_FLAG_PINV_F64 |
-                    SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16;
+                    SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16 | SMR_FLAG_MATVEC_LEVEL |
+                    SMR_FLAG_MATVEC_TILES;
   if ((d->flags & ~known) != 0) return fail(SMR_EINVAL, "unknown flags 0x%x", d->flags);
+  if ((d->flags & SMR_FLAG_MATVEC_LEVEL) && (d->flags & SMR_FLAG_MATVEC_TILES))
+    return fail(SMR_EINVAL, "SMR_FLAG_MATVEC_LEVEL and SMR_FLAG_MATVEC_TILES exclude each other");
   const int pinv_flags =
       d->flags & (SMR_FLAG_PINV_F64 | SMR_FLAG_PINV_F32 | SMR_FLAG_PINV_F32_COL16 | SMR_FLAG_PINV_F64_COL16);
   if (pinv_flags & (pinv_flags - 1)) return fail(SMR_EINVAL, "at most one SMR_FLAG_PINV_* flag");
@@ -221,6 +224,10 @@ bool var_sine_basis(const smr_desc *d) {
   return d->dim == 2 && (L == 32 || L == 64 || L == 128) && d->precond == SMR_P_H &&
          !(d->flags & SMR_FLAG_GENERAL_PATH) && (d->ax_host || d->a_nodal_host);
 }
+
+// The N = 127 variable-coefficient sine-basis solve can also run its per-level matvec as
+// three passes over line tiles (four more level-sized intermediates in the workspace).
+bool ks_split_capable(const smr_desc *d) { return var_sine_basis(d) && d->N + 1 == 128; }
 
 // interior points and face values per axis array: m = N^dim; faces along one axis (N+1) N^(dim-1)
 size_t m_of(int dim, int N) { return dim == 1 ? (size_t)N : dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
@@ -268,7 +275,7 @@ Layout layout_of(const smr_desc *d) {
   l.sc = take(2 * sizeof(Scal));
   // V0 V1 Z0 Z1 W0 W1 Q T1 T2 G (+ T3 T4 for the Chebyshev inner solve, + QX for the
   // variable-coefficient sine-basis solve)
-  l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0) + (var_sine_basis(d) ? 1 : 0);
+  l.nvec = 10 + (d->precond == SMR_P_THETA_CHEB ? 2 : 0) + (var_sine_basis(d) ? 1 : 0) + (ks_split_capable(d) ? 4 : 0);
   l.vec0 = off;
   off += (size_t)l.nvec * align256(sizeof(double) * len);
   l.total = off;
@@ -332,6 +339,7 @@ int cu_count() {
 
 // Times the physical-basis P^{-1} variants of a float32 plan and sets p.pinv_var (defined below).
 smr_status pinv_tune(Plan &p, hipStream_t s);
+smr_status kslice_tune(Plan &p, hipStream_t s);
 
 // P_H / Phat (any a the sine-basis path takes), and P_theta of a constant a (its per-mode
 // blocks are diagonal in the spatial sine basis)
@@ -589,7 +597,7 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.part = (double *)(base_ptr + lay.part);
   p.sc = (Scal *)(base_ptr + lay.sc);
   const size_t vstride = align256(sizeof(double) * p.vlen);
-  double *vec[12] = {};
+  double *vec[16] = {};
   for (int i = 0; i < lay.nvec; ++i) vec[i] = (double *)(base_ptr + lay.vec0 + (size_t)i * vstride);
   p.V[0] = vec[0]; p.V[1] = vec[1];
   p.Z[0] = vec[2]; p.Z[1] = vec[3];
@@ -599,6 +607,8 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   p.T3 = cheb ? vec[10] : nullptr;
   p.T4 = cheb ? vec[11] : nullptr;
   p.QX = var_sine_basis(d) ? vec[lay.nvec - 1] : nullptr;
+  for (int i = 0; i < 4; ++i) p.Y[i] = ks_split_capable(d) ? vec[lay.nvec - 5 + i] : nullptr;
+  p.ks_split = false;
 
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s); };
   hipError_t e = hipSuccess;
@@ -624,6 +634,19 @@ smr_status smr_setup(const smr_desc *d, void *d_ws, size_t ws_bytes, void *strea
   if (e != hipSuccess) {
     delete pl;
     return fail(SMR_EDEVICE, "setup upload failed: %s", hipGetErrorString(e));
+  }
+  // the N = 127 per-level matvec: one level per block or three tiled passes, forced by a flag,
+  // else timed (before the fused kernel's width, whose variable-coefficient partial count
+  // depends on it)
+  if (p.Y[0] && use_spectral(p)) {
+    if (p.flags & SMR_FLAG_MATVEC_TILES) p.ks_split = true;
+    else if (!(p.flags & SMR_FLAG_MATVEC_LEVEL)) {
+      const smr_status ts = kslice_tune(p, s);
+      if (ts != SMR_OK) {
+        delete pl;
+        return ts;
+      }
+    }
   }
   if (use_spectral(p) && !(p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64))) {
     e = spec_tune(&p, s);
@@ -749,6 +772,31 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
 // spatial passes are bound by memory-instruction issue as much as by bytes), so a few
 // applications of each are timed on the plan's workspace and the fastest kept (variant 0
 // unless another is 3% faster).
+// Per-level matvec of an N = 127 variable-coefficient plan: time a few steady launches of each
+// form on the plan's workspace (a benign running scalar state in slot 0, which a launch with
+// j = 7 reads; the residual chain runs or not alike in both) and keep the tiled passes unless
+// the level kernel is 3% faster.  Cached per device and shape.
+smr_status kslice_tune(Plan &p, hipStream_t s) {
+  const std::vector<long> key{TUNE_KSLICE, p.dim, p.N, p.n, p.scheme, p.pprec};
+  int cached = 0;
+  if (tune_get(key, &cached)) {
+    p.ks_split = cached != 0;
+    return SMR_OK;
+  }
+  p.ks_split = false;
+  hipError_t e = spec_tune_state(&p, s, spec_desc(&p, p.T2, p.T1, p.spec_c));
+  float ms[2] = {0.0f, 0.0f};
+  for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    p.ks_split = v == 1;
+    Ctx c{&p, s};
+    e = tune_time(s, 3, [&]() { return launch_kslice(c, 1, 7, p.T2, p.T1); }, &ms[v]);
+  }
+  if (e != hipSuccess) return fail(SMR_EDEVICE, "timing the per-level matvec failed: %s", hipGetErrorString(e));
+  p.ks_split = !(ms[0] < 0.97f * ms[1]);
+  tune_put(key, p.ks_split ? 1 : 0);
+  return SMR_OK;
+}
+
 smr_status pinv_tune(Plan &p, hipStream_t s) {
   std::vector<int> cand{0};
   if (dst_tile_supported(&p)) cand.push_back(3);
@@ -1171,6 +1219,12 @@ smr_status smr_pinv_variant(const smr_plan *plan, int32_t *variant) {
   return SMR_OK;
 }
 
+smr_status smr_matvec_tiles(const smr_plan *plan, int32_t *tiled) {
+  if (!plan || !tiled) return fail(SMR_EINVAL, "plan and tiled must be non-NULL");
+  *tiled = plan->p.ks_split ? 1 : 0;
+  return SMR_OK;
+}
+
 smr_status smr_tune_stats(int64_t *entries, int64_t *hits, int64_t *misses) {
   if (!entries || !hits || !misses) return fail(SMR_EINVAL, "NULL argument");
   long e = 0, h = 0, m = 0;
@@ -1416,15 +1470,16 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     if (!plans[i]->p.const_coef) var_ids.push_back(i);
   std::stable_sort(var_ids.begin(), var_ids.end(), [&](int a, int c) {
     const Plan &pa = plans[a]->p, &pc = plans[c]->p;
-    return pa.L != pc.L ? pa.L < pc.L : pa.pprec < pc.pprec;
+    return pa.L != pc.L ? pa.L < pc.L : pa.pprec != pc.pprec ? pa.pprec < pc.pprec : pa.ks_split < pc.ks_split;
   });
-  struct KClass { int first, count, blocks, L, pprec; };
+  struct KClass { int first, count, blocks, L, pprec; bool split; };
   std::vector<KClass> kclasses;
   std::vector<KsP> ktable(var_ids.size());
   for (size_t k = 0; k < var_ids.size(); ++k) {
     const Plan &p = plans[var_ids[k]]->p;
-    if (kclasses.empty() || kclasses.back().L != p.L || kclasses.back().pprec != p.pprec)
-      kclasses.push_back(KClass{(int)k, 0, 0, p.L, p.pprec});
+    if (kclasses.empty() || kclasses.back().L != p.L || kclasses.back().pprec != p.pprec ||
+        kclasses.back().split != p.ks_split)
+      kclasses.push_back(KClass{(int)k, 0, 0, p.L, p.pprec, p.ks_split});
     KClass &cl = kclasses.back();
     ktable[k] = kslice_desc(&p, p.T2, p.T1);
     ktable[k].blk0 = cl.blocks;
@@ -1456,7 +1511,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     // (T x0)^ is needed only for a given guess (zero-guess instances ignore it)
     if (any_guess_ext)
       for (const KClass &cl : kclasses)
-        LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0));
+        LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 0, 0, cl.split));
     for (const Class &cl : classes)
       LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps, 0, 0));
     // one iteration j: the per-level matvec of every N class, then the fused launch of every
@@ -1506,7 +1561,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     auto iteration_par = [&](hipStream_t cs, int j) -> hipError_t {
       hipError_t e = phase(cs, (int)kclasses.size(), [&](hipStream_t st, int c) {
         const KClass &cl = kclasses[c];
-        return launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j);
+        return launch_kslice_multi(st, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j, cl.split);
       });
       if (e == hipSuccess)
         e = phase(cs, (int)classes.size(), [&](hipStream_t st, int c) {
@@ -1547,7 +1602,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
         for (int it = 0; it < todo; ++it) {
           const int j = issued + it + 1;
           for (const KClass &cl : kclasses)
-            LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j));
+            LAUNCH(PROF_KSLICE, launch_kslice_multi(s, d_ks + cl.first, cl.count, cl.blocks, cl.L, cl.pprec, 1, j, cl.split));
           for (const Class &cl : classes)
             LAUNCH(PROF_SPEC, launch_spec_multi(s, d_table + cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps,
                                                 j == 1 ? 1 : 2, j));

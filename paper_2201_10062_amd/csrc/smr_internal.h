@@ -18,6 +18,7 @@ constexpr int kMaxN3 = 127;      // N + 1 <= 128 in 3D (the stencil's spatial ti
 constexpr int kMaxn = 1024;
 constexpr int kRedSlots = 8192;  // partial sums per reduction (grid-stride kernels use <= this many blocks)
 constexpr size_t kKsPartOffset = 8 * (size_t)kRedSlots;   // per-level partials of the sine-basis matvec
+constexpr int kKsTiles = 8;      // row / column tiles per level of the tiled N = 127 matvec (16 lines each)
 // Above this many column tiles, a fused launch's partial sums are first reduced by kPartGroups
 // blocks (one fixed group of tiles each) instead of being re-read in full by every block of
 // the next launch.
@@ -94,6 +95,8 @@ struct Plan {
   // vectors (device), each vlen doubles (physical-basis use: stride m; sine basis: stride ld)
   double *V[2], *Z[2], *W[2], *Q, *T1, *T2, *T3, *T4, *G;
   double *QX;                 // (T z)^ of the variable-coefficient sine-basis solve (or null)
+  double *Y[4];               // level intermediates of the tiled N = 127 matvec (or null)
+  bool ks_split;              // N = 127 matvec as three passes over line tiles, not one level per block
   double *gface;              // 2 (N+1)^2 face-gradient scratch
   float *ZF[3];               // float32 z vectors of the mixed-precision sine-basis solve
   double *part;               // >= 16 * kRedSlots partial sums (more when the fused kernel's
@@ -204,7 +207,8 @@ struct KsP {
   const void *Z[3];      // z rotation of the fused kernel (the transform's precision)
   const double *x, *bh;  // iterate and right-hand side (sine basis)
   double *q;             // out: (T s)^
-  double *kpart;         // out: 4 partial sums per time level
+  double *kpart;         // out: 4 partial sums per time level (per level and tile when tiled)
+  double *y[4];          // intermediates of the tiled N = 127 passes (source chain, residual chain)
   const Scal *sc;
 };
 bool kslice_supported(const Plan *p);
@@ -222,8 +226,9 @@ KsP kslice_desc(const Plan *p, double *x, const double *bh);
 // mode 0: q = (T x)^ before the initialising launch; mode 1: q = (T z_j)^ with its partials
 // before fused launch j
 hipError_t launch_kslice(Ctx c, int mode, int j, double *x, const double *bh);
+// split: the class runs the tiled N = 127 passes (levels = blocks of the level kernel).
 hipError_t launch_kslice_multi(hipStream_t st, const KsP *table, int ninst, int blocks, int L, int pprec, int mode,
-                               int j);
+                               int j, bool split = false);
 
 // INIT (mode 0) also writes the starting scalar state (rtol, maxit) and, with x0zero, x = 0.
 hipError_t launch_spec(Ctx c, int mode, int j, double *x, const double *bh, bool x0zero = false,
@@ -255,7 +260,7 @@ void tune_clear();
 // One warm call of run, then reps timed calls on st (HIP events); ms per call.  Synchronises st.
 hipError_t tune_time(hipStream_t st, int reps, const std::function<hipError_t()> &run, float *ms_per_call);
 // Cache keys (first element) of the tuned choices.
-enum TuneKind : long { TUNE_SPEC_WIDTH = 1, TUNE_PINV = 2, TUNE_BATCH_WIDTH = 3 };
+enum TuneKind : long { TUNE_SPEC_WIDTH = 1, TUNE_PINV = 2, TUNE_BATCH_WIDTH = 3, TUNE_KSLICE = 4 };
 // The scalar state and partial sums of a running steady iteration that never converges, for
 // timing fused launches on a plan's workspace (k_spec.hip).
 hipError_t spec_tune_state(const Plan *p, hipStream_t st, const SpecP &P);

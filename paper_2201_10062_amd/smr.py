@@ -28,7 +28,7 @@ EXPORTS = (
     "smr_workspace_size", "smr_setup", "smr_destroy", "smr_build_rhs", "smr_apply_A", "smr_apply_P_inv",
     "smr_minres_solve", "smr_batch_workspace_size", "smr_minres_solve_batched", "smr_solve_adjoint", "smr_solve_adjoint_batched", "smr_rhs_adjoint", "smr_grad_a",
     "smr_profile_enable", "smr_profile_read", "smr_version", "smr_last_error", "smr_tile_cols",
-    "smr_apply_P_inv_static", "smr_pinv_variant", "smr_tune_stats", "smr_tune_reset",
+    "smr_apply_P_inv_static", "smr_pinv_variant", "smr_tune_stats", "smr_tune_reset", "smr_matvec_tiles",
 )
 STATIC_SCRATCH_BYTES = 64 << 20   # SMR_STATIC_SCRATCH_BYTES
 PROFILE_CLASSES = {"time": 0, "dst": 1, "stencil": 2, "vec": 3, "scalar": 4, "spec": 5, "kslice": 6}
@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
     lib.smr_destroy.argtypes = [P]
     lib.smr_tile_cols.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.smr_pinv_variant.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.smr_matvec_tiles.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.smr_tune_stats.argtypes = [ctypes.POINTER(ctypes.c_int64)] * 3
     lib.smr_tune_reset.argtypes = []
     lib.smr_build_rhs.argtypes = [P, P, P, P, P]
@@ -116,17 +117,21 @@ FLAG_TILE16 = 2
 FLAG_TILE32 = 4
 FLAG_TILE64 = 128
 PINV_FLAGS = {None: 0, "f64": 8, "f32": 16, "f32c16": 32, "f64c16": 64}
+MATVEC_FLAGS = {None: 0, "level": 256, "tiles": 512}
 
 
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
-              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None):
+              ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None, matvec=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
     tile_cols: None (timed at setup), 16, 32 or 64 (single solves, ceil(n/2) <= 32).  pinv: None (timed at setup), "f64", "f64c16",
-    "f32" or "f32c16" (the physical-basis P^{-1} variant; the float32 ones for float32 plans)."""
+    "f32" or "f32c16" (the physical-basis P^{-1} variant; the float32 ones for float32 plans).
+    matvec: None (timed at setup), "level" or "tiles" (form of the N = 127 per-level matvec)."""
     if tile_cols not in (None, 16, 32, 64):
         raise ValueError(f"tile_cols must be None, 16, 32 or 64 (got {tile_cols})")
     if pinv not in PINV_FLAGS:
         raise ValueError(f"pinv must be one of {list(PINV_FLAGS)} (got {pinv})")
+    if matvec not in MATVEC_FLAGS:
+        raise ValueError(f"matvec must be one of {list(MATVEC_FLAGS)} (got {matvec})")
     keep = []
 
     def host(a):
@@ -138,7 +143,8 @@ def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="
 
     d = SmrDesc(dim=dim, N=N, n=n, scheme=SCHEMES[scheme], precond=PRECONDS[precond], pprec=PPRECS[pprec],
                 cheb_k=cheb_k, flags=(FLAG_GENERAL_PATH if general_path else 0)
-                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32, 64: FLAG_TILE64}[tile_cols] | PINV_FLAGS[pinv], T=T, theta=theta,
+                | {None: 0, 16: FLAG_TILE16, 32: FLAG_TILE32, 64: FLAG_TILE64}[tile_cols] | PINV_FLAGS[pinv]
+                | MATVEC_FLAGS[matvec], T=T, theta=theta,
                 ax_host=host(ax), ay_host=host(ay), a_nodal_host=host(a_nodal), az_host=host(az))
     return d, keep
 
@@ -190,7 +196,8 @@ class Plan:
 
     def __init__(self, dim: int, N: int, n: int, scheme: str = "theta", theta: float = 1.0, T: float = 1.0,
                  precond: str = "PH", pprec: str = "fp64", cheb_k: int = 3, ax=None, ay=None, a_nodal=None,
-                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None, az=None, pinv=None):
+                 device="cuda", general_path: bool = False, tile_cols=None, workspace=None, az=None, pinv=None,
+                 matvec=None):
         """ax, ay, az: face values (az with dim 3 only); a_nodal: nodal values (dim 1, 2).
         workspace: a uint8 device tensor to build the plan in (e.g. the ``raw_workspace``
         of a plan that is no longer used); a new one is allocated when it is None or too small."""
@@ -202,7 +209,7 @@ class Plan:
         self.precond, self.pprec = precond, pprec
         self.device = torch.device(device)
         d, keep = make_desc(dim, N, n, scheme, theta, T, precond, pprec, cheb_k, ax, ay, a_nodal, general_path,
-                            tile_cols, az, pinv)
+                            tile_cols, az, pinv, matvec)
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
@@ -233,6 +240,13 @@ class Plan:
         c = ctypes.c_int32(0)
         _check(self.lib.smr_pinv_variant(self.handle, ctypes.byref(c)))
         return {0: "f64", 1: "f32", 2: "f32c16", 3: "f64c16"}.get(c.value)
+
+    @property
+    def matvec_tiles(self) -> bool:
+        """True when the per-level matvec runs as tiled passes (N = 127, variable a, sine basis)."""
+        c = ctypes.c_int32(0)
+        _check(self.lib.smr_matvec_tiles(self.handle, ctypes.byref(c)))
+        return c.value == 1
 
     @property
     def raw_workspace(self):

@@ -68,7 +68,7 @@ def test_tile_width_flags_checked_on_host():
     out = ctypes.c_size_t(0)
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     assert b"exclude" in lib.smr_last_error()
-    d.flags = 256                     # no such flag
+    d.flags = 1024                    # no such flag
     assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     with pytest.raises(ValueError):
         smr.make_desc(2, 7, 4, tile_cols=24)
@@ -103,6 +103,29 @@ def test_pinv_flags_checked_on_host():
     assert pkg.load().smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
     with pytest.raises(ValueError):
         smr.make_desc(2, 7, 4, pinv="bf16")
+
+
+def test_matvec_flags_checked_on_host():
+    """The N = 127 variable-coefficient sine-basis plan holds four more level-sized vectors (for
+    the tiled per-level matvec); the two forms exclude each other; other plans are unchanged."""
+    ax, ay = np.full((127, 128), 1.3), np.full((128, 127), 1.3)
+    ax[3, 4] = 1.7
+    base = smr.workspace_size(dim=2, N=127, n=16, scheme="bdf2", ax=ax, ay=ay)
+    const = smr.workspace_size(dim=2, N=127, n=16, scheme="bdf2")
+    assert base > const
+    assert smr.workspace_size(dim=2, N=127, n=16, scheme="bdf2", ax=ax, ay=ay, matvec="level") == base
+    assert smr.workspace_size(dim=2, N=127, n=16, scheme="bdf2", ax=ax, ay=ay, matvec="tiles") == base
+    assert smr.workspace_size(dim=2, N=63, n=16, matvec="tiles") == smr.workspace_size(dim=2, N=63, n=16)
+    d, keep = smr.make_desc(2, 127, 16, ax=ax, ay=ay)
+    d.flags = smr.MATVEC_FLAGS["level"] | smr.MATVEC_FLAGS["tiles"]
+    out = ctypes.c_size_t(0)
+    lib = pkg.load()
+    assert lib.smr_workspace_size(ctypes.byref(d), ctypes.byref(out)) == smr.SMR_EINVAL
+    assert b"exclude" in lib.smr_last_error()
+    with pytest.raises(ValueError):
+        smr.make_desc(2, 7, 4, matvec="fft")
+    t = ctypes.c_int32(-1)
+    assert lib.smr_matvec_tiles(None, ctypes.byref(t)) == smr.SMR_EINVAL
 
 
 def test_tune_stats_on_host():
