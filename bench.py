@@ -142,7 +142,8 @@ def batch_algorithmic(probs, infos, pprec_bytes):
     return spec_b, ks_b, ks_f
 
 
-def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, profiled_only: bool = False):
+def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, profiled_only: bool = False,
+                          matvec=None):
     """The 64-instance BDF2 batch (uneven N in {31, 63, 127}, n in {64, 128, 256}, a = 1 or
     1 + 0.5 cos(pi x), b ~ N(0, 1), seed 2), inputs resident in HBM.  Mixed + batched (float64
     MINRES, matvec and residual; float32 time transform and z; every iteration one per-level
@@ -157,7 +158,8 @@ def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, 
     probs = W.bdf2_batch()
     bs = [torch.from_numpy(q.b.reshape(-1)).to(dev) for q in probs]
     plain = [] if profiled_only else [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, device=dev) for q in probs]
-    mixed = [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, pprec="fp32", device=dev) for q in probs]
+    mixed = [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, pprec="fp32", device=dev, matvec=matvec)
+             for q in probs]
     batch = Batch(mixed)
 
     def run_plain():
@@ -217,7 +219,9 @@ def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, 
                  "bytes_per_launch": spec_b / max(n_spec // steps, 1), "kernel_ms_per_solve": ms_spec / steps}
     roof_ks = {"bound": "alu", "achieved": ks_tf, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                "frac": ks_tf / PEAK_FP64_VALU_TFLOPS, "traffic": None,
-               "kernel": "k_kslice_multi (per-level U K(a) U matvec, every N class)",
+               "kernel": "per-level U K(a) U matvec, every N class: k_kslice_multi (a level per block) or, "
+                         "where timed faster, k_ks_tiles_multi (three passes over 16-line tiles, N = 127)",
+               "tiled_instances": sum(pl.matvec_tiles for pl in mixed),
                "launches": n_ks // steps, "avg_launch_us": ms_ks * 1e3 / max(n_ks, 1),
                "flops_per_launch": ks_f / max(n_ks // steps, 1), "kernel_ms_per_solve": ms_ks / steps,
                "hbm_achieved_gbs": ks_gbs, "hbm_frac": ks_gbs / PEAK_HBM_GBS}
@@ -536,6 +540,9 @@ def main() -> int:
                          "and differentiable legs)")
     ap.add_argument("--profiled-pass-only", action="store_true",
                     help="only the headline's profiled pass (warm-up + the timed steps with per-launch events)")
+    ap.add_argument("--matvec", choices=["level", "tiles"], default=None,
+                    help="with --profiled-pass-only: force the form of the N = 127 per-level matvec (default: "
+                         "the one the set-up timing keeps; the counter runs profile each form this way)")
     ap.add_argument("--only-cn2d", action="store_true",
                     help="only the 2D Crank-Nicolson leg (for profiling its fused kernel)")
     ap.add_argument("--only-varcoef", action="store_true",
@@ -575,7 +582,7 @@ def main() -> int:
         return 0
     if args.profiled_pass_only:
         print(json.dumps(batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=False,
-                                               profiled_only=True)), flush=True)
+                                               profiled_only=True, matvec=args.matvec)), flush=True)
         return 0
     head = batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=not args.no_cpu)
     print(f"headline done: {head['ms_per_step']:.1f} ms per batch solve", file=sys.stderr, flush=True)
