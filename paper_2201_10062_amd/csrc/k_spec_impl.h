@@ -602,12 +602,22 @@ hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode,
   return hipErrorInvalidValue;
 }
 
-// 64-column tiles (single plans with hp <= 32, where a block's fixed costs weigh most)
+// 64-column tiles (hp <= 32, where a block's fixed costs weigh most)
 template <int PR, int TAPS>
 hipError_t run_spec_hp64(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
     case 16: return run_spec<16, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
     case 32: return run_spec<32, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+template <int PR, int TAPS>
+hipError_t run_multi_hp64(hipStream_t st, const SpecP *table, int ninst, int mode, int blocks, int hp, int jph,
+                          int pmode) {
+  switch (hp) {
+    case 16: return run_spec_multi<16, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
+    case 32: return run_spec_multi<32, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -633,6 +643,9 @@ hipError_t run_one_taps(hipStream_t st, const SpecP &P, int pprec, int cols, int
 template <int TAPS>
 hipError_t run_multi_taps(hipStream_t st, const SpecP *table, int ninst, int blocks, int hp, int cols, int pprec,
                           int mode, int jph, int pmode) {
+  if (cols == 64)
+    return pprec == SMR_FP32 ? run_multi_hp64<1, TAPS>(st, table, ninst, mode, blocks, hp, jph, pmode)
+                             : run_multi_hp64<0, TAPS>(st, table, ninst, mode, blocks, hp, jph, pmode);
   if (cols == 16)
     return pprec == SMR_FP32 ? run_multi_hp<1, 16, TAPS>(st, table, ninst, mode, blocks, hp, jph, pmode)
                              : run_multi_hp<0, 16, TAPS>(st, table, ninst, mode, blocks, hp, jph, pmode);

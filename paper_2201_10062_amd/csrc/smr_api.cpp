@@ -1359,15 +1359,17 @@ smr_status check_distinct_plans(int count, const smr_plan *const *plans) {
   return SMR_OK;
 }
 
-// Times one steady fused launch of a group of batch instances at each column-tile width (on
+// Times steady fused launches of a group of batch instances at each column-tile width (on
 // their own workspaces, from a running state that never converges, through the batch's
-// descriptor table) and returns the faster: 32 unless 16 is at least 5% faster.
+// descriptor table) and returns the fastest: 32 unless 16 (or 64, for hp <= 32) is at least
+// 5% faster.
 smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const std::vector<int> &ids, int hp,
                             int pprec, int taps, SpecP *d_table, int *width) {
-  const int cand[2] = {32, 16};
-  float best[2] = {1e30f, 1e30f};
+  const int cand[3] = {32, 16, 64};
+  const int ncand = spec_cols_ok(hp, 64) ? 3 : 2;
+  float best[3] = {1e30f, 1e30f, 1e30f};
   std::vector<SpecP> t(ids.size());
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < ncand; ++k) {
     int blocks = 0;
     for (size_t q = 0; q < ids.size(); ++q) {
       const Plan &p = plans[ids[q]]->p;
@@ -1383,7 +1385,10 @@ smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const s
       return launch_spec_multi(s, d_table, (int)ids.size(), blocks, hp, cand[k], pprec, taps, 2, 7);
     }, &best[k]));
   }
-  *width = best[1] < 0.95f * best[0] ? 16 : 32;
+  int arg = 0;
+  for (int k = 1; k < ncand; ++k)
+    if (best[k] < 0.95f * best[0] && best[k] < best[arg]) arg = k;
+  *width = cand[arg];
   return SMR_OK;
 }
 
@@ -1406,7 +1411,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
   // any of this call's data enters them.
   std::vector<int> cols(count, 0);
   {
-    auto forced = [](const Plan &p) { return (p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32)) != 0; };
+    auto forced = [](const Plan &p) { return (p.flags & (SMR_FLAG_TILE16 | SMR_FLAG_TILE32 | SMR_FLAG_TILE64)) != 0; };
     struct Group {
       int hp, pprec, taps;
       std::vector<int> ids;
@@ -1414,7 +1419,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     std::vector<Group> groups;
     for (int i : spec_ids) {
       const Plan &p = plans[i]->p;
-      if (forced(p) && p.spec_c != 64) { cols[i] = p.spec_c; continue; }
+      if (forced(p)) { cols[i] = p.spec_c; continue; }
       if (!spec_cols_ok(p.hp, 32)) { cols[i] = 16; continue; }
       Group *g = nullptr;
       for (Group &h : groups)

@@ -145,3 +145,35 @@ def test_tile64_rejected_beyond_hp32():
     _dev()
     with pytest.raises(smr.SmrError, match="eunsupported"):
         Plan(2, 15, 80, tile_cols=64)
+
+
+def test_tile64_batched_classes():
+    """Batched launches with 64-mode column tiles (every instance has ceil(n/2) <= 32):
+    constant and variable a, BDF2 beside BDF3 (3- and 5-tap classes in separate batches), a
+    class of 64-mode tiles beside a class of 32; every instance equals the oracle."""
+    from paper_2201_10062_amd import Batch, Plan
+    _dev()
+    probs = W.bdf2_batch(count=9, Ns=(15, 31, 63), ns=(16, 40, 64))
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, tile_cols=64 if i % 2 == 0 else 32)
+             for i, p in enumerate(probs)]
+    assert {pl.tile_cols for pl in plans} == {32, 64}
+    xs, infos = Batch(plans).solve([_t(p.b) for p in probs], rtol=1e-8)
+    for p, x, info in zip(probs, xs, infos):
+        ref = System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay).solve(p.b.reshape(-1), rtol=1e-8, maxit=600)
+        assert info["status"] == "ok" and info["iters"] == ref.iters, (p.name, info, ref.iters)
+        assert rel(_n(x), ref.x) < 1e-10, p.name
+    # 5 time taps (BDF3) in a batch of their own, float64 and float32
+    rng = np.random.default_rng(34)
+    shapes = [(31, 20, "fp64"), (63, 24, "fp64"), (31, 30, "fp32")]
+    plans5 = [Plan(2, N, n, scheme="bdf3", tile_cols=64, pprec=pp) for N, n, pp in shapes]
+    bs = [rng.standard_normal(n * N * N) for N, n, _ in shapes]
+    xs, infos = Batch(plans5).solve([_t(b) for b in bs], rtol=1e-8)
+    for (N, n, pp), b, x, info in zip(shapes, bs, xs, infos):
+        o = System(2, N, n, scheme="bdf3")
+        ref = o.solve(b, rtol=1e-8, maxit=600)
+        assert info["status"] == "ok", (N, n, pp, info)
+        if pp == "fp64":
+            assert info["iters"] == ref.iters and rel(_n(x), ref.x) < 1e-10, (N, n)
+        else:
+            assert info["iters"] <= int(1.1 * ref.iters) + 1
+            assert np.linalg.norm(b - o.apply_T(_n(x))) / np.linalg.norm(b) <= 1e-8
