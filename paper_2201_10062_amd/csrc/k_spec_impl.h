@@ -602,12 +602,13 @@ hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode,
   return hipErrorInvalidValue;
 }
 
-// 64-column tiles (hp <= 32, where a block's fixed costs weigh most)
+// 64-column tiles (hp <= 64, where a block's fixed costs weigh most)
 template <int PR, int TAPS>
 hipError_t run_spec_hp64(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
     case 16: return run_spec<16, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
     case 32: return run_spec<32, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
+    case 64: return run_spec<64, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
     default: break;
   }
   return hipErrorInvalidValue;
@@ -618,6 +619,7 @@ hipError_t run_multi_hp64(hipStream_t st, const SpecP *table, int ninst, int mod
   switch (hp) {
     case 16: return run_spec_multi<16, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
     case 32: return run_spec_multi<32, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
+    case 64: return run_spec_multi<64, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
     default: break;
   }
   return hipErrorInvalidValue;

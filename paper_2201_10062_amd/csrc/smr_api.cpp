@@ -206,7 +206,7 @@ smr_status validate(const smr_desc *d) {
   if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
     return fail(SMR_EUNSUPPORTED, "32-column tiles need ceil(n/2) <= 128 (got n = %d)", d->n);
   if ((d->flags & SMR_FLAG_TILE64) && !spec_cols_ok(hp_of((d->n + 1) / 2), 64))
-    return fail(SMR_EUNSUPPORTED, "64-column tiles need ceil(n/2) <= 32 (got n = %d)", d->n);
+    return fail(SMR_EUNSUPPORTED, "64-column tiles need ceil(n/2) <= 64 (got n = %d)", d->n);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
   if (d->ax_host && d->dim >= 2 && !d->ay_host) return fail(SMR_EINVAL, "dim %d face values need ay", d->dim);
@@ -1361,7 +1361,7 @@ smr_status check_distinct_plans(int count, const smr_plan *const *plans) {
 
 // Times steady fused launches of a group of batch instances at each column-tile width (on
 // their own workspaces, from a running state that never converges, through the batch's
-// descriptor table) and returns the fastest: 32 unless 16 (or 64, for hp <= 32) is at least
+// descriptor table) and returns the fastest: 32 unless 16 (or 64, for hp <= 64) is at least
 // 5% faster.
 smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const std::vector<int> &ids, int hp,
                             int pprec, int taps, SpecP *d_table, int *width) {
