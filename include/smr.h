@@ -103,7 +103,8 @@ typedef enum { SMR_FP64 = 0, SMR_FP32 = 1, SMR_BF16 = 2 } smr_pprec;
  * tiles pay off when the spatial grid is small; with ceil(n/2) <= 64 a 64-mode tile is a
  * third candidate, for large grids with few time levels); the choice is cached per device
  * and shape (see smr_tune_stats); batched calls time each class of instances the same way.
- * 32 needs ceil(n/2) <= 128 and 64 (SMR_FLAG_TILE64) ceil(n/2) <= 64 (SMR_EUNSUPPORTED otherwise);
+ * 32 needs ceil(n/2) <= 128 and 64 (SMR_FLAG_TILE64) ceil(n/2) <= 64, or <= 128 with SMR_FP32
+ * (SMR_EUNSUPPORTED otherwise);
  * ceil(n/2) > 128 always takes 16.  The width changes only the summation order of the
  * reductions.  Setting more than one of the three bits is SMR_EINVAL. */
 #define SMR_FLAG_TILE16 2

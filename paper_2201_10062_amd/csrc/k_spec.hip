@@ -56,7 +56,11 @@ int spec_cols(const Plan *p) { return p->spec_c; }
 
 int spec_cols_default(int hp) { return hp >= 256 ? 16 : 32; }
 
-bool spec_cols_ok(int hp, int cols) { return cols == 16 || (cols == 32 && hp <= 128) || (cols == 64 && hp <= 64); }
+// 64-mode tiles at hp = 128 only with float32 transforms (two 128 x 65 float32 blocks in LDS;
+// the float64 instance would hold one block per CU and spill)
+bool spec_cols_ok(int hp, int cols, int pprec) {
+  return cols == 16 || (cols == 32 && hp <= 128) || (cols == 64 && (hp <= 64 || (hp == 128 && pprec == SMR_FP32)));
+}
 
 SpecP spec_desc(const Plan *p, double *x, const double *bh, int cols) {
   SpecP P{};
@@ -174,9 +178,9 @@ hipError_t spec_tune(Plan *p, hipStream_t st) {
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMemsetAsync(p->ZF[i], 0, sizeof(float) * p->vlen, st);
   if (e != hipSuccess) return e;
   // a steady launch with j = 7 reads scalar and partial slot 0 and writes slot 1, so repeated
-  // launches all start from the same state; 64-column tiles are a candidate at hp <= 64
+  // launches all start from the same state; 64-column tiles are a candidate at hp <= 64 (128 with float32 transforms)
   const int cand[3] = {32, 16, 64};
-  const int ncand = spec_cols_ok(p->hp, 64) ? 3 : 2;
+  const int ncand = spec_cols_ok(p->hp, 64, p->pprec) ? 3 : 2;
   float best[3] = {1e30f, 1e30f, 1e30f};
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
     for (int k = 0; k < ncand && e == hipSuccess; ++k) {

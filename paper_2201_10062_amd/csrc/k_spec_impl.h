@@ -602,7 +602,7 @@ hipError_t run_multi_hp(hipStream_t st, const SpecP *table, int ninst, int mode,
   return hipErrorInvalidValue;
 }
 
-// 64-column tiles (hp <= 64, where a block's fixed costs weigh most)
+// 64-column tiles (hp <= 64, or 128 with float32 transforms: fewer blocks pay the fixed costs)
 template <int PR, int TAPS>
 hipError_t run_spec_hp64(hipStream_t st, const SpecP &P, int mode, int blocks, int hp, int jph, int pmode) {
   switch (hp) {
@@ -611,6 +611,8 @@ hipError_t run_spec_hp64(hipStream_t st, const SpecP &P, int mode, int blocks, i
     case 64: return run_spec<64, 64, PR, TAPS>(st, P, mode, blocks, jph, pmode);
     default: break;
   }
+  if constexpr (PR == 1)
+    if (hp == 128) return run_spec<128, 64, 1, TAPS>(st, P, mode, blocks, jph, pmode);
   return hipErrorInvalidValue;
 }
 template <int PR, int TAPS>
@@ -622,6 +624,8 @@ hipError_t run_multi_hp64(hipStream_t st, const SpecP *table, int ninst, int mod
     case 64: return run_spec_multi<64, 64, PR, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
     default: break;
   }
+  if constexpr (PR == 1)
+    if (hp == 128) return run_spec_multi<128, 64, 1, TAPS>(st, table, ninst, mode, blocks, jph, pmode);
   return hipErrorInvalidValue;
 }
 

@@ -205,8 +205,8 @@ smr_status validate(const smr_desc *d) {
   if (tile_flags & (tile_flags - 1)) return fail(SMR_EINVAL, "SMR_FLAG_TILE16/32/64 exclude each other");
   if ((d->flags & SMR_FLAG_TILE32) && !spec_cols_ok(hp_of((d->n + 1) / 2), 32))
     return fail(SMR_EUNSUPPORTED, "32-column tiles need ceil(n/2) <= 128 (got n = %d)", d->n);
-  if ((d->flags & SMR_FLAG_TILE64) && !spec_cols_ok(hp_of((d->n + 1) / 2), 64))
-    return fail(SMR_EUNSUPPORTED, "64-column tiles need ceil(n/2) <= 64 (got n = %d)", d->n);
+  if ((d->flags & SMR_FLAG_TILE64) && !spec_cols_ok(hp_of((d->n + 1) / 2), 64, d->pprec))
+    return fail(SMR_EUNSUPPORTED, "64-column tiles need ceil(n/2) <= 64, or <= 128 with SMR_FP32 (got n = %d)", d->n);
   const int forms = (d->ax_host != nullptr) + (d->a_nodal_host != nullptr);
   if (forms > 1) return fail(SMR_EINVAL, "give face values or nodal values of a, not both");
   if (d->ax_host && d->dim >= 2 && !d->ay_host) return fail(SMR_EINVAL, "dim %d face values need ay", d->dim);
@@ -1361,12 +1361,12 @@ smr_status check_distinct_plans(int count, const smr_plan *const *plans) {
 
 // Times steady fused launches of a group of batch instances at each column-tile width (on
 // their own workspaces, from a running state that never converges, through the batch's
-// descriptor table) and returns the fastest: 32 unless 16 (or 64, for hp <= 64) is at least
+// descriptor table) and returns the fastest: 32 unless 16 (or 64, for hp <= 64, or 128 in float32) is at least
 // 5% faster.
 smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const std::vector<int> &ids, int hp,
                             int pprec, int taps, SpecP *d_table, int *width) {
   const int cand[3] = {32, 16, 64};
-  const int ncand = spec_cols_ok(hp, 64) ? 3 : 2;
+  const int ncand = spec_cols_ok(hp, 64, pprec) ? 3 : 2;
   float best[3] = {1e30f, 1e30f, 1e30f};
   std::vector<SpecP> t(ids.size());
   for (int k = 0; k < ncand; ++k) {

@@ -245,7 +245,7 @@ hipError_t launch_gather_scal(hipStream_t st, const SpecP *table, int ninst, int
 // for hp <= 128 only (two 32-column LDS blocks of 256 rows do not fit).
 int spec_cols(const Plan *p);
 int spec_cols_default(int hp);
-bool spec_cols_ok(int hp, int cols);
+bool spec_cols_ok(int hp, int cols, int pprec = SMR_FP64);
 // Times one steady launch per width on the plan's (still empty) work vectors and stores the
 // faster width in p->spec_c; synchronises st.
 hipError_t spec_tune(Plan *p, hipStream_t st);

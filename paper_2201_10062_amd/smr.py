@@ -123,7 +123,7 @@ MATVEC_FLAGS = {None: 0, "level": 256, "tiles": 512}
 def make_desc(dim, N, n, scheme="theta", theta=1.0, T=1.0, precond="PH", pprec="fp64", cheb_k=3,
               ax=None, ay=None, a_nodal=None, general_path=False, tile_cols=None, az=None, pinv=None, matvec=None):
     """Build an SmrDesc; returns (desc, keepalive) where keepalive holds the host arrays.
-    tile_cols: None (timed at setup), 16, 32 or 64 (ceil(n/2) <= 64).  pinv: None (timed at setup), "f64", "f64c16",
+    tile_cols: None (timed at setup), 16, 32 or 64 (ceil(n/2) <= 64, or 128 with pprec="fp32").  pinv: None (timed at setup), "f64", "f64c16",
     "f32" or "f32c16" (the physical-basis P^{-1} variant; the float32 ones for float32 plans).
     matvec: None (timed at setup), "level" or "tiles" (form of the N = 127 per-level matvec)."""
     if tile_cols not in (None, 16, 32, 64):

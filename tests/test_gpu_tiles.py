@@ -120,7 +120,8 @@ def test_batch_mixes_tile_widths():
 
 @pytest.mark.parametrize("scheme,theta,N,n,pprec", [("theta", 0.5, 63, 64, "fp64"), ("bdf4", 1.0, 127, 40, "fp64"),
                                                      ("bdf2", 1.0, 63, 64, "fp32"), ("theta", 1.0, 31, 128, "fp64"),
-                                                     ("bdf3", 1.0, 63, 100, "fp64"), ("bdf2", 1.0, 63, 128, "fp32")])
+                                                     ("bdf3", 1.0, 63, 100, "fp64"), ("bdf2", 1.0, 63, 128, "fp32"),
+                                                     ("theta", 0.5, 31, 256, "fp32"), ("bdf2", 1.0, 127, 200, "fp32")])
 def test_tile64_single_solves(scheme, theta, N, n, pprec):
     """64-mode column tiles (single plans, ceil(n/2) <= 64): float64 equal to the oracle's
     iterate to 1e-10 at its stopping iteration; float32 within the iteration bound."""
@@ -142,10 +143,32 @@ def test_tile64_single_solves(scheme, theta, N, n, pprec):
 
 
 def test_tile64_rejected_beyond_hp64():
+    """64-mode tiles: ceil(n/2) <= 64 in float64, <= 128 with float32 transforms."""
     from paper_2201_10062_amd import Plan, smr
     _dev()
     with pytest.raises(smr.SmrError, match="eunsupported"):
         Plan(2, 15, 160, tile_cols=64)
+    assert Plan(2, 15, 160, tile_cols=64, pprec="fp32").tile_cols == 64
+    with pytest.raises(smr.SmrError, match="eunsupported"):
+        Plan(2, 15, 300, tile_cols=64, pprec="fp32")
+
+
+def test_tile64_batched_fp32_hp128():
+    """Float32 batched launches with 64-mode tiles at ceil(n/2) = 128 beside 32-mode ones
+    (parity unpinned by rounding): every instance reaches the tolerance with the float64 true
+    residual, within 10% (+1) of the float64 oracle's iterations."""
+    from paper_2201_10062_amd import Batch, Plan
+    _dev()
+    probs = W.bdf2_batch(count=18, Ns=(31, 63, 127), ns=(200, 256))
+    plans = [Plan(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay, pprec="fp32", tile_cols=64 if i % 2 == 0 else 32)
+             for i, p in enumerate(probs)]
+    xs, infos = Batch(plans).solve([_t(p.b) for p in probs], rtol=1e-8)
+    for p, x, info in zip(probs, xs, infos):
+        o = System(2, p.N, p.n, scheme="bdf2", ax=p.ax, ay=p.ay)
+        ref = o.solve(p.b.reshape(-1), rtol=1e-8, maxit=600)
+        r = np.linalg.norm(p.b.reshape(-1) - o.apply_T(_n(x))) / np.linalg.norm(p.b)
+        assert info["status"] == "ok" and r <= 1e-8, (p.name, info)
+        assert info["iters"] <= int(1.1 * ref.iters) + 1, (p.name, info["iters"], ref.iters)
 
 
 def test_tile64_batched_classes():
