@@ -55,15 +55,20 @@ def kernel_hash(files=("k_spec.hip", "k_spec_impl.h", "mfma_tiles.h")) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_entry(path=TRAFFIC_FILE):
+def traffic_entry(path=TRAFFIC_FILE, widths=None):
     """HBM bytes per launch of a kernel from a committed rocprofv3 --pmc summary, or None when
-    the kernel's source changed since the counters were taken."""
+    the kernel's source changed since the counters were taken or when the column-tile widths
+    this run launched with (`widths`: one width, or {time padding: width} per batch class)
+    differ from those of the counter run (the autotuner may choose differently in another
+    process, e.g. under the profiler)."""
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    if widths is not None and t.get("tile_cols") != widths:
         return None
     return t.get("bytes_per_launch")
 
@@ -142,8 +147,16 @@ def batch_algorithmic(probs, infos, pprec_bytes):
     return spec_b, ks_b, ks_f
 
 
+def time_padding(n: int) -> int:
+    """The fused kernel's folded time rows: ceil(n/2) rounded up to 16 * 2^k."""
+    hp = 16
+    while hp < (n + 1) // 2:
+        hp *= 2
+    return hp
+
+
 def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, profiled_only: bool = False,
-                          matvec=None):
+                          matvec=None, class_widths=None):
     """The 64-instance BDF2 batch (uneven N in {31, 63, 127}, n in {64, 128, 256}, a = 1 or
     1 + 0.5 cos(pi x), b ~ N(0, 1), seed 2), inputs resident in HBM.  Mixed + batched (float64
     MINRES, matvec and residual; float32 time transform and z; every iteration one per-level
@@ -158,8 +171,9 @@ def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, 
     probs = W.bdf2_batch()
     bs = [torch.from_numpy(q.b.reshape(-1)).to(dev) for q in probs]
     plain = [] if profiled_only else [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, device=dev) for q in probs]
-    mixed = [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, pprec="fp32", device=dev, matvec=matvec)
-             for q in probs]
+    cw = class_widths or {}
+    mixed = [Plan(2, q.N, q.n, scheme="bdf2", ax=q.ax, ay=q.ay, pprec="fp32", device=dev, matvec=matvec,
+                  tile_cols=cw.get(str(time_padding(q.n)))) for q in probs]
     batch = Batch(mixed)
 
     def run_plain():
@@ -207,13 +221,19 @@ def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, 
     it_m, it_p = sum(i["iters"] for i in im), sum(i["iters"] for i in ip)
     ratio = max(b["iters"] / a["iters"] for a, b in zip(ip, im) if a["iters"] > 0)
     spec_b, ks_b, ks_f = batch_algorithmic(probs, im, 4)
+    # the column-tile width each time-size class ran with (keyed by ceil(n/2) padded to 16 * 2^k)
+    class_widths = {}
+    for q, i in zip(probs, im):
+        if i["tile_cols"]:
+            class_widths[str(time_padding(q.n))] = i["tile_cols"]
     spec_s = ms_spec * 1e-3 / steps
     ks_s = ms_ks * 1e-3 / steps
     spec_gbs = spec_b / spec_s / 1e9
     ks_gbs = ks_b / ks_s / 1e9
     ks_tf = ks_f / ks_s / 1e12
     roof_spec = {"bound": "hbm", "achieved": spec_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                 "frac": spec_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(TRAFFIC_FILE_BATCH),
+                 "frac": spec_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(TRAFFIC_FILE_BATCH, class_widths),
+                 "class_widths": class_widths,
                  "kernel": "k_spec_multi (fused batched MINRES iteration, every time-size class)",
                  "launches": n_spec // steps, "avg_launch_us": ms_spec * 1e3 / max(n_spec, 1),
                  "bytes_per_launch": spec_b / max(n_spec // steps, 1), "kernel_ms_per_solve": ms_spec / steps}
@@ -256,7 +276,7 @@ def batched_bdf2_headline(dev, warmup: int, steps: int, rtol: float, cpu: bool, 
     return rec
 
 
-def cn2d_leg(dev, warmup: int, steps: int, rtol: float):
+def cn2d_leg(dev, warmup: int, steps: int, rtol: float, tile_cols=None):
     """The 2D Crank-Nicolson workload (N = 127, n = 256, a = 1, noisy source, seed 0, P_H),
     plain float64, one solve per step; the fused sine-basis iteration kernel timed with HIP
     events and priced against the HBM roofline (its two folded time GEMMs against the FP64
@@ -267,7 +287,7 @@ def cn2d_leg(dev, warmup: int, steps: int, rtol: float):
     p = W.crank_nicolson_2d_noisy()          # N = 127, n = 256, theta = 1/2, seed 0
     f = torch.from_numpy(p.f.reshape(-1)).to(dev)
     u0 = torch.from_numpy(p.u0).to(dev)
-    plan = Plan(2, p.N, p.n, theta=p.theta, device=dev)
+    plan = Plan(2, p.N, p.n, theta=p.theta, device=dev, tile_cols=tile_cols)
     b = plan.empty()
 
     def step():
@@ -306,7 +326,8 @@ def cn2d_leg(dev, warmup: int, steps: int, rtol: float):
            "iters_per_s": sum(iters) / dt, "time_to_1e-8_ms": dt / steps * 1e3, "iters_per_solve": iters[-1],
            "residuals_evaluated_per_solve": infos[-1]["res_evals"], "relres_true": infos[-1]["relres_true"],
            "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(),
+                        "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic_entry(widths=plan.tile_cols),
+                        "tile_cols": plan.tile_cols,
                         "kernel": "k_spec (fused sine-basis MINRES iteration)", "launches": n_spec,
                         "launches_expected": sum(k + 2 for k in iters), "avg_launch_us": avg_launch_s * 1e6,
                         "bytes_per_launch": bytes_per_launch},
@@ -417,7 +438,8 @@ def paper_tables_leg(dev, reps: int = 3):
                 bpl = spec_fp64_bytes([pinfo], dof) / max(nl, 1)
                 gbs = bpl / (msl / max(nl, 1) * 1e-3) / 1e9
                 e["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                 "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_entry(TRAFFIC_FILE_3D),
+                                 "frac": gbs / PEAK_HBM_GBS,
+                                 "traffic": traffic_entry(TRAFFIC_FILE_3D, g.tile_cols),
                                  "kernel": "k_spec + grouped partial reduction (3D, 4D sine basis)",
                                  "launches": nl, "avg_launch_us": msl / max(nl, 1) * 1e3, "bytes_per_launch": bpl,
                                  "tile_cols": g.tile_cols}
@@ -540,6 +562,14 @@ def main() -> int:
                          "and differentiable legs)")
     ap.add_argument("--profiled-pass-only", action="store_true",
                     help="only the headline's profiled pass (warm-up + the timed steps with per-launch events)")
+    ap.add_argument("--tile-cols", type=int, choices=[16, 32, 64], default=None,
+                    help="with --only-cn2d: force the fused kernel's column-tile width (default: the set-up "
+                         "timing's choice; the counter runs fix it so that they profile the width the bench "
+                         "normally launches)")
+    ap.add_argument("--class-widths", default=None,
+                    help="with --profiled-pass-only: force the column-tile width of each time-size class, "
+                         "e.g. 32:64,64:64,128:32 (time padding:width; the headline's own choice is printed in "
+                         "its roofline as class_widths, and the counter runs repeat it)")
     ap.add_argument("--matvec", choices=["level", "tiles"], default=None,
                     help="with --profiled-pass-only: force the form of the N = 127 per-level matvec (default: "
                          "the one the set-up timing keeps; the counter runs profile each form this way)")
@@ -572,7 +602,7 @@ def main() -> int:
                           "bytes_read": nel * 8, "bytes_written": nel * 8}), flush=True)
         return 0
     if args.only_cn2d:
-        print(json.dumps({"cn2d": cn2d_leg(dev, args.warmup, args.steps, args.rtol)}), flush=True)
+        print(json.dumps({"cn2d": cn2d_leg(dev, args.warmup, args.steps, args.rtol, args.tile_cols)}), flush=True)
         return 0
     if args.only_varcoef:
         print(json.dumps({"variable_coefficient": variable_coef_leg(dev, args.rtol, oracle=False)}), flush=True)
@@ -581,8 +611,10 @@ def main() -> int:
         print(json.dumps({"paper_tables_largest": paper_tables_leg(dev)}), flush=True)
         return 0
     if args.profiled_pass_only:
+        cw = dict(kv.split(":") for kv in args.class_widths.split(",")) if args.class_widths else None
+        cw = {k: int(v) for k, v in cw.items()} if cw else None
         print(json.dumps(batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=False,
-                                               profiled_only=True, matvec=args.matvec)), flush=True)
+                                               profiled_only=True, matvec=args.matvec, class_widths=cw)), flush=True)
         return 0
     head = batched_bdf2_headline(dev, args.warmup, args.steps, args.rtol, cpu=not args.no_cpu)
     print(f"headline done: {head['ms_per_step']:.1f} ms per batch solve", file=sys.stderr, flush=True)

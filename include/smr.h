@@ -173,7 +173,8 @@ typedef struct {
   int32_t res_evals;       /* true residuals evaluated (the initial one included); the
                               sine-basis path skips those that sqrt(min sigma) |eta| proves
                               to exceed the tolerance                                     */
-  int32_t reserved;
+  int32_t tile_cols;       /* column-tile width of the fused sine-basis launches the solve ran
+                              with (a batch class's timed width; 0 on the physical-basis path) */
 } smr_info;
 
 /* Bytes of device workspace needed by a plan for `desc` (Sec. 3.1.1: O(nm) storage). */

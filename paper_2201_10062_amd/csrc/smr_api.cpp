@@ -856,7 +856,7 @@ smr_status from_sine_basis(const Plan &p, hipStream_t s, const double *in, doubl
   return spatial_dst(p, s, in, out, p.ld, p.m);
 }
 
-smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
+smr_status finish_info(const Scal &h, int maxit, smr_info *info, int tile_cols = 0) {
   smr_status res = SMR_OK;
   switch (h.status) {
     case DONE_CONV: res = SMR_OK; break;
@@ -870,7 +870,7 @@ smr_status finish_info(const Scal &h, int maxit, smr_info *info) {
     info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
     info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
     info->res_evals = h.nres;
-    info->reserved = 0;
+    info->tile_cols = tile_cols;
   }
   return res;
 }
@@ -1129,7 +1129,7 @@ smr_status minres_spectral(const Plan &p, hipStream_t s, const double *b, const 
     if (st != SMR_OK) return st;
   }
   HIP_TRY(hipStreamSynchronize(s));
-  return finish_info(h, maxit, info);
+  return finish_info(h, maxit, info, p.spec_c);
 }
 
 const double *scal_field(const Plan &p, size_t off) { return (const double *)((const char *)p.sc + off); }
@@ -1203,7 +1203,7 @@ smr_status minres(const Plan &p, hipStream_t s, const double *b, const double *x
     info->relres_true = h.bnorm == 0.0 ? 0.0 : h.relres;
     info->relres_prec = h.gamma1 > 0.0 ? std::fabs(h.eta) / h.gamma1 : 0.0;
     info->res_evals = h.iter + 1;      // the physical-basis iteration evaluates every one
-    info->reserved = 0;
+    info->tile_cols = 0;
   }
   return res;
 }
@@ -1369,21 +1369,26 @@ smr_status batch_width_tune(hipStream_t s, const smr_plan *const *plans, const s
   const int ncand = spec_cols_ok(hp, 64, pprec) ? 3 : 2;
   float best[3] = {1e30f, 1e30f, 1e30f};
   std::vector<SpecP> t(ids.size());
-  for (int k = 0; k < ncand; ++k) {
-    int blocks = 0;
-    for (size_t q = 0; q < ids.size(); ++q) {
-      const Plan &p = plans[ids[q]]->p;
-      t[q] = spec_desc(&p, p.T2, p.T1, cand[k]);
-      t[q].rtiles = 0;
-      t[q].tile0 = blocks;
-      blocks += t[q].tiles;
-      HIP_TRY(spec_tune_state(&p, s, t[q]));
+  // three interleaved rounds, the fastest of each width kept (steadier than one round)
+  for (int rep = 0; rep < 3; ++rep) {
+    for (int k = 0; k < ncand; ++k) {
+      int blocks = 0;
+      for (size_t q = 0; q < ids.size(); ++q) {
+        const Plan &p = plans[ids[q]]->p;
+        t[q] = spec_desc(&p, p.T2, p.T1, cand[k]);
+        t[q].rtiles = 0;
+        t[q].tile0 = blocks;
+        blocks += t[q].tiles;
+        HIP_TRY(spec_tune_state(&p, s, t[q]));
+      }
+      HIP_TRY(hipMemcpyAsync(d_table, t.data(), sizeof(SpecP) * t.size(), hipMemcpyHostToDevice, s));
+      // a steady launch with j = 7 reads slot 0 and writes slot 1: repeated launches start alike
+      float ms = 0.0f;
+      HIP_TRY(tune_time(s, 4, [&]() {
+        return launch_spec_multi(s, d_table, (int)ids.size(), blocks, hp, cand[k], pprec, taps, 2, 7);
+      }, &ms));
+      best[k] = std::min(best[k], ms);
     }
-    HIP_TRY(hipMemcpyAsync(d_table, t.data(), sizeof(SpecP) * t.size(), hipMemcpyHostToDevice, s));
-    // a steady launch with j = 7 reads slot 0 and writes slot 1: repeated launches start alike
-    HIP_TRY(tune_time(s, 4, [&]() {
-      return launch_spec_multi(s, d_table, (int)ids.size(), blocks, hp, cand[k], pprec, taps, 2, 7);
-    }, &best[k]));
   }
   int arg = 0;
   for (int k = 1; k < ncand; ++k)
@@ -1655,7 +1660,7 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
         smr_status st = from_sine_basis(p, s, p.T2, x[i]);
         if (st != SMR_OK) return st;
       }
-      smr_status st = finish_info(hs[k], maxit, &infos[i]);
+      smr_status st = finish_info(hs[k], maxit, &infos[i], cols[i]);
       if (st != SMR_OK && first_bad == SMR_OK) first_bad = st;
     }
     HIP_TRY(hipStreamSynchronize(s));

@@ -47,12 +47,12 @@ class SmrDesc(ctypes.Structure):
 class SmrInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("relres_true", ctypes.c_double), ("relres_prec", ctypes.c_double),
-                ("res_evals", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("res_evals", ctypes.c_int32), ("tile_cols", ctypes.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "status": STATUS_NAMES.get(self.status, self.status),
                 "relres_true": self.relres_true, "relres_prec": self.relres_prec,
-                "res_evals": self.res_evals}
+                "res_evals": self.res_evals, "tile_cols": self.tile_cols}
 
 
 class SmrError(RuntimeError):
