@@ -68,6 +68,13 @@ def traffic_entry(path=TRAFFIC_FILE, widths=None):
         return None
     if t.get("kernel_sha256_16") != kernel_hash():
         return None
+    if isinstance(widths, dict) and "per_class_bytes_per_launch" in t:
+        # batches: every time-size class launches once per iteration, so the bytes per launch
+        # is the mean over the classes, each at the width this run chose for it
+        pc = t["per_class_bytes_per_launch"]
+        if any(str(c) not in pc.get(hp, {}) for hp, c in widths.items()):
+            return None
+        return sum(pc[hp][str(c)] for hp, c in widths.items()) / len(widths)
     if widths is not None and t.get("tile_cols") != widths:
         return None
     return t.get("bytes_per_launch")
