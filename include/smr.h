@@ -144,9 +144,11 @@ typedef struct {
   int32_t precond;         /* smr_precond                                                 */
   int32_t pprec;           /* smr_pprec                                                   */
   int32_t cheb_k;          /* Chebyshev steps per mode (SMR_P_THETA_CHEB), 1..16          */
-  int32_t flags;           /* bit 0 (SMR_FLAG_GENERAL_PATH): iterate in the physical basis
-                            * even when a is constant; bits 1, 2 (SMR_FLAG_TILE16/32):
-                            * fix the column-tile width; other bits must be 0           */
+  int32_t flags;           /* SMR_FLAG_* bits: GENERAL_PATH (iterate in the physical basis
+                            * even when a is constant), TILE16/32/64 (fix the column-tile
+                            * width), PINV_* (the physical-basis P^{-1} variant),
+                            * MATVEC_LEVEL/TILES (the N = 127 per-level matvec form);
+                            * other bits must be 0 (SMR_EINVAL)                          */
   double T;                /* final time (> 0)                                            */
   double theta;            /* theta-method parameter (SMR_THETA)                          */
   /* Coefficient a (host pointers, copied during smr_setup).  Give at most one form:
