@@ -586,8 +586,8 @@ hipError_t run_ks_r(hipStream_t st, int L, const KsP *K, const KsP *table, int n
 // at most 18 lines (18.6 KB of LDS) instead of a whole level (139 KB), so several blocks
 // share a CU and one block's loads overlap another's transforms.  The true-residual chain
 // runs the same three passes on x in the same launches, through intermediates of its own,
-// when launch j-1's scalars ask for it.  Same arithmetic as
-// the level kernel; only the partial sums are grouped per tile (kKsTiles per level).
+// when launch j-1's scalars ask for it.  Same arithmetic as the level kernel; only the
+// partial sums are grouped per tile (kKsTiles per level).
 constexpr int kKsN = 127, kKsLP = kKsN + 2;   // level size, LDS pitch of a line
 constexpr int kKsTT = 256;                     // threads per block: 4 waves
 constexpr int kKsTL = 16;                      // rows (passes A, C) or columns (pass B) per tile

@@ -201,3 +201,21 @@ def test_tile64_batched_classes():
         else:
             assert info["iters"] <= int(1.1 * ref.iters) + 1
             assert np.linalg.norm(b - o.apply_T(_n(x))) / np.linalg.norm(b) <= 1e-8
+
+
+def test_info_reports_tile_width():
+    """smr_info.tile_cols: the width a solve's fused launches ran with (the plan's for single
+    solves, the class's for batched ones), 0 on the physical-basis path."""
+    from paper_2201_10062_amd import Batch, Plan
+    _dev()
+    rng = np.random.default_rng(35)
+    g = Plan(2, 31, 40, scheme="bdf2", tile_cols=64)
+    _, info = g.solve(_t(rng.standard_normal(40 * 31 * 31)), rtol=1e-8)
+    assert info["tile_cols"] == 64
+    gp = Plan(2, 31, 40, scheme="bdf2", general_path=True)
+    _, info = gp.solve(_t(rng.standard_normal(40 * 31 * 31)), rtol=1e-8)
+    assert info["tile_cols"] == 0
+    plans = [Plan(2, 31, 40, scheme="bdf2", tile_cols=16), Plan(2, 15, 40, scheme="bdf2", tile_cols=32),
+             Plan(2, 31, 24, scheme="bdf2", general_path=True)]
+    _, infos = Batch(plans).solve([_t(rng.standard_normal(p.n * p.m)) for p in plans], rtol=1e-8)
+    assert [i["tile_cols"] for i in infos] == [16, 32, 0]
