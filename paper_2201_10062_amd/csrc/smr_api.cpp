@@ -1587,7 +1587,8 @@ smr_status solve_batched_locked(BatchState &bst, int32_t count, const smr_plan *
     if (!g_prof.on) {
       // the descriptor tables' places in the workspace depend on the instance count as well
       std::vector<long> key{(long)(uintptr_t)d_ws, (long)count};
-      for (const KClass &cl : kclasses) key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec});
+      for (const KClass &cl : kclasses)
+        key.insert(key.end(), {0, cl.first, cl.count, cl.blocks, cl.L, cl.pprec, cl.split ? 1L : 0L});
       for (const Class &cl : classes)
         key.insert(key.end(), {1, cl.first, cl.count, cl.blocks, cl.hp, cl.cols, cl.pprec, cl.taps});
       g6 = batch_graph(bst, key, [&](hipStream_t cs) {

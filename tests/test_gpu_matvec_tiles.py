@@ -173,3 +173,26 @@ def test_matvec_forms_full_size_bdf2(form):
     r = np.linalg.norm(b - o.apply_T(x)) / np.linalg.norm(b)
     assert r <= 1e-8 and abs(r - info["relres_true"]) <= 1e-3 * r
     assert rel(x, o.solve_direct(b)) < 1e-6
+
+
+def test_batch_graph_follows_matvec_form():
+    """Two batches on one workspace with the same class layout whose N = 127 instance takes
+    the per-level form in one and the tiled form in the other: the second must not replay the
+    first one's captured steady iterations (the fused launch reads as many matvec partials as
+    its own form writes).  Both equal the oracle past the captured iterations."""
+    from paper_2201_10062_amd import Batch, Plan
+    _dev()
+    N, n = 127, 8
+    ax, ay = _faces("sin", N)
+    o = System(2, N, n, scheme="bdf2", ax=ax, ay=ay)
+    b = _rhs(o, n, N * N, "bdf2", 45)
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    assert ref.iters > 12
+    raw = None
+    for form in ("level", "tiles", "level"):
+        g = Plan(2, N, n, scheme="bdf2", ax=ax, ay=ay, matvec=form)
+        bt = Batch([g], workspace=raw)
+        raw = bt.raw_workspace
+        xs, infos = bt.solve([_t(b)], rtol=1e-8, maxit=400)
+        assert infos[0]["status"] == "ok" and infos[0]["iters"] == ref.iters, (form, infos[0], ref.iters)
+        assert rel(_n(xs[0]), ref.x) < 1e-10, form
