@@ -10,7 +10,7 @@
 // <S x, diag(1/sigma) S x> (= gamma^2 by Parseval) per block.
 //
 // A block owns C consecutive columns (spatial points); its butterflied columns sit in
-// LDS and the four waves multiply them by one folded sine block per pass (the fragments
+// LDS and its waves multiply them by the folded sine blocks (the fragments
 // stream from L2 in MFMA-fragment order, two k-steps per load); the results go back to LDS,
 // where the 1/sigma scaling and the final butterfly read them.
 // PR 1 (mixed precision): the butterflied columns and the sine blocks are float32 and the
@@ -57,12 +57,79 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
-// hp <= 128: both parities per k-step (each wave owns output tiles of both halves and keeps
-// their accumulators; the final butterfly runs in registers).
-__device__ __forceinline__ size_t frag_at(int r, int ks, int kk, int lane) {
-  return (((size_t)r * (ks / 2) + kk / 2) * 64 + lane) * 2 + (kk & 1);
+// Both parities' GEMMs of one pass for the wave's tiles (tile = wave + 4 t, wave-uniform):
+// ao[t] += Ao[r] * U[:, ct], ae[t] += Ae[r] * D[:, ct].  The tables hold the fragments of
+// k-steps 2q and 2q+1 side by side per lane (one load fetches both); loads run two pairs
+// ahead of the MFMAs (near the end they reload the last pair, unused, so that the loads need
+// no branch).
+template <int HP, int C, int PR>
+__device__ __forceinline__ void pair_gemm(const typename Prec<PR>::T *__restrict__ Ao,
+                                          const typename Prec<PR>::T *__restrict__ Ae,
+                                          const typename Prec<PR>::T *U, const typename Prec<PR>::T *D,
+                                          int wave, int lane,
+                                          typename Prec<PR>::Acc (&ao)[((HP / 16) * (C / 16) + 3) / 4],
+                                          typename Prec<PR>::Acc (&ae)[((HP / 16) * (C / 16) + 3) / 4]) {
+  typedef typename Prec<PR>::T T;
+  typedef typename std::conditional<PR == 0, double2, float2>::type T2;
+  constexpr int LD = C + 1;
+  constexpr int RT = HP / 16, CT = C / 16, NT = RT * CT, TPW = (NT + 3) / 4;
+  constexpr int KS = HP / 4, KP = KS / 2;
+  constexpr bool kAll = NT % 4 == 0;           // every wave owns TPW tiles
+  const int bk = lane >> 4, bj = lane & 15;
+  const T2 *__restrict__ Ao2 = reinterpret_cast<const T2 *>(Ao);
+  const T2 *__restrict__ Ae2 = reinterpret_cast<const T2 *>(Ae);
+  // a wave past the last tile reads row 0's fragments (valid, unused)
+  size_t base[TPW];
+  int boff[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave + 4 * t;
+    base[t] = (size_t)((kAll || tile < NT) ? tile / CT : 0) * KP * 64 + lane;
+    boff[t] = bk * LD + 16 * (tile % CT) + bj;
+  }
+  T2 qo[TPW], qe[TPW], po[TPW], pe[TPW];     // pairs kp and kp + 1
+  constexpr int K1 = KP > 1 ? 1 : 0;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    qo[t] = Ao2[base[t]];
+    qe[t] = Ae2[base[t]];
+    po[t] = Ao2[base[t] + (size_t)K1 * 64];
+    pe[t] = Ae2[base[t] + (size_t)K1 * 64];
+  }
+#pragma unroll 1   // a rolled loop keeps the loads two pairs ahead (unrolled, they sink to their uses)
+  for (int kp = 0; kp < KP; ++kp) {
+    const int kn = kp + 2 < KP ? kp + 2 : KP - 1;
+    T2 no[TPW], ne[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      no[t] = Ao2[base[t] + (size_t)kn * 64];
+      ne[t] = Ae2[base[t] + (size_t)kn * 64];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = 2 * kp + h;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        if (kAll || wave + 4 * t < NT) {
+          const T bu = U[4 * kk * LD + boff[t]];
+          const T bd = D[4 * kk * LD + boff[t]];
+          ao[t] = Prec<PR>::mfma(h ? qo[t].y : qo[t].x, bu, ao[t]);
+          ae[t] = Prec<PR>::mfma(h ? qe[t].y : qe[t].x, bd, ae[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      qo[t] = po[t];
+      qe[t] = pe[t];
+      po[t] = no[t];
+      pe[t] = ne[t];
+    }
+  }
 }
 
+// hp <= 32: both parities per k-step (each wave owns output tiles of both halves and keeps
+// their accumulators; the final butterfly runs in registers).
 template <int HP, int C, int MODE, int PR, typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restrict__ in, TO *__restrict__ out,
                                               double *__restrict__ part, const Scal *__restrict__ gate) {
@@ -72,7 +139,6 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
   constexpr int LD = C + 1;                   // LDS row stride (doubles)
   constexpr int RT = HP / 16, CT = C / 16, NT = RT * CT;
   constexpr int TPW = (NT + 3) / 4;           // tiles per wave (per parity)
-  constexpr int KS = HP / 4;                  // k-steps
   extern __shared__ double lds_raw[];
   T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
   T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
@@ -82,7 +148,8 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
   const T *__restrict__ SeT = reinterpret_cast<const T *>(tp.SeT);
   __shared__ double red[4];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index in a scalar register: the per-wave tile tests below are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = blockIdx.x * C;
   const int n = tp.n, m = tp.m, h1 = tp.h1, h2 = tp.h2;
 
@@ -117,21 +184,7 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
   const int bk = lane >> 4, bj = lane & 15;
 
   // 2. first GEMM: [S_o u | S_e d] for this wave's tiles
-  for (int kk = 0; kk < KS; ++kk) {
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + 4 * t;
-      if (tile < NT) {
-        const int r = tile / CT, ct = tile - r * CT;
-        const T bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
-        const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const T au = So[frag_at(r, KS, kk, lane)];
-        const T ad = Se[frag_at(r, KS, kk, lane)];
-        ao[t] = Prec<PR>::mfma(au, bu, ao[t]);
-        ae[t] = Prec<PR>::mfma(ad, bd, ae[t]);
-      }
-    }
-  }
+  pair_gemm<HP, C, PR>(So, Se, U, D, wave, lane, ao, ae);
 
   if (MODE == 0) {
     // y_{2p} (odd modes) and y_{2p+1} (even modes), 0-based rows
@@ -185,21 +238,7 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
   // 4. second GEMM with the transposed blocks
 #pragma unroll
   for (int t = 0; t < TPW; ++t) { ao[t] = zacc; ae[t] = zacc; }
-  for (int kk = 0; kk < KS; ++kk) {
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + 4 * t;
-      if (tile < NT) {
-        const int r = tile / CT, ct = tile - r * CT;
-        const T bu = U[(4 * kk + bk) * LD + 16 * ct + bj];
-        const T bd = D[(4 * kk + bk) * LD + 16 * ct + bj];
-        const T au = SoT[frag_at(r, KS, kk, lane)];
-        const T ad = SeT[frag_at(r, KS, kk, lane)];
-        ao[t] = Prec<PR>::mfma(au, bu, ao[t]);
-        ae[t] = Prec<PR>::mfma(ad, bd, ae[t]);
-      }
-    }
-  }
+  pair_gemm<HP, C, PR>(SoT, SeT, U, D, wave, lane, ao, ae);
   __syncthreads();   // all LDS reads done before any in-place global write of this block's columns
 
   // 5. output butterfly z_p = u'_p + d'_p, z_{n-1-p} = u'_p - d'_p (odd n: middle row once)
@@ -228,9 +267,9 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
   }
 }
 
-// hp >= 256: one folded block per pass (fewer live accumulators), results through LDS.
-// One block: C columns, all n levels; NW waves, all on the matrix cores (eight, so that a
-// CU holding a single block of the largest tiles still runs two waves per SIMD).
+// hp >= 64: one folded block per pass (fewer live accumulators), results through LDS.
+// One block: C columns, all n levels; NW waves, all on the matrix cores (eight for hp >= 128,
+// so that a CU holding a single block of the largest tiles still runs two waves per SIMD).
 template <int HP, int C, int MODE, int PR, int NW, typename TI, typename TO>
 __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict__ in,
                                                   TO *__restrict__ out, double *__restrict__ part,
@@ -353,8 +392,10 @@ hipError_t run_time(Ctx c, const TimeP &tp, const TI *in, TO *out, int mode, dou
   const int blocks = (tp.m + C - 1) / C;
   if (nb) *nb = blocks;
   const size_t shmem = 2 * (size_t)HP * (C + 1) * sizeof(typename Prec<PR>::T);
-  if constexpr (HP >= 256) {
-    constexpr int NW = 8;
+  // hp >= 64: one folded block per pass on eight (hp >= 128) or four matrix-core waves; the
+  // smaller paddings keep both parities per k-step (measured faster there)
+  if constexpr (HP >= 64) {
+    constexpr int NW = HP >= 128 ? 8 : 4;
     if (shmem > 65536) {
       (void)lds_limit((const void *)k_time<HP, C, 0, PR, NW, TI, TO>, shmem);
       (void)lds_limit((const void *)k_time<HP, C, 1, PR, NW, TI, TO>, shmem);

@@ -137,6 +137,44 @@ def test_physical_path_hp256(precond):
     _check(g, o, _rhs(o, "theta", n, g.m, 60))
 
 
+@pytest.mark.parametrize("n", [100, 129, 200])
+@pytest.mark.parametrize("precond", ["PH", "PTHETA_CHEB"])
+def test_physical_path_hp64_hp128(precond, n):
+    """The physical-basis time transform at hp = 64 (n = 100) and hp = 128 (n = 129, odd: the
+    middle level has no odd-symmetric partner; n = 200), one folded block per pass on four or
+    eight matrix-core waves: P^{-1} to 1e-12, and the MINRES iterate to 1e-10 at the oracle's
+    stopping iteration, for P_H(Kbar) and P_theta with 3 Chebyshev steps."""
+    from paper_2201_10062_amd import Plan
+    _dev()
+    N = 31
+    ax, ay = _smooth_faces(N)
+    g = Plan(2, N, n, theta=1.0, precond=precond, cheb_k=3, ax=ax, ay=ay, general_path=True)
+    assert g.tile_cols == 0
+    o = System(2, N, n, theta=1.0, ax=ax, ay=ay, precond=precond, cheb_k=3)
+    v = np.random.default_rng(61).standard_normal(n * g.m)
+    assert rel(_n(g.apply_P_inv(_t(v))), o.apply_Pinv(v)) < 1e-12
+    _check(g, o, _rhs(o, "theta", n, g.m, 62))
+
+
+def test_physical_path_hp128_fp32():
+    """Float32 time transforms at hp = 128 on the physical path (parity unpinned by rounding):
+    the float64 true residual at the tolerance, iterations within 10% (+1) of the oracle's."""
+    from paper_2201_10062_amd import Plan
+    _dev()
+    N, n = 31, 200
+    ax, ay = _smooth_faces(N)
+    g = Plan(2, N, n, theta=1.0, ax=ax, ay=ay, general_path=True, pprec="fp32")
+    o = System(2, N, n, theta=1.0, ax=ax, ay=ay)
+    b = _rhs(o, "theta", n, g.m, 63)
+    ref = o.solve(b, rtol=1e-8, maxit=400)
+    x, info = g.solve(_t(b), rtol=1e-8, maxit=400)
+    x = _n(x)
+    r = np.linalg.norm(b - o.apply_T(x)) / np.linalg.norm(b)
+    assert info["status"] == "ok" and r <= 1e-8
+    assert info["iters"] <= int(1.1 * ref.iters) + 1
+    assert rel(x, ref.x) < 1e-6
+
+
 @pytest.mark.parametrize("precond", ["PH", "PTHETA_CHEB"])
 def test_physical_path_N255_two_iterations(precond):
     """N + 1 = 256 (the persistent 512-point spatial transform) with the variable coefficient
