@@ -33,8 +33,8 @@ struct TimeP {
 
 // 1/sigma from a float reciprocal square root refined by two Newton steps in float64 (relative
 // error ~1e-16; far cheaper than a float64 square root and division)
-__device__ __forceinline__ double inv_sigma(const TimeP &tp, int tmode, double t) {
-  const double *c = tp.tcoef + 4 * tmode;
+__device__ __forceinline__ double inv_sigma(const double *tc, int tmode, double t) {
+  const double *c = tc + 4 * tmode;
   const double re = c[0] + t * c[1];
   const double im = c[2] + t * c[3];
   const double q = re * re + im * im;
@@ -221,12 +221,12 @@ __global__ __launch_bounds__(256) void k_time_pair(TimeP tp, const TI *__restric
       double so = 0.0, se = 0.0;
       if (col < m && p < h1) {
         const double a = (double)ao[t][i];
-        so = a * inv_sigma(tp, 2 * p, tm);
+        so = a * inv_sigma(tp.tcoef, 2 * p, tm);
         g2 += a * so;
       }
       if (col < m && p < h2) {
         const double a = (double)ae[t][i];
-        se = a * inv_sigma(tp, 2 * p + 1, tm);
+        se = a * inv_sigma(tp.tcoef, 2 * p + 1, tm);
         g2 += a * se;
       }
       U[p * LD + cl] = (T)so;
@@ -284,12 +284,19 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
   T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
   T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
   __shared__ double red[NW];
+  // the 4 coefficients of every time mode, staged in LDS for the 1/sigma pass where they fit
+  // beside the two halves (all but float64 hp = 512); the pass reads them per element
+  constexpr bool kTcLds = MODE == 1 && 2 * HP * (C + 1) * sizeof(T) + 8 * HP * sizeof(double) + 1024 <= 160 * 1024;
+  __shared__ double tcl[kTcLds ? 8 * HP : 1];
   const T *So = reinterpret_cast<const T *>(tp.So), *Se = reinterpret_cast<const T *>(tp.Se);
   const T *SoT = reinterpret_cast<const T *>(tp.SoT), *SeT = reinterpret_cast<const T *>(tp.SeT);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col0 = blockIdx.x * C;
   const int n = tp.n, m = tp.m, h1 = tp.h1, h2 = tp.h2;
+
+  if (kTcLds)
+    for (int e = tid; e < 4 * n; e += NT) tcl[e] = tp.tcoef[e];   // n <= 2 HP modes
 
   // 1. butterfly load (zero padding rows and columns beyond m), kBL elements per thread with
   //    all their loads issued before the LDS stores
@@ -338,6 +345,7 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
   }
 
   // 3. scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
+  const double *tc = kTcLds ? tcl : tp.tcoef;
   double g2 = 0.0;
   for (int e = tid; e < HP * C; e += NT) {
     const int p = e / C, c = e - p * C, col = col0 + c;
@@ -346,12 +354,12 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
     double so = 0.0, se = 0.0;
     if (okc && p < h1) {
       const double a = (double)U[p * LD + c];
-      so = a * inv_sigma(tp, 2 * p, tm);
+      so = a * inv_sigma(tc, 2 * p, tm);
       g2 += a * so;
     }
     if (okc && p < h2) {
       const double a = (double)D[p * LD + c];
-      se = a * inv_sigma(tp, 2 * p + 1, tm);
+      se = a * inv_sigma(tc, 2 * p + 1, tm);
       g2 += a * se;
     }
     U[p * LD + c] = (T)so;
