@@ -323,13 +323,46 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
   }
   __syncthreads();
 
-  // 2. [S_o u | S_e d], each result back to LDS once every wave is done reading its block
+  // 2. [S_o u | S_e d], each result back to LDS once every wave is done reading its block.
+  //    MODE 1 scales them by 1/sigma in registers on the way (time mode 2p+1 is row p of U,
+  //    mode 2p+2 row p of D; padding rows and columns past m become zero) and accumulates the
+  //    Parseval partial.
+  const double *tc = kTcLds ? tcl : tp.tcoef;
+  double g2 = 0.0;
+  auto scale_acc = [&](Acc (&ac)[RPW][CT], int parity, int hlim) {
+    constexpr int RT = HP / 16;
+    const int wv = __builtin_amdgcn_readfirstlane(wave), bk = lane >> 4, bj = lane & 15;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wv + NW * i;
+      if (r >= RT) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int col = col0 + 16 * ct + bj;
+        const bool okc = col < m;
+        const double tm = tp.tmu[okc ? col : m - 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int p = 16 * r + Prec<PR>::row(q, bk);
+          const double a = (double)ac[i][ct][q];
+          double sv = 0.0;
+          if (okc && p < hlim) {
+            sv = a * inv_sigma(tc, 2 * p + parity, tm);
+            g2 += a * sv;
+          }
+          ac[i][ct][q] = (T)sv;
+        }
+      }
+    }
+  };
   Acc acc[RPW][CT];
   gemm_tiles<HP, C, PR, NW>(So, U, wave, lane, acc);
   __syncthreads();
+  if (MODE == 1) scale_acc(acc, 0, h1);
   store_acc<HP, C, PR, NW>(acc, U, wave, lane);
   gemm_tiles<HP, C, PR, NW>(Se, D, wave, lane, acc);
   __syncthreads();
+  if (MODE == 1) scale_acc(acc, 1, h2);
   store_acc<HP, C, PR, NW>(acc, D, wave, lane);
   __syncthreads();
 
@@ -344,30 +377,7 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
     return;
   }
 
-  // 3. scale by 1/sigma (time mode 2p+1 -> index 2p, 2p+2 -> 2p+1), Parseval partial
-  const double *tc = kTcLds ? tcl : tp.tcoef;
-  double g2 = 0.0;
-  for (int e = tid; e < HP * C; e += NT) {
-    const int p = e / C, c = e - p * C, col = col0 + c;
-    const bool okc = col < m;
-    const double tm = tp.tmu[okc ? col : m - 1];
-    double so = 0.0, se = 0.0;
-    if (okc && p < h1) {
-      const double a = (double)U[p * LD + c];
-      so = a * inv_sigma(tc, 2 * p, tm);
-      g2 += a * so;
-    }
-    if (okc && p < h2) {
-      const double a = (double)D[p * LD + c];
-      se = a * inv_sigma(tc, 2 * p + 1, tm);
-      g2 += a * se;
-    }
-    U[p * LD + c] = (T)so;
-    D[p * LD + c] = (T)se;
-  }
-  __syncthreads();
-
-  // 4. the transposed blocks
+  // 3. the transposed blocks
   gemm_tiles<HP, C, PR, NW>(SoT, U, wave, lane, acc);
   __syncthreads();
   store_acc<HP, C, PR, NW>(acc, U, wave, lane);
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
   store_acc<HP, C, PR, NW>(acc, D, wave, lane);
   __syncthreads();
 
-  // 5. output butterfly z_p = u'_p + d'_p, z_{n-1-p} = u'_p - d'_p (odd n: middle row once)
+  // 4. output butterfly z_p = u'_p + d'_p, z_{n-1-p} = u'_p - d'_p (odd n: middle row once)
   for (int e = tid; e < HP * C; e += NT) {
     const int p = e / C, c = e - p * C, col = col0 + c;
     if (col >= m) continue;
