@@ -1003,7 +1003,10 @@ __device__ __forceinline__ void pair_dft512(double2 (&v)[8], int lane, const dou
 // (loads of one tile and stores of another touch different lines, so in == out is allowed);
 // the regrouping buffers alias the tile once the line pairs are in registers.
 // NWV waves, one line pair each: tiles of 2 NWV lines (8 lines, or 16 in column passes when
-// tuned, for longer row pieces).
+// tuned, for longer row pieces).  scale_mode 1 divides the result by the Chebyshev inner
+// diagonal on the way out; scale_mode 2 (column passes) divides it in the tile and takes the
+// tile through the same transform again: the two consecutive column passes of the inner
+// preconditioner in one read and one write of the vector.
 template <int DIR, typename TI, typename TO, int NWV>
 __global__ __launch_bounds__(64 * NWV) void k_dst_tile512(TileP d, const TI *__restrict__ in,
                                                           TO *__restrict__ out, const Scal *__restrict__ gate,
@@ -1065,29 +1068,45 @@ __global__ __launch_bounds__(64 * NWV) void k_dst_tile512(TileP d, const TI *__r
     // the wave's line pair, oddly extended to M points (lines past nl read as zero)
     const int la = min(2 * wave, nl - 1), lb = min(2 * wave + 1, nl - 1);
     const bool oka = 2 * wave < nl, okb = 2 * wave + 1 < nl;
-    double2 v[8];
+    // the tile's lines through the DST, results back in the tile
+    auto transform = [&]() {
+      double2 v[8];
 #pragma unroll
-    for (int j1 = 0; j1 < 8; ++j1) {
-      const int jn = 64 * j1 + lane;
-      const bool lo = jn >= 1 && jn <= N, hi = jn > L;
-      const int sp = lo ? jn - 1 : hi ? M - jn - 1 : 0;
-      const double sg = lo ? 1.0 : hi ? -1.0 : 0.0;
-      v[j1] = make_double2(oka ? sg * X[at(la, sp)] : 0.0, okb ? sg * X[at(lb, sp)] : 0.0);
-    }
-    __syncthreads();
-    pair_dft512(v, lane, wa, wb, T);
-    __syncthreads();
-    // (S a)_k = -Im Z_{k+1} / sqrt(2L), (S b)_k = Re Z_{k+1} / sqrt(2L); k + 1 < 256 needs d < 4
-    const int k1 = lane >> 3, c = lane & 7;
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-      const int K = k1 + 8 * c + 64 * dd;
-      if (K >= 1) {
-        if (oka) X[at(la, K - 1)] = -v[dd].y * d.scale;
-        if (okb) X[at(lb, K - 1)] = v[dd].x * d.scale;
+      for (int j1 = 0; j1 < 8; ++j1) {
+        const int jn = 64 * j1 + lane;
+        const bool lo = jn >= 1 && jn <= N, hi = jn > L;
+        const int sp = lo ? jn - 1 : hi ? M - jn - 1 : 0;
+        const double sg = lo ? 1.0 : hi ? -1.0 : 0.0;
+        v[j1] = make_double2(oka ? sg * X[at(la, sp)] : 0.0, okb ? sg * X[at(lb, sp)] : 0.0);
       }
+      __syncthreads();
+      pair_dft512(v, lane, wa, wb, T);
+      __syncthreads();
+      // (S a)_k = -Im Z_{k+1} / sqrt(2L), (S b)_k = Re Z_{k+1} / sqrt(2L); k + 1 < 256 needs d < 4
+      const int k1 = lane >> 3, c = lane & 7;
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const int K = k1 + 8 * c + 64 * dd;
+        if (K >= 1) {
+          if (oka) X[at(la, K - 1)] = -v[dd].y * d.scale;
+          if (okb) X[at(lb, K - 1)] = v[dd].x * d.scale;
+        }
+      }
+      __syncthreads();
+    };
+    transform();
+    if (DIR == 1 && d.scale_mode == 2) {
+      // the diagonal division between two column passes, in the tile, then the second pass
+      for (int e = tid; e < TL * N; e += kTT) {
+        const int j = e / TL, c2 = e - j * TL;
+        if (c2 < nl) {
+          const size_t q = (size_t)j * N + i0 + c2;
+          X[j * LP + c2] /= d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q];
+        }
+      }
+      __syncthreads();
+      transform();
     }
-    __syncthreads();
     TO *dst = out + (size_t)s * d.sout;
     auto fin = [&](double x, size_t q) {
       return d.scale_mode == 1 ? x / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : x;
@@ -1186,6 +1205,8 @@ hipError_t launch_dst_tile(Ctx c, int dir, const void *in, bool in32, void *out,
   d.ez = p->ez;
   d.tmu_lap = p->tmu_lap;
   d.scale_mode = scale_mode;
+  // scale_mode 2 (divide, then the same column pass again) exists for N + 1 = 256 only
+  if (scale_mode == 2 && (p->L != 256 || dir != 1)) return hipErrorInvalidValue;
   switch (p->L) {
     case 32: return run_dst_tile_v<1>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
     case 64: return run_dst_tile_v<2>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);

@@ -736,9 +736,16 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   else LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
   // inner preconditioner: the spatial transform along every axis (the last pass divides by
-  // the diagonal), then back
+  // the diagonal), then back; 2D with N + 1 = 256: the two middle column passes run as one
+  // (divide in the tile, transform again)
   auto binv = [&](const double *in, double *out) -> smr_status {
     const int last = p.dim - 1;
+    if (p.dim == 2 && p.L == 256 && dst_tile_supported(&p)) {
+      LAUNCH(PROF_DST, launch_dst_v(c, 0, in, w, out, w, p.n, 0, gate, 0, 0, c16));
+      LAUNCH(PROF_DST, launch_dst_v(c, 1, out, w, out, w, p.n, 2, gate, 0, 0, c16));
+      LAUNCH(PROF_DST, launch_dst_v(c, 0, out, w, out, w, p.n, 0, gate, 0, 0, c16));
+      return SMR_OK;
+    }
     LAUNCH(PROF_DST, launch_dst_v(c, 0, in, w, out, w, p.n, last == 0 ? 1 : 0, gate, 0, 0, c16));
     for (int ax = 1; ax <= last; ++ax)
       LAUNCH(PROF_DST, launch_dst_v(c, ax, out, w, out, w, p.n, ax == last ? 1 : 0, gate, 0, 0, c16));
