@@ -135,7 +135,8 @@ hipError_t launch_grad_faces(Ctx c, const double *u, const double *u0, const dou
 // Spatial sine transform (orthonormal DST-I) along x (dir 0), y (dir 1) or z (dir 2, 3D) of nslices
 // slices; in-place allowed when the strides agree.  Slice strides of in and out default
 // (0) to m.  scale_mode 1 divides the result by the Chebyshev inner diagonal
-// eta_s + zeta_s * abar * tau * mu_lap.
+// eta_s + zeta_s * abar * tau * mu_lap; scale_mode 2 (2D column pass with N + 1 = 256 only,
+// else hipErrorInvalidValue) divides by it and applies the column transform once more.
 hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices, int scale_mode,
                       const Scal *gate, long in_stride = 0, long out_stride = 0);
 // The same pass with float32 (in32 / out32) or float64 input and output vectors; the
