@@ -284,9 +284,13 @@ __global__ __launch_bounds__(64 * NW) void k_time(TimeP tp, const TI *__restrict
   T *U = reinterpret_cast<T *>(lds_raw);      // [HP][LD] even-symmetric half (u)
   T *D = U + HP * LD;                         // [HP][LD] odd-symmetric half (d)
   __shared__ double red[NW];
-  // the 4 coefficients of every time mode, staged in LDS for the 1/sigma pass where they fit
-  // beside the two halves (all but float64 hp = 512); the pass reads them per element
-  constexpr bool kTcLds = MODE == 1 && 2 * HP * (C + 1) * sizeof(T) + 8 * HP * sizeof(double) + 1024 <= 160 * 1024;
+  // the 4 coefficients of every time mode, staged in LDS for the 1/sigma scaling where they
+  // fit beside the two halves without lowering the blocks per CU (the float64 tiles up to
+  // hp = 256); the scaling reads them per element
+  constexpr int kHalves = 2 * HP * (C + 1) * (int)sizeof(T), kTcBytes = 8 * HP * (int)sizeof(double);
+  constexpr int kLdsCU = 160 * 1024;
+  constexpr bool kTcLds = MODE == 1 && kHalves + kTcBytes + 1024 <= kLdsCU &&
+                          kLdsCU / (kHalves + kTcBytes + 1024) == kLdsCU / (kHalves + 1024);
   __shared__ double tcl[kTcLds ? 8 * HP : 1];
   const T *So = reinterpret_cast<const T *>(tp.So), *Se = reinterpret_cast<const T *>(tp.Se);
   const T *SoT = reinterpret_cast<const T *>(tp.SoT), *SeT = reinterpret_cast<const T *>(tp.SeT);
