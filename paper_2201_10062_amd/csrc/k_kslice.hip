@@ -899,6 +899,11 @@ struct TileP {
   double scale, abar;
   const double *tw, *ez, *tmu_lap;
   int scale_mode;
+  // scale_mode 3 (row passes, N + 1 = 256): the Chebyshev update takes the result t instead
+  // of a store: dv = a_t t (cfirst) or a_d dv + a_t t, then x = dv (cfirst) or x + dv
+  void *cx, *cd;
+  double ca_d, ca_t;
+  int cfirst;
 };
 
 // TI, TO: element types of the vectors in memory (float32 intermediates of a mixed-precision
@@ -1111,7 +1116,18 @@ __global__ __launch_bounds__(64 * NWV) void k_dst_tile512(TileP d, const TI *__r
     auto fin = [&](double x, size_t q) {
       return d.scale_mode == 1 ? x / (d.ez[s] + d.ez[d.n + s] * d.abar * d.tmu_lap[q]) : x;
     };
-    if (DIR == 0) {
+    if (DIR == 0 && d.scale_mode == 3) {
+      TO *xv = reinterpret_cast<TO *>(d.cx) + (size_t)s * d.sout;
+      TO *dv = reinterpret_cast<TO *>(d.cd) + (size_t)s * d.sout;
+      for (int e = tid; e < nl * N; e += kTT) {
+        const int c2 = e / N, j = e - c2 * N;
+        const size_t q = (size_t)i0 * N + e;
+        const double tv = (double)(TO)X[c2 * LP + j];     // the result as a stored vector holds it
+        const double dn = d.cfirst ? d.ca_t * tv : d.ca_d * (double)dv[q] + d.ca_t * tv;
+        dv[q] = (TO)dn;
+        xv[q] = d.cfirst ? (TO)dn : (TO)((double)xv[q] + dn);
+      }
+    } else if (DIR == 0) {
       for (int e = tid; e < nl * N; e += kTT) {
         const int c2 = e / N, j = e - c2 * N;
         const size_t q = (size_t)i0 * N + e;
@@ -1205,8 +1221,9 @@ hipError_t launch_dst_tile(Ctx c, int dir, const void *in, bool in32, void *out,
   d.ez = p->ez;
   d.tmu_lap = p->tmu_lap;
   d.scale_mode = scale_mode;
-  // scale_mode 2 (divide, then the same column pass again) exists for N + 1 = 256 only
-  if (scale_mode == 2 && (p->L != 256 || dir != 1)) return hipErrorInvalidValue;
+  // scale_mode 2 (divide, then the same column pass again) exists for N + 1 = 256 only, and
+  // scale_mode 3 (the Chebyshev update) only through launch_dst_cheb_axpy
+  if ((scale_mode == 2 && (p->L != 256 || dir != 1)) || scale_mode == 3) return hipErrorInvalidValue;
   switch (p->L) {
     case 32: return run_dst_tile_v<1>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
     case 64: return run_dst_tile_v<2>(c.st, dir, d, nslices, in, in32, out, out32, gate, col16);
@@ -1215,6 +1232,29 @@ hipError_t launch_dst_tile(Ctx c, int dir, const void *in, bool in32, void *out,
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_dst_cheb_axpy(Ctx c, const void *in, void *x, void *dvec, bool f32, double a_d, double a_t,
+                                int first, const Scal *gate) {
+  const Plan *p = c.p;
+  if (!dst_tile_supported(p) || p->L != 256) return hipErrorInvalidValue;
+  TileP d{};
+  d.N = p->N;
+  d.n = p->n;
+  d.tiles = (p->N + kTL - 1) / kTL;
+  d.sin = d.sout = p->m;
+  d.scale = 1.0 / sqrt(2.0 * p->L);
+  d.abar = p->abar;
+  d.tw = p->tw;
+  d.ez = p->ez;
+  d.tmu_lap = p->tmu_lap;
+  d.scale_mode = 3;
+  d.cx = x;
+  d.cd = dvec;
+  d.ca_d = a_d;
+  d.ca_t = a_t;
+  d.cfirst = first;
+  return run_dst_tile_v<8>(c.st, 0, d, p->n, in, f32, x, f32, gate, false);
 }
 
 bool kslice_supported(const Plan *p) { return p->dim == 2 && (p->L == 32 || p->L == 64 || p->L == 128); }

@@ -735,35 +735,38 @@ smr_status apply_pinv(const Plan &p, hipStream_t s, const double *v, double *z, 
   if (w) LAUNCH(PROF_TIME, launch_time_v(c, v, false, tb.t1, true, 0, nullptr, nullptr, gate));
   else LAUNCH(PROF_TIME, launch_time(c, v, tb.t1, 0, nullptr, nullptr, gate, f32));
   const double cc = 0.5 * (p.cheb_hi + p.cheb_lo), dd = 0.5 * (p.cheb_hi - p.cheb_lo);
-  // inner preconditioner: the spatial transform along every axis (the last pass divides by
-  // the diagonal), then back; 2D with N + 1 = 256: the two middle column passes run as one
-  // (divide in the tile, transform again)
-  auto binv = [&](const double *in, double *out) -> smr_status {
+  // one Chebyshev step: the inner preconditioner applied to the residual (the spatial
+  // transform along every axis, the last pass dividing by the diagonal, then back) into tmp,
+  // then dvec = a_t tmp (first) or a_d dvec + a_t tmp and x = dvec (first) or x + dvec.  2D
+  // with N + 1 = 256: the two middle column passes run as one (divide in the tile, transform
+  // again) and the last row pass applies the update in place of storing tmp.
+  auto cheb_step = [&](double a_d, double a_t, int first) -> smr_status {
+    const double *in = tb.t1;
+    double *out = tb.t4;
     const int last = p.dim - 1;
     if (p.dim == 2 && p.L == 256 && dst_tile_supported(&p)) {
       LAUNCH(PROF_DST, launch_dst_v(c, 0, in, w, out, w, p.n, 0, gate, 0, 0, c16));
       LAUNCH(PROF_DST, launch_dst_v(c, 1, out, w, out, w, p.n, 2, gate, 0, 0, c16));
-      LAUNCH(PROF_DST, launch_dst_v(c, 0, out, w, out, w, p.n, 0, gate, 0, 0, c16));
+      LAUNCH(PROF_DST, launch_dst_cheb_axpy(c, out, tb.t2, tb.t3, w, a_d, a_t, first, gate));
       return SMR_OK;
     }
     LAUNCH(PROF_DST, launch_dst_v(c, 0, in, w, out, w, p.n, last == 0 ? 1 : 0, gate, 0, 0, c16));
     for (int ax = 1; ax <= last; ++ax)
       LAUNCH(PROF_DST, launch_dst_v(c, ax, out, w, out, w, p.n, ax == last ? 1 : 0, gate, 0, 0, c16));
     for (int ax = last; ax >= 0; --ax) LAUNCH(PROF_DST, launch_dst_v(c, ax, out, w, out, w, p.n, 0, gate, 0, 0, c16));
+    LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, a_d, a_t, first, gate, w));
     return SMR_OK;
   };
-  smr_status st = binv(tb.t1, tb.t4);
+  smr_status st = cheb_step(0.0, 1.0 / cc, 1);
   if (st != SMR_OK) return st;
-  LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, 0.0, 1.0 / cc, 1, gate, w));
   if (dd > 0.0) {
     const double s1 = cc / dd;
     double rho = 1.0 / s1;
     for (int i = 1; i < p.cheb_k; ++i) {
       LAUNCH(PROF_STENCIL, launch_cheb_resid(c, tb.t1, tb.t3, gate, w));
-      st = binv(tb.t1, tb.t4);
-      if (st != SMR_OK) return st;
       const double rn = 1.0 / (2.0 * s1 - rho);
-      LAUNCH(PROF_VEC, launch_cheb_axpy(c, tb.t2, tb.t3, tb.t4, rn * rho, 2.0 * rn / dd, 0, gate, w));
+      st = cheb_step(rn * rho, 2.0 * rn / dd, 0);
+      if (st != SMR_OK) return st;
       rho = rn;
     }
   }

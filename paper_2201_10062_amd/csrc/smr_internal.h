@@ -145,6 +145,11 @@ hipError_t launch_dst(Ctx c, int dir, const double *in, double *out, int nslices
 hipError_t launch_dst_v(Ctx c, int dir, const void *in, bool in32, void *out, bool out32, int nslices,
                         int scale_mode, const Scal *gate, long in_stride = 0, long out_stride = 0,
                         bool col16 = false);
+// The last spatial pass (rows, 2D, N + 1 = 256) of the Chebyshev inner preconditioner with the
+// Chebyshev update taking its result t in place of a store: dvec = a_t t (first) or
+// a_d dvec + a_t t, then x = dvec (first) or x + dvec (every vector float32 when f32).
+hipError_t launch_dst_cheb_axpy(Ctx c, const void *in, void *x, void *dvec, bool f32, double a_d, double a_t,
+                                int first, const Scal *gate);
 // Time transform: mode 0: out = (S_n (x) I) in; mode 1: out = (S_n (x) I) diag(1/sigma) (S_n (x) I) in
 // with partial sums of <D vhat, vhat> into part when part != null.  f32: the GEMMs on the
 // float32 matrix cores with the plan's float32 sine tables (pprec SMR_FP32 plans only).
